@@ -1,0 +1,190 @@
+/*
+ * fts.h - C ABI of the fast tensor-product Schwarz smoother library (libfts.so)
+ *
+ * Additive Schwarz smoothing for the symmetric interior penalty (SIPG) DG
+ * discretisation of the Laplacian on Cartesian Q_k meshes, with local solvers
+ * by fast diagonalisation, a matrix-free SIPG operator and a geometric
+ * multigrid V-cycle (Witte, Arndt, Kanschat, "Fast tensor product Schwarz
+ * smoothers for high-order discontinuous Galerkin methods").  All compute runs
+ * in HIP kernels for gfx950.
+ *
+ * Conventions
+ *   Vectors   FP64, device memory owned by the caller, contiguous, cell-major:
+ *             cells lexicographic with x fastest, and inside a cell the
+ *             (k+1)^d DoFs lexicographic with x fastest (Sec. 3, eq. multiindex).
+ *             Coefficients are Lagrange values in the Gauss-Lobatto points of
+ *             each cell (Sec. 2.1); the inner product is the Euclidean one of the
+ *             coefficient space (Sec. 2.1).
+ *   Streams   every device call is asynchronous on the given stream (a
+ *             hipStream_t passed as void*; NULL = default stream).  No call
+ *             synchronises the device unless documented.
+ *   Ownership handles (fts_level, fts_eigs, fts_hierarchy) own host metadata
+ *             and the device tables they allocate at creation (1-D matrices,
+ *             eigenvectors, level vectors, coarse factor); *_destroy frees them
+ *             and accepts NULL.  Hot calls (apply, residual, smooth, vcycle,
+ *             transfers) never allocate; the smoother's residual buffer is a
+ *             caller-provided workspace.
+ *   Errors    every function returns fts_status (0 = FTS_OK, < 0 error); the
+ *             last error message of the calling thread is available through
+ *             fts_last_error.  No exception crosses the ABI, nothing aborts.
+ *             Creation calls validate all arguments; hot calls check handles
+ *             and pointers for NULL and report kernel launch failures as
+ *             FTS_E_HIP.  Faults of earlier asynchronous work surface at the
+ *             next synchronising call as FTS_E_HIP.
+ */
+#ifndef FTS_H
+#define FTS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fts_status;
+#define FTS_OK 0
+#define FTS_E_INVAL (-1)       /* invalid argument */
+#define FTS_E_HIP (-2)         /* HIP runtime or kernel launch failure */
+#define FTS_E_NOT_SPD (-3)     /* a 1-D mass or operator matrix is not positive definite */
+#define FTS_E_UNSUPPORTED (-4) /* dimension / degree / precision not built */
+#define FTS_E_SIZE (-5)        /* workspace too small or size overflow */
+
+/* Subdomains of the Schwarz smoother (Sec. 2.3): single cells, or the 2^d
+ * cells around each interior vertex. */
+typedef enum { FTS_CELL = 0, FTS_VERTEX_PATCH = 1 } fts_patch_kind;
+
+/* Arithmetic of the local-solver contractions (gather, forward transform,
+ * eigenvalue scaling, backward transform).  Residual, 1-D setup, transfers
+ * and coarse solve are FP64 in every mode; the update of x is accumulated in
+ * FP64.  BF16/F16 run the contractions on MFMA with FP32 accumulation. */
+typedef enum { FTS_PREC_F64 = 0, FTS_PREC_F32 = 1, FTS_PREC_BF16 = 2, FTS_PREC_F16 = 3 } fts_prec;
+
+/* Rectilinear Cartesian mesh of [0, sum h_x] x [0, sum h_y] (x [0, sum h_z])
+ * (Sec. 2.1).  h[a] points to ncells[a] positive widths in HOST memory (read
+ * during the call only).  penalty_factor is gamma_hat of eq. (penalty):
+ * gamma_e = gamma_hat k (k+1) (1/h+ + 1/h-), h+ = h- on the boundary.
+ * Homogeneous Dirichlet conditions are imposed weakly on the whole boundary. */
+typedef struct fts_mesh_desc {
+    int32_t dim;            /* 2 or 3 */
+    int32_t degree;         /* k, 1..9 */
+    int32_t ncells[3];      /* cells per axis (ncells[2] ignored for dim 2) */
+    const double *h[3];     /* host arrays of widths */
+    double penalty_factor;  /* gamma_hat > 0 */
+} fts_mesh_desc;
+
+typedef struct fts_level fts_level;         /* one mesh with its operator tables */
+typedef struct fts_eigs fts_eigs;           /* 1-D eigenpairs of all subdomains of a level */
+typedef struct fts_hierarchy fts_hierarchy; /* multigrid hierarchy with coarse LU */
+
+/* Library version string (static storage). */
+const char *fts_version(void);
+
+/* Copies the calling thread's last error message into buf (NUL terminated,
+ * truncated to len).  Returns FTS_OK. */
+fts_status fts_last_error(char *buf, size_t len);
+
+/* ---- a level: mesh + operator tables ---------------------------------- */
+
+/* Builds the FP64 1-D operator tables of the SIPG form on this mesh (Sec. 3.2,
+ * eq. 1Dstiffnessmass, 1Dnitsche, 1Dsipg, 1DsipgVP) and uploads them to the
+ * current device.  Validates: dim in {2,3}, 1 <= degree <= 9, ncells >= 1,
+ * h > 0 and finite, penalty_factor > 0.  *out receives the handle. */
+fts_status fts_level_create(const fts_mesh_desc *mesh, fts_level **out);
+fts_status fts_level_destroy(fts_level *level);
+/* Number of DoFs, (k+1)^d prod ncells; -1 for NULL. */
+int64_t fts_level_ndofs(const fts_level *level);
+
+/* ---- a1-a3: 1-D generalised eigenproblems ------------------------------ */
+
+/* For every axis and every subdomain position along it, assembles the 1-D
+ * matrices A and M of the subdomain (a cell: eq. 1Dsipg; a vertex patch: the
+ * 2x2 block form eq. 1DsipgVP, whose outer faces see the outside neighbours'
+ * widths) and solves A S = M S diag(lambda) with S^T M S = I (eq.
+ * generalizedEVP) in FP64 on the host (Cholesky + cyclic Jacobi), then
+ * uploads S (n x n, row-major, column m = eigenvector m) and lambda (n) per
+ * (axis, position), n = k+1 for cells and 2(k+1) for patches.  Vertex
+ * patches need at least 2 cells per axis.  FTS_E_NOT_SPD if M or A is not
+ * positive definite (e.g. too small a penalty).  *out receives the handle,
+ * valid while the level lives. */
+fts_status fts_setup_1d_eigs(const fts_level *level, fts_patch_kind kind, fts_eigs **out);
+fts_status fts_eigs_destroy(fts_eigs *eigs);
+
+/* Host copies of the 1-D data of subdomain position `index` along `axis`
+ * (0 <= index < ncells[axis] for cells, < ncells[axis]-1 for patches):
+ * A, M, S as n x n row-major (any pointer may be NULL), lambda of length n. */
+fts_status fts_eigs_get(const fts_eigs *eigs, int32_t axis, int32_t index, double *A, double *M,
+                        double *S, double *lambda);
+/* n of the subdomains (k+1 or 2(k+1)). */
+int32_t fts_eigs_n(const fts_eigs *eigs);
+
+/* ---- a4: matrix-free SIPG operator --------------------------------------- */
+
+/* y = A x, the SIPG matrix of eq. (bfsipg) on this level (x, y: ndofs FP64,
+ * must not alias). */
+fts_status fts_apply_operator(const fts_level *level, const double *x, double *y, void *stream);
+/* r = b - A x (r must not alias x; may alias b). */
+fts_status fts_residual(const fts_level *level, const double *b, const double *x, double *r,
+                        void *stream);
+
+/* ---- a5-a9, a12: additive Schwarz smoother --------------------------------- */
+
+/* Workspace bytes fts_schwarz_smooth needs (one residual vector). */
+size_t fts_smooth_ws_bytes(const fts_level *level);
+
+/* nsweeps steps of the additive Schwarz smoother, Alg. (addsmoother) with the
+ * damping of eq. (additiveschwarz):
+ *     r = b - A x;   x <- x + omega * sum_j R_j^T A_j^-1 R_j r
+ * with A_j^-1 = (S x..x S) diag(1/Lambda) (S x..x S)^T (eq. fastinverse).
+ * Overlapping vertex patches are processed in 2^d parquet colors (patches of
+ * one color share no cell), which is the same operator as the uncolored sum
+ * (Sec. 2.3).  ws: device workspace of fts_smooth_ws_bytes bytes. */
+fts_status fts_schwarz_smooth(const fts_level *level, const fts_eigs *eigs, double omega,
+                              fts_prec prec, const double *b, double *x, int32_t nsweeps, void *ws,
+                              size_t ws_bytes, void *stream);
+/* Only the local-solver part: x <- x + omega * sum_j R_j^T A_j^-1 R_j r. */
+fts_status fts_schwarz_apply(const fts_level *level, const fts_eigs *eigs, double omega,
+                             fts_prec prec, const double *r, double *x, void *stream);
+
+/* ---- a10: transfers and V-cycle ------------------------------------------ */
+
+/* Transfers between a level and its parent (each parent cell = 2^d children,
+ * Sec. 2.1).  Prolongation is the embedding of V_{l-1} in V_l: the fine
+ * coefficients are the coarse polynomial's values at the fine Gauss-Lobatto
+ * nodes; restriction is its transpose (Sec. 2.2).
+ * fts_restrict:       bc  = P^T rf   (bc overwritten)
+ * fts_prolongate_add: xf += P ec */
+fts_status fts_restrict(const fts_level *coarse, const fts_level *fine, const double *rf, double *bc,
+                        void *stream);
+fts_status fts_prolongate_add(const fts_level *coarse, const fts_level *fine, const double *ec,
+                              double *xf, void *stream);
+
+/* Builds nlevels levels by coarsening `finest` (pairs of equal children per
+ * axis are merged; every level but the coarsest needs >= 2 cells per axis for
+ * vertex patches), 1-D eigen-data of every level > 0, the level vectors, and
+ * the dense FP64 LU factorisation of the coarsest matrix A_0 on the device
+ * (no pivoting: A_0 is symmetric positive definite).  omega_per_level and
+ * penalty_per_level: host arrays of nlevels entries, index 0 = coarsest
+ * (omega[0] unused); penalty_per_level may be NULL (then the mesh's
+ * penalty_factor on every level).  Allocates device memory: ~8 N_0^2 bytes
+ * for the coarse factor plus the level vectors. */
+fts_status fts_hierarchy_create(const fts_mesh_desc *finest, int32_t nlevels, fts_patch_kind kind,
+                                const double *omega_per_level, const double *penalty_per_level,
+                                int32_t m_pre, int32_t m_post, fts_hierarchy **out);
+fts_status fts_hierarchy_destroy(fts_hierarchy *hier);
+/* Level handle l (0 = coarsest), owned by the hierarchy. */
+const fts_level *fts_hierarchy_level(const fts_hierarchy *hier, int32_t l);
+const fts_eigs *fts_hierarchy_eigs(const fts_hierarchy *hier, int32_t l);
+
+/* x <- MG_L(x, b): one V-cycle of Alg. (gmg) with x as initial guess (pass
+ * x = 0 for the preconditioner), prec as in fts_schwarz_smooth.  Returns
+ * after the coarse solve on level 0.  b, x: finest-level vectors. */
+fts_status fts_vcycle(fts_hierarchy *hier, fts_prec prec, const double *b, double *x, void *stream);
+
+/* x0 = A_0^-1 b0 by the two triangular solves with the stored LU factors. */
+fts_status fts_coarse_solve(fts_hierarchy *hier, const double *b0, double *x0, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FTS_H */

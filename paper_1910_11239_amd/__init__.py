@@ -1,0 +1,242 @@
+"""Fast tensor-product Schwarz smoothers for SIPG on MI355X (gfx950).
+
+Thin ctypes binding of ``libfts.so`` (C ABI in ``include/fts.h``): argument
+marshalling only.  Vectors are torch float64 CUDA tensors (cell-major,
+lexicographic, x fastest); every call is enqueued on the current torch
+stream.  There is no CPU fallback: if the library is not built the first call
+raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfts.so")
+
+FTS_CELL, FTS_VERTEX_PATCH = 0, 1
+PREC = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
+KIND = {"cell": FTS_CELL, "vertex": FTS_VERTEX_PATCH}
+
+_lib = None
+
+
+class FtsError(RuntimeError):
+    pass
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("degree", ctypes.c_int32), ("ncells", ctypes.c_int32 * 3),
+                ("h", ctypes.c_void_p * 3), ("penalty_factor", ctypes.c_double)]
+
+
+_VP, _I32, _I64, _D, _SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+_SIGS = {
+    "fts_version": (ctypes.c_char_p, []),
+    "fts_last_error": (_I32, [ctypes.c_char_p, _SZ]),
+    "fts_level_create": (_I32, [_VP, _VP]),
+    "fts_level_destroy": (_I32, [_VP]),
+    "fts_level_ndofs": (_I64, [_VP]),
+    "fts_setup_1d_eigs": (_I32, [_VP, _I32, _VP]),
+    "fts_eigs_destroy": (_I32, [_VP]),
+    "fts_eigs_get": (_I32, [_VP, _I32, _I32, _VP, _VP, _VP, _VP]),
+    "fts_eigs_n": (_I32, [_VP]),
+    "fts_apply_operator": (_I32, [_VP, _VP, _VP, _VP]),
+    "fts_residual": (_I32, [_VP, _VP, _VP, _VP, _VP]),
+    "fts_smooth_ws_bytes": (_SZ, [_VP]),
+    "fts_schwarz_smooth": (_I32, [_VP, _VP, _D, _I32, _VP, _VP, _I32, _VP, _SZ, _VP]),
+    "fts_schwarz_apply": (_I32, [_VP, _VP, _D, _I32, _VP, _VP, _VP]),
+    "fts_restrict": (_I32, [_VP, _VP, _VP, _VP, _VP]),
+    "fts_prolongate_add": (_I32, [_VP, _VP, _VP, _VP, _VP]),
+    "fts_hierarchy_create": (_I32, [_VP, _I32, _I32, _VP, _VP, _I32, _I32, _VP]),
+    "fts_hierarchy_destroy": (_I32, [_VP]),
+    "fts_hierarchy_level": (_VP, [_VP, _I32]),
+    "fts_hierarchy_eigs": (_VP, [_VP, _I32]),
+    "fts_vcycle": (_I32, [_VP, _I32, _VP, _VP, _VP]),
+    "fts_coarse_solve": (_I32, [_VP, _VP, _VP, _VP]),
+}
+
+
+def lib():
+    """The loaded library; raises if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FtsError(f"{LIB_PATH} is not built: run `python -m paper_1910_11239_amd.build`")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(handle, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def last_error():
+    buf = ctypes.create_string_buffer(1024)
+    lib().fts_last_error(buf, 1024)
+    return buf.value.decode()
+
+
+def _check(status, what):
+    if status != 0:
+        raise FtsError(f"{what} failed with status {status}: {last_error()}")
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, n=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float64")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _desc(dim, k, widths, gamma_hat):
+    ws = [np.ascontiguousarray(np.asarray(w, dtype=np.float64)) for w in widths]
+    if len(ws) != dim:
+        raise ValueError("need one width array per axis")
+    d = MeshDesc()
+    d.dim, d.degree, d.penalty_factor = dim, k, float(gamma_hat)
+    for a in range(3):
+        d.ncells[a] = len(ws[a]) if a < dim else 1
+        d.h[a] = ws[a].ctypes.data if a < dim else None
+    return d, ws
+
+
+class Level:
+    """One mesh with its operator tables (fts_level)."""
+
+    def __init__(self, dim, k, widths, gamma_hat=1.0, _handle=None, _owner=None):
+        self.dim, self.k = dim, k
+        self.widths = tuple(np.asarray(w, dtype=np.float64) for w in widths)
+        self.gamma_hat = gamma_hat
+        self._owner = _owner
+        if _handle is not None:
+            self._h = ctypes.c_void_p(_handle)
+        else:
+            d, keep = _desc(dim, k, self.widths, gamma_hat)
+            h = ctypes.c_void_p()
+            _check(lib().fts_level_create(ctypes.byref(d), ctypes.byref(h)), "fts_level_create")
+            self._h = h
+        self.ndofs = int(lib().fts_level_ndofs(self._h))
+
+    def __del__(self):
+        if getattr(self, "_owner", None) is None and getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.fts_level_destroy(self._h)
+            self._h = None
+
+    def apply(self, x, y):
+        _check(lib().fts_apply_operator(self._h, _ptr(x, self.ndofs, "x"), _ptr(y, self.ndofs, "y"), _stream()),
+               "fts_apply_operator")
+        return y
+
+    def residual(self, b, x, r):
+        _check(lib().fts_residual(self._h, _ptr(b, self.ndofs, "b"), _ptr(x, self.ndofs, "x"),
+                                  _ptr(r, self.ndofs, "r"), _stream()), "fts_residual")
+        return r
+
+
+class Eigs:
+    """1-D eigen-data of all subdomains of a level (fts_setup_1d_eigs)."""
+
+    def __init__(self, level, kind="vertex", _handle=None, _owner=None):
+        self.level, self.kind = level, kind
+        self._owner = _owner
+        if _handle is not None:
+            self._h = ctypes.c_void_p(_handle)
+        else:
+            h = ctypes.c_void_p()
+            _check(lib().fts_setup_1d_eigs(level._h, KIND[kind], ctypes.byref(h)), "fts_setup_1d_eigs")
+            self._h = h
+        self.n = int(lib().fts_eigs_n(self._h))
+
+    def __del__(self):
+        if getattr(self, "_owner", None) is None and getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.fts_eigs_destroy(self._h)
+            self._h = None
+
+    def get(self, axis, index):
+        n = self.n
+        A, M, S = (np.zeros((n, n)) for _ in range(3))
+        lam = np.zeros(n)
+        _check(lib().fts_eigs_get(self._h, axis, index, A.ctypes.data, M.ctypes.data, S.ctypes.data,
+                                  lam.ctypes.data), "fts_eigs_get")
+        return A, M, S, lam
+
+
+def smooth_ws_bytes(level):
+    return int(lib().fts_smooth_ws_bytes(level._h))
+
+
+def schwarz_smooth(level, eigs, omega, b, x, nsweeps=1, prec="f64", ws=None):
+    import torch
+    if ws is None:
+        ws = torch.empty(level.ndofs, dtype=torch.float64, device=x.device)
+    _check(lib().fts_schwarz_smooth(level._h, eigs._h, float(omega), PREC[prec], _ptr(b, level.ndofs, "b"),
+                                    _ptr(x, level.ndofs, "x"), int(nsweeps), _ptr(ws, None, "ws"),
+                                    ws.numel() * 8, _stream()), "fts_schwarz_smooth")
+    return x
+
+
+def schwarz_apply(level, eigs, omega, r, x, prec="f64"):
+    _check(lib().fts_schwarz_apply(level._h, eigs._h, float(omega), PREC[prec], _ptr(r, level.ndofs, "r"),
+                                   _ptr(x, level.ndofs, "x"), _stream()), "fts_schwarz_apply")
+    return x
+
+
+def restrict(coarse, fine, rf, bc):
+    _check(lib().fts_restrict(coarse._h, fine._h, _ptr(rf, fine.ndofs, "rf"), _ptr(bc, coarse.ndofs, "bc"),
+                              _stream()), "fts_restrict")
+    return bc
+
+
+def prolongate_add(coarse, fine, ec, xf):
+    _check(lib().fts_prolongate_add(coarse._h, fine._h, _ptr(ec, coarse.ndofs, "ec"),
+                                    _ptr(xf, fine.ndofs, "xf"), _stream()), "fts_prolongate_add")
+    return xf
+
+
+class Hierarchy:
+    """Multigrid hierarchy (fts_hierarchy_create); level 0 is the coarsest."""
+
+    def __init__(self, dim, k, widths, nlevels, kind="vertex", omegas=0.5, gamma_hats=1.0, m_pre=2, m_post=2):
+        om = np.full(nlevels, float(omegas)) if np.isscalar(omegas) else np.asarray(omegas, dtype=np.float64)
+        gh = np.full(nlevels, float(gamma_hats)) if np.isscalar(gamma_hats) else np.asarray(gamma_hats, np.float64)
+        om, gh = np.ascontiguousarray(om), np.ascontiguousarray(gh)
+        d, keep = _desc(dim, k, widths, gh[-1])
+        h = ctypes.c_void_p()
+        _check(lib().fts_hierarchy_create(ctypes.byref(d), nlevels, KIND[kind], om.ctypes.data, gh.ctypes.data,
+                                          m_pre, m_post, ctypes.byref(h)), "fts_hierarchy_create")
+        self._h = h
+        self.dim, self.k, self.nlevels, self.kind = dim, k, nlevels, kind
+        self.levels = []
+        for l in range(nlevels):
+            lh = lib().fts_hierarchy_level(self._h, l)
+            self.levels.append(Level(dim, k, [np.zeros(1)] * dim, gh[l], _handle=lh, _owner=self))
+        self.eigs = [None] + [Eigs(self.levels[l], kind, _handle=lib().fts_hierarchy_eigs(self._h, l), _owner=self)
+                              for l in range(1, nlevels)]
+        self.ndofs = self.levels[-1].ndofs
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.fts_hierarchy_destroy(self._h)
+            self._h = None
+
+    def vcycle(self, b, x, prec="f64"):
+        _check(lib().fts_vcycle(self._h, PREC[prec], _ptr(b, self.ndofs, "b"), _ptr(x, self.ndofs, "x"),
+                                _stream()), "fts_vcycle")
+        return x
+
+    def coarse_solve(self, b0, x0):
+        n0 = self.levels[0].ndofs
+        _check(lib().fts_coarse_solve(self._h, _ptr(b0, n0, "b0"), _ptr(x0, n0, "x0"), _stream()),
+               "fts_coarse_solve")
+        return x0

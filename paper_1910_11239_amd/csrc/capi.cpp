@@ -1,0 +1,241 @@
+// C entry points for the hot calls and the multigrid hierarchy (Alg. gmg).
+#include <algorithm>
+#include <cmath>
+
+#include "fts_internal.h"
+
+namespace fts {
+fts_status coarse_factor(double *A, int64_t N, double *Linv, double *Uinv, hipStream_t stream);
+fts_status coarse_solve(const double *LU, int64_t N, const double *Linv, const double *Uinv, const double *b,
+                        double *x, hipStream_t stream);
+int coarse_nblk(int64_t N);
+int coarse_nb();
+}  // namespace fts
+
+using namespace fts;
+
+struct fts_hierarchy {
+    int nlevels = 0;
+    int kind = 0;
+    int m_pre = 1, m_post = 1;
+    std::vector<double> omega;
+    std::vector<fts_level *> levels;  // 0 = coarsest
+    std::vector<fts_eigs *> eigs;     // eigs[0] = nullptr
+    std::vector<double *> vb, vx, vr;  // per-level vectors (b, x for l < L; r for every l)
+    double *LU = nullptr, *Linv = nullptr, *Uinv = nullptr;
+    int64_t N0 = 0;
+};
+
+static hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+extern "C" {
+
+fts_status fts_apply_operator(const fts_level *level, const double *x, double *y, void *stream) {
+    if (!level || !x || !y) return fail(FTS_E_INVAL, "fts_apply_operator: NULL argument");
+    return launch_operator(level, x, nullptr, y, false, S(stream));
+}
+
+fts_status fts_residual(const fts_level *level, const double *b, const double *x, double *r, void *stream) {
+    if (!level || !b || !x || !r) return fail(FTS_E_INVAL, "fts_residual: NULL argument");
+    if (r == x) return fail(FTS_E_INVAL, "fts_residual: r must not alias x");
+    return launch_operator(level, x, b, r, true, S(stream));
+}
+
+size_t fts_smooth_ws_bytes(const fts_level *level) { return level ? (size_t)level->ndofs * sizeof(double) : 0; }
+
+fts_status fts_schwarz_apply(const fts_level *level, const fts_eigs *eigs, double omega, fts_prec prec,
+                             const double *r, double *x, void *stream) {
+    if (!level || !eigs || !r || !x) return fail(FTS_E_INVAL, "fts_schwarz_apply: NULL argument");
+    if (eigs->level != level) return fail(FTS_E_INVAL, "fts_schwarz_apply: eigs belong to another level");
+    return launch_schwarz(level, eigs, omega, prec, r, x, S(stream));
+}
+
+fts_status fts_schwarz_smooth(const fts_level *level, const fts_eigs *eigs, double omega, fts_prec prec,
+                              const double *b, double *x, int32_t nsweeps, void *ws, size_t ws_bytes,
+                              void *stream) {
+    if (!level || !eigs || !b || !x || !ws) return fail(FTS_E_INVAL, "fts_schwarz_smooth: NULL argument");
+    if (eigs->level != level) return fail(FTS_E_INVAL, "fts_schwarz_smooth: eigs belong to another level");
+    if (ws_bytes < fts_smooth_ws_bytes(level)) return fail(FTS_E_SIZE, "fts_schwarz_smooth: workspace too small");
+    double *r = static_cast<double *>(ws);
+    for (int it = 0; it < nsweeps; ++it) {
+        fts_status st = launch_operator(level, x, b, r, true, S(stream));
+        if (st != FTS_OK) return st;
+        st = launch_schwarz(level, eigs, omega, prec, r, x, S(stream));
+        if (st != FTS_OK) return st;
+    }
+    return FTS_OK;
+}
+
+static fts_status check_pair(const fts_level *c, const fts_level *f) {
+    if (!c || !f) return fail(FTS_E_INVAL, "transfer: NULL level");
+    if (c->dim != f->dim || c->k != f->k) return fail(FTS_E_INVAL, "transfer: levels differ in dim or degree");
+    for (int a = 0; a < c->dim; ++a) {
+        if (f->m[a] != 2 * c->m[a]) return fail(FTS_E_INVAL, "transfer: fine level is not the refinement");
+        for (int i = 0; i < c->m[a]; ++i) {
+            const double w = f->h[a][2 * i] + f->h[a][2 * i + 1];
+            if (std::fabs(w - c->h[a][i]) > 1e-12 * c->h[a][i] ||
+                std::fabs(f->h[a][2 * i] - f->h[a][2 * i + 1]) > 1e-12 * c->h[a][i])
+                return fail(FTS_E_INVAL, "transfer: children must be equal halves of the parent");
+        }
+    }
+    return FTS_OK;
+}
+
+fts_status fts_restrict(const fts_level *coarse, const fts_level *fine, const double *rf, double *bc,
+                        void *stream) {
+    fts_status st = check_pair(coarse, fine);
+    if (st != FTS_OK) return st;
+    if (!rf || !bc) return fail(FTS_E_INVAL, "fts_restrict: NULL vector");
+    return launch_restrict(coarse, fine, rf, bc, S(stream));
+}
+
+fts_status fts_prolongate_add(const fts_level *coarse, const fts_level *fine, const double *ec, double *xf,
+                              void *stream) {
+    fts_status st = check_pair(coarse, fine);
+    if (st != FTS_OK) return st;
+    if (!ec || !xf) return fail(FTS_E_INVAL, "fts_prolongate_add: NULL vector");
+    return launch_prolongate(coarse, fine, ec, xf, S(stream));
+}
+
+fts_status fts_hierarchy_destroy(fts_hierarchy *h) {
+    if (!h) return FTS_OK;
+    for (auto *e : h->eigs) fts_eigs_destroy(e);
+    for (auto *l : h->levels) fts_level_destroy(l);
+    for (auto *p : h->vb) if (p) hipFree(p);
+    for (auto *p : h->vx) if (p) hipFree(p);
+    for (auto *p : h->vr) if (p) hipFree(p);
+    if (h->LU) hipFree(h->LU);
+    if (h->Linv) hipFree(h->Linv);
+    if (h->Uinv) hipFree(h->Uinv);
+    delete h;
+    return FTS_OK;
+}
+
+fts_status fts_hierarchy_create(const fts_mesh_desc *finest, int32_t nlevels, fts_patch_kind kind,
+                                const double *omega_per_level, const double *penalty_per_level, int32_t m_pre,
+                                int32_t m_post, fts_hierarchy **out) {
+    if (!finest || !out || !omega_per_level) return fail(FTS_E_INVAL, "fts_hierarchy_create: NULL argument");
+    *out = nullptr;
+    if (nlevels < 1 || nlevels > 16) return fail(FTS_E_INVAL, "nlevels must be in 1..16");
+    if (m_pre < 0 || m_post < 0) return fail(FTS_E_INVAL, "negative smoothing step count");
+    if (finest->dim != 2 && finest->dim != 3) return fail(FTS_E_UNSUPPORTED, "dim must be 2 or 3");
+    fts_hierarchy *h = new fts_hierarchy();
+    h->nlevels = nlevels;
+    h->kind = kind;
+    h->m_pre = m_pre;
+    h->m_post = m_post;
+    h->omega.assign(omega_per_level, omega_per_level + nlevels);
+    // widths of every level, finest last
+    std::vector<std::vector<double>> w[3];
+    for (int a = 0; a < finest->dim; ++a) {
+        if (!finest->h[a] || finest->ncells[a] < 1) {
+            delete h;
+            return fail(FTS_E_INVAL, "invalid finest mesh");
+        }
+        w[a].assign(nlevels, {});
+        w[a][nlevels - 1].assign(finest->h[a], finest->h[a] + finest->ncells[a]);
+        for (int l = nlevels - 2; l >= 0; --l) {
+            const auto &f = w[a][l + 1];
+            if (f.size() % 2) {
+                delete h;
+                return fail(FTS_E_INVAL, "cannot coarsen an odd number of cells");
+            }
+            for (size_t i = 0; i < f.size(); i += 2) {
+                if (std::fabs(f[i] - f[i + 1]) > 1e-12 * f[i]) {
+                    delete h;
+                    return fail(FTS_E_INVAL, "children of a coarse cell must be equal halves");
+                }
+                w[a][l].push_back(f[i] + f[i + 1]);
+            }
+        }
+    }
+    fts_status st = FTS_OK;
+    for (int l = 0; l < nlevels && st == FTS_OK; ++l) {
+        fts_mesh_desc d = *finest;
+        for (int a = 0; a < finest->dim; ++a) {
+            d.ncells[a] = (int32_t)w[a][l].size();
+            d.h[a] = w[a][l].data();
+        }
+        d.penalty_factor = penalty_per_level ? penalty_per_level[l] : finest->penalty_factor;
+        fts_level *lv = nullptr;
+        st = fts_level_create(&d, &lv);
+        if (st != FTS_OK) break;
+        h->levels.push_back(lv);
+        fts_eigs *eg = nullptr;
+        if (l > 0) {
+            st = fts_setup_1d_eigs(lv, kind, &eg);
+            if (st != FTS_OK) break;
+        }
+        h->eigs.push_back(eg);
+        double *pb = nullptr, *px = nullptr, *pr = nullptr;
+        const size_t bytes = (size_t)lv->ndofs * sizeof(double);
+        if (l < nlevels - 1 && (hipMalloc(&pb, bytes) != hipSuccess || hipMalloc(&px, bytes) != hipSuccess))
+            st = fail(FTS_E_HIP, "hipMalloc of level vectors failed");
+        if (st == FTS_OK && hipMalloc(&pr, bytes) != hipSuccess) st = fail(FTS_E_HIP, "hipMalloc of level vectors failed");
+        h->vb.push_back(pb);
+        h->vx.push_back(px);
+        h->vr.push_back(pr);
+    }
+    if (st == FTS_OK) {
+        const fts_level *l0 = h->levels[0];
+        const int64_t N = l0->ndofs;
+        h->N0 = N;
+        const int nblk = coarse_nblk(N), nb = coarse_nb();
+        if (hipMalloc(&h->LU, (size_t)N * N * sizeof(double)) != hipSuccess ||
+            hipMalloc(&h->Linv, (size_t)nblk * nb * nb * sizeof(double)) != hipSuccess ||
+            hipMalloc(&h->Uinv, (size_t)nblk * nb * nb * sizeof(double)) != hipSuccess)
+            st = fail(FTS_E_HIP, "hipMalloc of the coarse factor failed");
+        hipStream_t s0 = nullptr;
+        if (st == FTS_OK) st = launch_fill(h->LU, N * N, 0.0, s0);
+        if (st == FTS_OK) st = launch_assemble_dense(l0, h->LU, s0);
+        if (st == FTS_OK) st = coarse_factor(h->LU, N, h->Linv, h->Uinv, s0);
+    }
+    if (st != FTS_OK) {
+        fts_hierarchy_destroy(h);
+        return st;
+    }
+    *out = h;
+    return FTS_OK;
+}
+
+const fts_level *fts_hierarchy_level(const fts_hierarchy *h, int32_t l) {
+    return (h && l >= 0 && l < h->nlevels) ? h->levels[l] : nullptr;
+}
+const fts_eigs *fts_hierarchy_eigs(const fts_hierarchy *h, int32_t l) {
+    return (h && l >= 0 && l < h->nlevels) ? h->eigs[l] : nullptr;
+}
+
+fts_status fts_coarse_solve(fts_hierarchy *h, const double *b0, double *x0, void *stream) {
+    if (!h || !b0 || !x0) return fail(FTS_E_INVAL, "fts_coarse_solve: NULL argument");
+    return coarse_solve(h->LU, h->N0, h->Linv, h->Uinv, b0, x0, S(stream));
+}
+
+static fts_status vcycle_level(fts_hierarchy *h, int l, fts_prec prec, const double *b, double *x, hipStream_t s) {
+    if (l == 0) return coarse_solve(h->LU, h->N0, h->Linv, h->Uinv, b, x, s);
+    const fts_level *lv = h->levels[l];
+    const fts_eigs *eg = h->eigs[l];
+    double *r = h->vr[l];
+    fts_status st = FTS_OK;
+    for (int i = 0; i < h->m_pre && st == FTS_OK; ++i) {
+        st = launch_operator(lv, x, b, r, true, s);
+        if (st == FTS_OK) st = launch_schwarz(lv, eg, h->omega[l], prec, r, x, s);
+    }
+    if (st == FTS_OK) st = launch_operator(lv, x, b, r, true, s);
+    if (st == FTS_OK) st = launch_restrict(h->levels[l - 1], lv, r, h->vb[l - 1], s);
+    if (st == FTS_OK && l - 1 > 0) st = launch_fill(h->vx[l - 1], h->levels[l - 1]->ndofs, 0.0, s);
+    if (st == FTS_OK) st = vcycle_level(h, l - 1, prec, h->vb[l - 1], h->vx[l - 1], s);
+    if (st == FTS_OK) st = launch_prolongate(h->levels[l - 1], lv, h->vx[l - 1], x, s);
+    for (int i = 0; i < h->m_post && st == FTS_OK; ++i) {
+        st = launch_operator(lv, x, b, r, true, s);
+        if (st == FTS_OK) st = launch_schwarz(lv, eg, h->omega[l], prec, r, x, s);
+    }
+    return st;
+}
+
+fts_status fts_vcycle(fts_hierarchy *h, fts_prec prec, const double *b, double *x, void *stream) {
+    if (!h || !b || !x) return fail(FTS_E_INVAL, "fts_vcycle: NULL argument");
+    if (b == x) return fail(FTS_E_INVAL, "fts_vcycle: b must not alias x");
+    return vcycle_level(h, h->nlevels - 1, prec, b, x, S(stream));
+}
+
+}  // extern "C"

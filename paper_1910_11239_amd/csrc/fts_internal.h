@@ -1,0 +1,109 @@
+// Internal declarations of libfts: handle layouts, kernel argument structs,
+// host setup helpers and the launchers of the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fts.h"
+
+namespace fts {
+
+constexpr int kMaxDegree = 9;
+constexpr int kMaxN1 = kMaxDegree + 1;
+
+void set_error(const std::string &msg);
+fts_status fail(fts_status code, const std::string &msg);
+fts_status hip_fail(hipError_t err, const char *what);
+
+#define FTS_HIP_CHECK(call)                                   \
+    do {                                                      \
+        hipError_t e_ = (call);                               \
+        if (e_ != hipSuccess) return ::fts::hip_fail(e_, #call); \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Host 1-D reference data on [0, 1] (Sec. 2.1, Sec. 3 intro): Gauss-Lobatto
+// nodes, exact mass / stiffness matrices, endpoint values and derivatives,
+// and the two child-embedding matrices of the midpoint refinement.
+struct Ref1D {
+    int k = 0, n1 = 0;
+    std::vector<double> nodes;   // n1
+    std::vector<double> Mhat;    // n1 x n1, [test][trial]
+    std::vector<double> Lhat;    // n1 x n1
+    std::vector<double> v0, v1;  // phi_i(0), phi_i(1)
+    std::vector<double> d0, d1;  // phi_i'(0), phi_i'(1)
+    std::vector<double> E[2];    // E_c[i][j] = phi_j((xi_i + c)/2)
+    void build(int degree);
+    // 1-D SIPG matrices (Sec. 3.2), row = test function, column = trial function.
+    // Neighbour widths <= 0 mean "boundary face".
+    void cell_operator(double h, double h_left, double h_right, double gamma_hat,
+                       double *A) const;
+    void interface_block(double hl, double hr, double gamma_hat, double *B) const;
+};
+
+// Generalised symmetric-definite eigenproblem A S = M S diag(lam), S^T M S = I,
+// by Cholesky of M and cyclic Jacobi on L^-1 A L^-T (FP64, host).
+// Returns FTS_E_NOT_SPD if M is not positive definite or an eigenvalue <= 0.
+fts_status sym_gen_eig(int n, const double *A, const double *M, double *S, double *lam);
+
+// ---------------------------------------------------------------------------
+// Device-side views passed to kernels by value.
+struct LevelView {
+    int m[3];                 // cells per axis (m[2] = 1 in 2-D)
+    int64_t ncells;
+    const double *cellop[3];  // per axis: m[a] blocks of n1 x n1 (A_cell, eq. 1Dsipg)
+    const double *iface[3];   // per axis: m[a]-1 blocks, coupling cell c (test) to c+1 (trial)
+    const double *h[3];       // per axis widths
+    const double *Mhat;       // n1 x n1
+    const double *E;          // 2 x n1 x n1 embedding matrices
+};
+
+struct EigView {
+    int count[3];             // positions per axis
+    const double *S[3];       // per axis: count blocks of n x n, row-major [i][m]
+    const double *lam[3];     // per axis: count blocks of n
+    const float *S32[3];
+    const float *lam32[3];
+};
+
+}  // namespace fts
+
+struct fts_level {
+    int dim = 0, k = 0, n1 = 0;
+    int m[3] = {1, 1, 1};
+    std::vector<double> h[3];
+    double gamma_hat = 1.0;
+    int64_t ncells = 0, ndofs = 0;
+    fts::Ref1D ref;
+    std::vector<double> host_cellop[3], host_iface[3];
+    double *d_tab = nullptr;  // single device allocation holding every table
+    fts::LevelView view{};
+};
+
+struct fts_eigs {
+    const fts_level *level = nullptr;
+    int kind = 0, n = 0;
+    int count[3] = {0, 0, 0};
+    std::vector<double> A[3], M[3], S[3], lam[3];
+    double *d_tab = nullptr;
+    float *d_tab32 = nullptr;
+    fts::EigView view{};
+};
+
+namespace fts {
+// Launchers (kernels.hip).  All asynchronous on `stream`.
+fts_status launch_operator(const fts_level *lv, const double *x, const double *b, double *y,
+                           bool residual, hipStream_t stream);
+fts_status launch_schwarz(const fts_level *lv, const fts_eigs *eg, double omega, fts_prec prec,
+                          const double *r, double *x, hipStream_t stream);
+fts_status launch_restrict(const fts_level *coarse, const fts_level *fine, const double *rf,
+                           double *bc, hipStream_t stream);
+fts_status launch_prolongate(const fts_level *coarse, const fts_level *fine, const double *ec,
+                             double *xf, hipStream_t stream);
+fts_status launch_assemble_dense(const fts_level *lv, double *A, hipStream_t stream);
+fts_status launch_fill(double *p, int64_t n, double v, hipStream_t stream);
+}  // namespace fts

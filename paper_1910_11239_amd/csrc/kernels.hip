@@ -1,0 +1,600 @@
+// HIP kernels for gfx950: matrix-free SIPG operator, fast-diagonalisation
+// Schwarz local solves on cells and vertex patches, grid transfers and the
+// dense assembly of the coarse matrix.
+//
+// Data layout: vectors are cell-major (cells lexicographic, x fastest), each
+// cell holding (k+1)^d FP64 coefficients lexicographic with x fastest.  A
+// subdomain tensor of extent N per axis lives in LDS with x fastest.
+// Contractions are "one thread per 1-D line": a thread owns a line of the
+// tensor along one axis, keeps it in registers and applies the N x N 1-D
+// matrix, so each LDS value is read once per contraction.
+#include "fts_internal.h"
+
+namespace fts {
+
+constexpr int ipow(int b, int e) {
+    int r = 1;
+    for (int i = 0; i < e; ++i) r *= b;
+    return r;
+}
+constexpr int rup64(int x) { return (x + 63) / 64 * 64; }
+
+// Offset of the first element and stride of line l along axis a of a
+// D-dimensional tensor with extent N per axis (x fastest).  Lines enumerate
+// the remaining coordinates with the lower axis fastest.
+template <int D, int N>
+__device__ __forceinline__ int line_base(int a, int l) {
+    if constexpr (D == 2) {
+        return a == 0 ? l * N : l;
+    } else {
+        const int u = l % N, v = l / N;
+        if (a == 0) return u * N + v * N * N;
+        if (a == 1) return u + v * N * N;
+        return u + v * N;
+    }
+}
+template <int N>
+__device__ __forceinline__ int line_stride(int a) {
+    return a == 0 ? 1 : (a == 1 ? N : N * N);
+}
+
+__device__ __forceinline__ void cell_coords(int64_t cell, const int *m, int *c) {
+    c[0] = (int)(cell % m[0]);
+    const int64_t r = cell / m[0];
+    c[1] = (int)(r % m[1]);
+    c[2] = (int)(r / m[1]);
+}
+
+// ---------------------------------------------------------------------------
+// SIPG operator (Sec. 3.2, eq. KDseparable / bulkcart / 1Dsipg): on a
+// rectilinear mesh the operator restricted to the rows of cell K is
+//   (A x)_K = sum_t (prod_{s != t} h_s) (Mhat x..x W_t x..x Mhat)
+//   W_t = A_t^K x_K + B_t(K, K+e_t) x_{K+e_t} + B_t(K-e_t, K)^T x_{K-e_t}
+// with the 1-D cell operator A_t^K (both faces' Nitsche terms) and the
+// interface blocks B_t.  Each block of PPB cells: 1) every thread applies the
+// 1-D operator along one line of its cell for each axis, reading the
+// neighbour lines from global memory; 2) the transverse mass matrices are
+// applied line by line in LDS.
+template <int D, int N1>
+struct OpCfg {
+    static constexpr int NC = ipow(N1, D);
+    static constexpr int LINES = ipow(N1, D - 1);
+    static constexpr int THREADS = LINES <= 64 ? 64 : rup64(LINES);
+    static constexpr int PPB = THREADS / LINES;
+};
+
+template <int D, int N1>
+__device__ __forceinline__ void mass_line(const double *src, double *dst, int a, int l, double scale,
+                                          const double *Mh, bool acc) {
+    const int base = line_base<D, N1>(a, l), st = line_stride<N1>(a);
+    double in[N1];
+#pragma unroll
+    for (int i = 0; i < N1; ++i) in[i] = src[base + i * st];
+#pragma unroll
+    for (int o = 0; o < N1; ++o) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < N1; ++i) s = fma(Mh[o * N1 + i], in[i], s);
+        s *= scale;
+        dst[base + o * st] = acc ? dst[base + o * st] + s : s;
+    }
+}
+
+template <int D, int N1, bool RES>
+__global__ void __launch_bounds__((OpCfg<D, N1>::THREADS))
+k_operator(LevelView g, const double *__restrict__ x, const double *__restrict__ b, double *__restrict__ y) {
+    using C = OpCfg<D, N1>;
+    constexpr int NC = C::NC, LINES = C::LINES, PPB = C::PPB, TH = C::THREADS;
+    __shared__ double X[PPB * NC];
+    __shared__ double W[D][PPB * NC];
+    __shared__ double U[PPB * NC];
+    const int t = threadIdx.x;
+    const int q = t / LINES, l = t % LINES;
+    const int64_t cell0 = (int64_t)blockIdx.x * PPB;
+    for (int p = t; p < PPB * NC; p += TH) {
+        const int64_t cc = cell0 + p / NC;
+        X[p] = cc < g.ncells ? x[cc * NC + p % NC] : 0.0;
+    }
+    __syncthreads();
+    const int64_t cell = cell0 + q;
+    const bool act = (q < PPB) && (cell < g.ncells);
+    int c[3] = {0, 0, 0};
+    if (act) cell_coords(cell, g.m, c);
+    const int64_t cs[3] = {1, g.m[0], (int64_t)g.m[0] * g.m[1]};
+    const double hx = act ? g.h[0][c[0]] : 0.0, hy = act ? g.h[1][c[1]] : 0.0;
+    const double hz = (D == 3 && act) ? g.h[2][c[2]] : 1.0;
+    const int qo = q * NC;
+    if (act) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const int base = line_base<D, N1>(a, l), st = line_stride<N1>(a);
+            double in[N1], out[N1];
+#pragma unroll
+            for (int i = 0; i < N1; ++i) in[i] = X[qo + base + i * st];
+            const double *A = g.cellop[a] + (size_t)c[a] * N1 * N1;
+#pragma unroll
+            for (int o = 0; o < N1; ++o) {
+                double s = 0.0;
+#pragma unroll
+                for (int i = 0; i < N1; ++i) s = fma(A[o * N1 + i], in[i], s);
+                out[o] = s;
+            }
+            if (c[a] + 1 < g.m[a]) {
+                const double *nb = x + (cell + cs[a]) * NC;
+#pragma unroll
+                for (int i = 0; i < N1; ++i) in[i] = nb[base + i * st];
+                const double *B = g.iface[a] + (size_t)c[a] * N1 * N1;
+#pragma unroll
+                for (int o = 0; o < N1; ++o)
+#pragma unroll
+                    for (int i = 0; i < N1; ++i) out[o] = fma(B[o * N1 + i], in[i], out[o]);
+            }
+            if (c[a] > 0) {
+                const double *nb = x + (cell - cs[a]) * NC;
+#pragma unroll
+                for (int i = 0; i < N1; ++i) in[i] = nb[base + i * st];
+                const double *B = g.iface[a] + (size_t)(c[a] - 1) * N1 * N1;
+#pragma unroll
+                for (int o = 0; o < N1; ++o)
+#pragma unroll
+                    for (int i = 0; i < N1; ++i) out[o] = fma(B[i * N1 + o], in[i], out[o]);
+            }
+#pragma unroll
+            for (int o = 0; o < N1; ++o) W[a][qo + base + o * st] = out[o];
+        }
+    }
+    __syncthreads();
+    const double *Mh = g.Mhat;
+    double *Y;
+    if constexpr (D == 2) {
+        if (act) mass_line<D, N1>(W[0] + qo, U + qo, 1, l, hy, Mh, false);
+        __syncthreads();
+        if (act) mass_line<D, N1>(W[1] + qo, U + qo, 0, l, hx, Mh, true);
+        __syncthreads();
+        Y = U;
+    } else {
+        // U = hy hz (Mhat_y W_x) + hx hz (Mhat_x W_y);  X = Mhat_y W_z
+        if (act) mass_line<D, N1>(W[0] + qo, U + qo, 1, l, hy * hz, Mh, false);
+        __syncthreads();
+        if (act) {
+            mass_line<D, N1>(W[1] + qo, U + qo, 0, l, hx * hz, Mh, true);
+            mass_line<D, N1>(W[2] + qo, X + qo, 1, l, 1.0, Mh, false);
+        }
+        __syncthreads();
+        // W0 = Mhat_z U
+        if (act) mass_line<D, N1>(U + qo, W[0] + qo, 2, l, 1.0, Mh, false);
+        __syncthreads();
+        // W0 += hx hy Mhat_x X
+        if (act) mass_line<D, N1>(X + qo, W[0] + qo, 0, l, hx * hy, Mh, true);
+        __syncthreads();
+        Y = W[0];
+    }
+    for (int p = t; p < PPB * NC; p += TH) {
+        const int64_t cc = cell0 + p / NC;
+        if (cc < g.ncells) {
+            const int64_t gi = cc * NC + p % NC;
+            y[gi] = RES ? b[gi] - Y[p] : Y[p];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Schwarz local solves (Sec. 3.2, eq. fastinverse / eigenvectormatvec):
+//   x += omega * R_j^T (S x..x S) diag(1/Lambda) (S x..x S)^T R_j r
+// for a batch of subdomains (cells, or vertex patches of one parquet color).
+// KIND 0: cells, tensor extent N = k+1; KIND 1: vertex patches, N = 2(k+1),
+// local index a_t = (cell offset)_t (k+1) + i_t.  T is the contraction type.
+template <int D, int N1, int KIND>
+struct SwCfg {
+    static constexpr int N = KIND ? 2 * N1 : N1;
+    static constexpr int NT = ipow(N, D);
+    static constexpr int NC1 = ipow(N1, D);
+    static constexpr int NSC = KIND ? (1 << D) : 1;
+    static constexpr int LINES = ipow(N, D - 1);
+    static constexpr int THREADS = LINES <= 64 ? 64 : rup64(LINES);
+    static constexpr int PPB = THREADS / LINES;
+};
+
+struct SubGrid {
+    int cnt[3];    // subdomains per axis in this launch
+    int first[3];  // position of the first subdomain per axis
+    int step;      // 1 (cells) or 2 (one parquet color of vertex patches)
+    int64_t nsub;
+};
+
+template <typename T>
+__device__ __forceinline__ const T *eig_S(const EigView &e, int a);
+template <>
+__device__ __forceinline__ const double *eig_S<double>(const EigView &e, int a) { return e.S[a]; }
+template <>
+__device__ __forceinline__ const float *eig_S<float>(const EigView &e, int a) { return e.S32[a]; }
+template <typename T>
+__device__ __forceinline__ const T *eig_L(const EigView &e, int a);
+template <>
+__device__ __forceinline__ const double *eig_L<double>(const EigView &e, int a) { return e.lam[a]; }
+template <>
+__device__ __forceinline__ const float *eig_L<float>(const EigView &e, int a) { return e.lam32[a]; }
+
+template <int D, int N, bool FWD, typename T>
+__device__ __forceinline__ void contract_line(T *Tq, int a, int l, const T *__restrict__ S) {
+    const int base = line_base<D, N>(a, l), st = line_stride<N>(a);
+    T in[N], out[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) in[i] = Tq[base + i * st];
+    if constexpr (FWD) {
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            T s = 0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) s = fma(S[i * N + m], in[i], s);
+            out[m] = s;
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            T s = 0;
+#pragma unroll
+            for (int m = 0; m < N; ++m) s = fma(S[i * N + m], in[m], s);
+            out[i] = s;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) Tq[base + i * st] = out[i];
+}
+
+template <int D, int N1, int KIND, typename T>
+__global__ void __launch_bounds__((SwCfg<D, N1, KIND>::THREADS))
+k_schwarz(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r, double *__restrict__ x, double omega) {
+    using C = SwCfg<D, N1, KIND>;
+    constexpr int N = C::N, NT = C::NT, NC1 = C::NC1, NSC = C::NSC, LINES = C::LINES, PPB = C::PPB,
+                  TH = C::THREADS;
+    __shared__ T Ts[PPB * NT];
+    const int t = threadIdx.x;
+    const int q = t / LINES, l = t % LINES;
+    const int64_t s0 = (int64_t)blockIdx.x * PPB;
+
+    // subdomain -> per-axis position (anchor cell of a patch = vertex - 1)
+    auto position = [&](int64_t s, int *p) {
+        const int j0 = (int)(s % sg.cnt[0]);
+        const int64_t rr = s / sg.cnt[0];
+        const int j1 = (int)(rr % sg.cnt[1]);
+        const int j2 = (int)(rr / sg.cnt[1]);
+        p[0] = sg.first[0] + sg.step * j0;
+        p[1] = sg.first[1] + sg.step * j1;
+        p[2] = D == 3 ? sg.first[2] + sg.step * j2 : 0;
+    };
+    const int64_t cs1 = g.m[0], cs2 = (int64_t)g.m[0] * g.m[1];
+    // gather R_j r: flat over (subdomain, cell of the subdomain, local DoF)
+    for (int p = t; p < PPB * NSC * NC1; p += TH) {
+        const int qq = p / (NSC * NC1), rem = p % (NSC * NC1), sc = rem / NC1, i = rem % NC1;
+        const int64_t s = s0 + qq;
+        if (s >= sg.nsub) continue;
+        int pos[3];
+        position(s, pos);
+        const int o0 = sc & 1, o1 = (sc >> 1) & 1, o2 = (sc >> 2) & 1;
+        const int64_t cell = (pos[0] + o0) + (pos[1] + o1) * cs1 + (D == 3 ? (pos[2] + o2) * cs2 : 0);
+        const int i0 = i % N1, i1 = (i / N1) % N1, i2 = D == 3 ? i / (N1 * N1) : 0;
+        const int lds = (o0 * N1 + i0) + (o1 * N1 + i1) * N + (D == 3 ? (o2 * N1 + i2) * N * N : 0);
+        Ts[qq * NT + lds] = (T)r[cell * NC1 + i];
+    }
+    __syncthreads();
+    const int64_t s = s0 + q;
+    const bool act = (q < PPB) && (s < sg.nsub);
+    int pos[3] = {0, 0, 0};
+    if (act) position(s, pos);
+    T *Tq = Ts + q * NT;
+    // forward transform (S^T along every axis)
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        if (act) contract_line<D, N, true, T>(Tq, a, l, eig_S<T>(e, a) + (size_t)pos[a] * N * N);
+        __syncthreads();
+    }
+    // eigenvalue scaling omega / (lambda_x + lambda_y (+ lambda_z))
+    for (int p = t; p < PPB * NT; p += TH) {
+        const int qq = p / NT, mm = p % NT;
+        const int64_t ss = s0 + qq;
+        if (ss >= sg.nsub) continue;
+        int ps[3];
+        position(ss, ps);
+        const int m0 = mm % N, m1 = (mm / N) % N, m2 = D == 3 ? mm / (N * N) : 0;
+        T lam = eig_L<T>(e, 0)[(size_t)ps[0] * N + m0] + eig_L<T>(e, 1)[(size_t)ps[1] * N + m1];
+        if constexpr (D == 3) lam += eig_L<T>(e, 2)[(size_t)ps[2] * N + m2];
+        Ts[p] = Ts[p] * ((T)omega / lam);
+    }
+    __syncthreads();
+    // backward transform (S along every axis)
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        if (act) contract_line<D, N, false, T>(Tq, a, l, eig_S<T>(e, a) + (size_t)pos[a] * N * N);
+        __syncthreads();
+    }
+    // scatter-add R_j^T
+    for (int p = t; p < PPB * NSC * NC1; p += TH) {
+        const int qq = p / (NSC * NC1), rem = p % (NSC * NC1), sc = rem / NC1, i = rem % NC1;
+        const int64_t ss = s0 + qq;
+        if (ss >= sg.nsub) continue;
+        int ps[3];
+        position(ss, ps);
+        const int o0 = sc & 1, o1 = (sc >> 1) & 1, o2 = (sc >> 2) & 1;
+        const int64_t cell = (ps[0] + o0) + (ps[1] + o1) * cs1 + (D == 3 ? (ps[2] + o2) * cs2 : 0);
+        const int i0 = i % N1, i1 = (i / N1) % N1, i2 = D == 3 ? i / (N1 * N1) : 0;
+        const int lds = (o0 * N1 + i0) + (o1 * N1 + i1) * N + (D == 3 ? (o2 * N1 + i2) * N * N : 0);
+        const int64_t gi = cell * NC1 + i;
+        x[gi] = x[gi] + (double)Ts[qq * NT + lds];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Transfers (Sec. 2.2).  Child c of a coarse cell sits at offset o in
+// {0,1}^d; its coefficients are (E_{o_d} x..x E_{o_1}) applied to the coarse
+// coefficients, E_o[i][j] = phi_j((xi_i + o)/2).  Restriction applies the
+// transposes and sums over the 2^d children.
+template <int D, int N1>
+struct XferCfg {
+    static constexpr int NC = ipow(N1, D);
+    static constexpr int LINES = ipow(N1, D - 1);
+    static constexpr int THREADS = LINES <= 64 ? 64 : rup64(LINES);
+    static constexpr int PPB = THREADS / LINES;
+};
+
+template <int D, int N1, bool TRANS>
+__device__ __forceinline__ void embed_line(double *Tq, int a, int l, const double *E) {
+    const int base = line_base<D, N1>(a, l), st = line_stride<N1>(a);
+    double in[N1], out[N1];
+#pragma unroll
+    for (int i = 0; i < N1; ++i) in[i] = Tq[base + i * st];
+#pragma unroll
+    for (int o = 0; o < N1; ++o) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < N1; ++i) s = fma(TRANS ? E[i * N1 + o] : E[o * N1 + i], in[i], s);
+        out[o] = s;
+    }
+#pragma unroll
+    for (int o = 0; o < N1; ++o) Tq[base + o * st] = out[o];
+}
+
+template <int D, int N1, bool RESTRICT>
+__global__ void __launch_bounds__((XferCfg<D, N1>::THREADS))
+k_transfer(LevelView gc, LevelView gf, const double *__restrict__ src, double *__restrict__ dst) {
+    using C = XferCfg<D, N1>;
+    constexpr int NC = C::NC, LINES = C::LINES, PPB = C::PPB, TH = C::THREADS;
+    __shared__ double Tw[PPB * NC];
+    __shared__ double Acc[PPB * NC];
+    const int t = threadIdx.x, q = t / LINES, l = t % LINES;
+    const int64_t c0 = (int64_t)blockIdx.x * PPB;
+    const int64_t fs1 = gf.m[0], fs2 = (int64_t)gf.m[0] * gf.m[1];
+    auto child_cell = [&](int64_t cc, int ch) {
+        int c[3];
+        cell_coords(cc, gc.m, c);
+        return (int64_t)(2 * c[0] + (ch & 1)) + (2 * c[1] + ((ch >> 1) & 1)) * fs1 +
+               (D == 3 ? (int64_t)(2 * c[2] + ((ch >> 2) & 1)) * fs2 : 0);
+    };
+    if constexpr (!RESTRICT) {
+        for (int p = t; p < PPB * NC; p += TH) {
+            const int64_t cc = c0 + p / NC;
+            Acc[p] = cc < gc.ncells ? src[cc * NC + p % NC] : 0.0;
+        }
+    } else {
+        for (int p = t; p < PPB * NC; p += TH) Acc[p] = 0.0;
+    }
+    __syncthreads();
+    const bool act = q < PPB && (c0 + q) < gc.ncells;
+    for (int ch = 0; ch < (1 << D); ++ch) {
+        if constexpr (RESTRICT) {
+            for (int p = t; p < PPB * NC; p += TH) {
+                const int64_t cc = c0 + p / NC;
+                Tw[p] = cc < gc.ncells ? src[child_cell(cc, ch) * NC + p % NC] : 0.0;
+            }
+        } else {
+            for (int p = t; p < PPB * NC; p += TH) Tw[p] = Acc[p];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            if (act) embed_line<D, N1, RESTRICT>(Tw + q * NC, a, l, gc.E + ((ch >> a) & 1) * N1 * N1);
+            __syncthreads();
+        }
+        for (int p = t; p < PPB * NC; p += TH) {
+            const int64_t cc = c0 + p / NC;
+            if (cc >= gc.ncells) continue;
+            if constexpr (RESTRICT) {
+                Acc[p] += Tw[p];
+            } else {
+                const int64_t gi = child_cell(cc, ch) * NC + p % NC;
+                dst[gi] += Tw[p];
+            }
+        }
+        __syncthreads();
+    }
+    if constexpr (RESTRICT) {
+        for (int p = t; p < PPB * NC; p += TH) {
+            const int64_t cc = c0 + p / NC;
+            if (cc < gc.ncells) dst[cc * NC + p % NC] = Acc[p];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Dense coarse matrix, column-major with leading dimension N: entry (row, col)
+// from the same 1-D tables as the operator.  One thread per row; for a fixed
+// column the rows of a wave are consecutive, so the stores coalesce.
+template <int D, int N1>
+__global__ void __launch_bounds__(256) k_assemble_dense(LevelView g, double *__restrict__ A, int64_t N) {
+    constexpr int NC = ipow(N1, D);
+    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (row >= N) return;
+    const int64_t cell = row / NC;
+    const int iota = (int)(row % NC);
+    int c[3];
+    cell_coords(cell, g.m, c);
+    int ii[3] = {iota % N1, (iota / N1) % N1, D == 3 ? iota / (N1 * N1) : 0};
+    const int64_t cs[3] = {1, g.m[0], (int64_t)g.m[0] * g.m[1]};
+    double h[3] = {g.h[0][c[0]], g.h[1][c[1]], D == 3 ? g.h[2][c[2]] : 1.0};
+    const double *Mh = g.Mhat;
+    for (int j = 0; j < NC; ++j) {
+        int jj[3] = {j % N1, (j / N1) % N1, D == 3 ? j / (N1 * N1) : 0};
+        double mass[3];
+        for (int a = 0; a < D; ++a) mass[a] = h[a] * Mh[ii[a] * N1 + jj[a]];
+        // diagonal block
+        double v = 0.0;
+        for (int tt = 0; tt < D; ++tt) {
+            double term = g.cellop[tt][(size_t)c[tt] * N1 * N1 + ii[tt] * N1 + jj[tt]];
+            for (int a = 0; a < D; ++a)
+                if (a != tt) term *= mass[a];
+            v += term;
+        }
+        A[row + (cell * NC + j) * N] = v;
+        for (int tt = 0; tt < D; ++tt) {
+            double tr = 1.0;
+            for (int a = 0; a < D; ++a)
+                if (a != tt) tr *= mass[a];
+            if (c[tt] + 1 < g.m[tt]) {
+                const double bv = g.iface[tt][(size_t)c[tt] * N1 * N1 + ii[tt] * N1 + jj[tt]];
+                A[row + ((cell + cs[tt]) * NC + j) * N] = bv * tr;
+            }
+            if (c[tt] > 0) {
+                const double bv = g.iface[tt][(size_t)(c[tt] - 1) * N1 * N1 + jj[tt] * N1 + ii[tt]];
+                A[row + ((cell - cs[tt]) * NC + j) * N] = bv * tr;
+            }
+        }
+    }
+}
+
+__global__ void k_fill(double *__restrict__ p, int64_t n, double v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Dispatch on (dim, degree) to the template instances.
+template <template <int, int> class F, typename... Args>
+fts_status dispatch(int dim, int n1, Args &&...args) {
+#define FTS_CASE(DD, NN) \
+    if (dim == DD && n1 == NN) return F<DD, NN>::run(args...);
+    FTS_CASE(2, 2) FTS_CASE(2, 3) FTS_CASE(2, 4) FTS_CASE(2, 5) FTS_CASE(2, 6) FTS_CASE(2, 7)
+    FTS_CASE(2, 8) FTS_CASE(2, 9) FTS_CASE(2, 10)
+    FTS_CASE(3, 2) FTS_CASE(3, 3) FTS_CASE(3, 4) FTS_CASE(3, 5) FTS_CASE(3, 6) FTS_CASE(3, 7)
+    FTS_CASE(3, 8) FTS_CASE(3, 9) FTS_CASE(3, 10)
+#undef FTS_CASE
+    return fail(FTS_E_UNSUPPORTED, "dimension/degree combination not built");
+}
+
+static fts_status check_launch(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, what);
+    return FTS_OK;
+}
+
+template <int D, int N1>
+struct RunOperator {
+    static fts_status run(const fts_level *lv, const double *x, const double *b, double *y, bool res,
+                          hipStream_t st) {
+        using C = OpCfg<D, N1>;
+        const int64_t blocks = (lv->ncells + C::PPB - 1) / C::PPB;
+        if (blocks == 0) return FTS_OK;
+        if (res)
+            k_operator<D, N1, true><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(lv->view, x, b, y);
+        else
+            k_operator<D, N1, false><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(lv->view, x, b, y);
+        return check_launch("k_operator");
+    }
+};
+
+fts_status launch_operator(const fts_level *lv, const double *x, const double *b, double *y, bool residual,
+                           hipStream_t stream) {
+    return dispatch<RunOperator>(lv->dim, lv->n1, lv, x, b, y, residual, stream);
+}
+
+template <int D, int N1>
+struct RunSchwarz {
+    template <int KIND, typename T>
+    static fts_status go(const fts_level *lv, const fts_eigs *eg, double omega, const double *r, double *x,
+                         hipStream_t st) {
+        using C = SwCfg<D, N1, KIND>;
+        const int ncolor = KIND ? (1 << D) : 1;
+        for (int color = 0; color < ncolor; ++color) {
+            SubGrid sg{};
+            sg.step = KIND ? 2 : 1;
+            sg.nsub = 1;
+            for (int a = 0; a < 3; ++a) {
+                if (a >= D) {
+                    sg.cnt[a] = 1;
+                    sg.first[a] = 0;
+                    continue;
+                }
+                const int npos = eg->count[a];  // positions along the axis
+                sg.first[a] = KIND ? ((color >> a) & 1) : 0;
+                sg.cnt[a] = npos > sg.first[a] ? (npos - sg.first[a] + sg.step - 1) / sg.step : 0;
+                sg.nsub *= sg.cnt[a];
+            }
+            if (sg.nsub == 0) continue;
+            const int64_t blocks = (sg.nsub + C::PPB - 1) / C::PPB;
+            k_schwarz<D, N1, KIND, T><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(lv->view, eg->view, sg,
+                                                                                       r, x, omega);
+            fts_status s = check_launch("k_schwarz");
+            if (s != FTS_OK) return s;
+        }
+        return FTS_OK;
+    }
+    static fts_status run(const fts_level *lv, const fts_eigs *eg, double omega, fts_prec prec, const double *r,
+                          double *x, hipStream_t st) {
+        if (prec == FTS_PREC_F64)
+            return eg->kind == FTS_CELL ? go<0, double>(lv, eg, omega, r, x, st) : go<1, double>(lv, eg, omega, r, x, st);
+        if (prec == FTS_PREC_F32)
+            return eg->kind == FTS_CELL ? go<0, float>(lv, eg, omega, r, x, st) : go<1, float>(lv, eg, omega, r, x, st);
+        return fail(FTS_E_UNSUPPORTED, "precision not built");
+    }
+};
+
+fts_status launch_schwarz(const fts_level *lv, const fts_eigs *eg, double omega, fts_prec prec, const double *r,
+                          double *x, hipStream_t stream) {
+    return dispatch<RunSchwarz>(lv->dim, lv->n1, lv, eg, omega, prec, r, x, stream);
+}
+
+template <int D, int N1>
+struct RunTransfer {
+    static fts_status run(const fts_level *c, const fts_level *f, const double *src, double *dst, bool restrict_,
+                          hipStream_t st) {
+        using C = XferCfg<D, N1>;
+        const int64_t blocks = (c->ncells + C::PPB - 1) / C::PPB;
+        if (blocks == 0) return FTS_OK;
+        if (restrict_)
+            k_transfer<D, N1, true><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(c->view, f->view, src, dst);
+        else
+            k_transfer<D, N1, false><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(c->view, f->view, src, dst);
+        return check_launch("k_transfer");
+    }
+};
+
+fts_status launch_restrict(const fts_level *coarse, const fts_level *fine, const double *rf, double *bc,
+                           hipStream_t stream) {
+    return dispatch<RunTransfer>(coarse->dim, coarse->n1, coarse, fine, rf, bc, true, stream);
+}
+
+fts_status launch_prolongate(const fts_level *coarse, const fts_level *fine, const double *ec, double *xf,
+                             hipStream_t stream) {
+    return dispatch<RunTransfer>(coarse->dim, coarse->n1, coarse, fine, ec, xf, false, stream);
+}
+
+template <int D, int N1>
+struct RunAssemble {
+    static fts_status run(const fts_level *lv, double *A, hipStream_t st) {
+        const int64_t N = lv->ndofs;
+        k_assemble_dense<D, N1><<<dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st>>>(lv->view, A, N);
+        return check_launch("k_assemble_dense");
+    }
+};
+
+fts_status launch_assemble_dense(const fts_level *lv, double *A, hipStream_t stream) {
+    return dispatch<RunAssemble>(lv->dim, lv->n1, lv, A, stream);
+}
+
+fts_status launch_fill(double *p, int64_t n, double v, hipStream_t stream) {
+    if (n <= 0) return FTS_OK;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 65536);
+    k_fill<<<dim3((unsigned)blocks), dim3(256), 0, stream>>>(p, n, v);
+    return check_launch("k_fill");
+}
+
+}  // namespace fts

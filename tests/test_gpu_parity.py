@@ -1,0 +1,241 @@
+"""GPU parity: every C-ABI call against the FP64 oracle on the same seeded inputs.
+
+Bar (FP64): ||gpu - oracle||_2 / ||oracle||_2 <= 1e-12 per output vector; the
+oracle assembles the SIPG matrix by quadrature and solves local problems by
+dense LU, the GPU uses sum factorisation and fast diagonalisation.  Meshes are
+rectilinear with log-uniform random widths in [0.25, 4] and cell counts that
+leave ragged tails for the per-block batching of the kernels.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle.mesh import Mesh, uniform_mesh
+from oracle import sipg, onedim, schwarz, multigrid
+from synthetic import loguniform_widths, random_vector, uniform_widths, CONFIGS
+from gpu_util import dev, host, rel, announce
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1910_11239_amd as fts  # noqa: E402
+
+
+def omesh(d, k, ms, seed, gamma_hat=1.0, paired=False):
+    rng = np.random.default_rng(seed)
+    return Mesh(d, k, loguniform_widths(rng, d, ms, 0.25, 4.0, paired=paired), gamma_hat)
+
+
+def glevel(m):
+    return fts.Level(m.dim, m.k, m.widths, m.gamma_hat)
+
+
+OP_CASES = [(2, 1, (5, 3)), (2, 3, (5, 4)), (2, 9, (3, 2)), (3, 1, (4, 3, 5)), (3, 2, (3, 4, 3)),
+            (3, 4, (4, 3, 5)), (3, 7, (3, 2, 3)), (3, 9, (2, 2, 3))]
+
+
+@pytest.mark.parametrize("d,k,ms", OP_CASES)
+def test_operator_and_residual(d, k, ms):
+    announce("operator", d, k, ms)
+    m = omesh(d, k, ms, 11, gamma_hat=1.3)
+    A = sipg.assemble(m)
+    x, b = random_vector(m.ndofs, 1), random_vector(m.ndofs, 0)
+    lv = glevel(m)
+    y = dev(np.zeros(m.ndofs))
+    lv.apply(dev(x), y)
+    assert rel(host(y), A @ x) < TOL
+    r = dev(np.zeros(m.ndofs))
+    lv.residual(dev(b), dev(x), r)
+    assert rel(host(r), b - A @ x) < TOL
+
+
+@pytest.mark.parametrize("kind", ["cell", "vertex"])
+@pytest.mark.parametrize("d,k,ms", [(2, 3, (4, 3)), (3, 2, (3, 4, 3)), (3, 4, (2, 3, 2))])
+def test_setup_1d_eigs(kind, d, k, ms):
+    announce("eigs", kind, d, k, ms)
+    m = omesh(d, k, ms, 12, gamma_hat=1.25)
+    lv = glevel(m)
+    eg = fts.Eigs(lv, kind)
+    ref = onedim.Ref1D(k)
+    for a in range(d):
+        npos = m.ncells[a] if kind == "cell" else m.ncells[a] - 1
+        for s in range(npos):
+            A, M, S, lam = eg.get(a, s)
+            ws, lo, hi = onedim.axis_chain(m, a, s, 1 if kind == "cell" else 2)
+            A0, M0 = onedim.chain_operator(ref, ws, lo, hi, m.gamma_hat)
+            assert np.abs(A - A0).max() <= 1e-13 * np.abs(A0).max()
+            assert np.abs(M - M0).max() <= 1e-14 * np.abs(M0).max()
+            assert np.abs(S.T @ M0 @ S - np.eye(len(lam))).max() < 1e-12
+            assert np.abs(S.T @ A0 @ S - np.diag(lam)).max() < 1e-12 * lam.max()
+            assert np.allclose(lam, sla.eigh(A0, M0, eigvals_only=True), rtol=1e-12, atol=0)
+
+
+SMOOTH_CASES = [("cell", 2, 3, (5, 4)), ("cell", 3, 4, (3, 4, 3)), ("cell", 3, 9, (2, 2, 1)),
+                ("vertex", 2, 3, (5, 4)), ("vertex", 2, 9, (3, 3)), ("vertex", 3, 1, (5, 4, 3)),
+                ("vertex", 3, 2, (4, 3, 5)), ("vertex", 3, 4, (3, 4, 3)), ("vertex", 3, 6, (3, 3, 2))]
+
+
+@pytest.mark.parametrize("kind,d,k,ms", SMOOTH_CASES)
+def test_schwarz_smooth(kind, d, k, ms):
+    announce("smooth", kind, d, k, ms)
+    m = omesh(d, k, ms, 13)
+    A = sipg.assemble(m)
+    subs = schwarz.cell_subdomains(m) if kind == "cell" else schwarz.vertex_patch_subdomains(m)
+    sol = schwarz.ExactLocalSolvers(A, subs, cache=False)
+    x, b = random_vector(m.ndofs, 1), random_vector(m.ndofs, 0)
+    omega = 0.7 if kind == "cell" else 0.3
+    x1 = schwarz.additive_smooth(A, sol, x, b, omega)
+    x2 = schwarz.additive_smooth(A, sol, x1, b, omega)
+    lv = glevel(m)
+    eg = fts.Eigs(lv, kind)
+    xg = dev(x)
+    fts.schwarz_smooth(lv, eg, omega, dev(b), xg, nsweeps=1)
+    assert rel(host(xg), x1) < TOL
+    fts.schwarz_smooth(lv, eg, omega, dev(b), xg, nsweeps=1)
+    assert rel(host(xg), x2) < TOL
+    # local-solver part alone
+    r = b - A @ x
+    xa = dev(np.zeros(m.ndofs))
+    fts.schwarz_apply(lv, eg, 1.0, dev(r), xa)
+    assert rel(host(xa), sol.apply(r)) < TOL
+
+
+@pytest.mark.parametrize("d,k", [(2, 4), (3, 9)])
+def test_one_patch_mesh_is_exact_solve(d, k):
+    """2^d-cell mesh: one vertex patch, omega = 1 gives A^-1 b (largest degree)."""
+    announce("one patch", d, k)
+    m = omesh(d, k, (2,) * d, 14)
+    A = sipg.assemble(m)
+    b = random_vector(m.ndofs, 0)
+    lv = glevel(m)
+    eg = fts.Eigs(lv, "vertex")
+    xg = dev(random_vector(m.ndofs, 1))
+    fts.schwarz_smooth(lv, eg, 1.0, dev(b), xg, nsweeps=1)
+    xs = host(xg)
+    assert np.linalg.norm(A @ xs - b) < 1e-10 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("d,k,ms", [(2, 3, (3, 2)), (3, 2, (2, 3, 2)), (3, 4, (1, 2, 2)), (3, 9, (1, 1, 2))])
+def test_transfers(d, k, ms):
+    announce("transfer", d, k, ms)
+    mc = omesh(d, k, ms, 15)
+    from oracle.mesh import refine
+    mf = refine(mc)
+    P = multigrid.prolongation(mc, mf)
+    lc, lf = glevel(mc), glevel(mf)
+    ec, rf = random_vector(mc.ndofs, 2), random_vector(mf.ndofs, 3)
+    xf0 = random_vector(mf.ndofs, 4)
+    xg = dev(xf0)
+    fts.prolongate_add(lc, lf, dev(ec), xg)
+    assert rel(host(xg), xf0 + P @ ec) < TOL
+    bc = dev(np.zeros(mc.ndofs))
+    fts.restrict(lc, lf, dev(rf), bc)
+    assert rel(host(bc), P.T @ rf) < TOL
+
+
+@pytest.mark.parametrize("kind,d,k,ms,nl", [("vertex", 3, 2, (8, 4, 4), 3), ("cell", 2, 3, (8, 8), 3),
+                                            ("vertex", 2, 4, (8, 4), 3), ("vertex", 3, 4, (4, 4, 4), 2)])
+def test_vcycle(kind, d, k, ms, nl):
+    announce("vcycle", kind, d, k, ms, nl)
+    from oracle.mesh import refine
+    fine = omesh(d, k, tuple(mm >> (nl - 1) for mm in ms), 16)
+    for _ in range(nl - 1):
+        fine = refine(fine)
+    omegas = [0.0] + [0.7 if kind == "cell" else 0.25] * (nl - 1)
+    oh = multigrid.Hierarchy(fine, nl, kind, omegas, m_pre=2, m_post=2, cache=False)
+    gh = fts.Hierarchy(d, k, fine.widths, nl, kind, omegas, fine.gamma_hat, m_pre=2, m_post=2)
+    b, x = random_vector(fine.ndofs, 0), random_vector(fine.ndofs, 1)
+    ref = oh.vcycle(x.copy(), b)
+    xg = dev(x)
+    gh.vcycle(dev(b), xg)
+    assert rel(host(xg), ref) < TOL
+    # preconditioner form: zero initial guess
+    ref0 = oh.vcycle(np.zeros_like(b), b)
+    x0 = dev(np.zeros_like(b))
+    gh.vcycle(dev(b), x0)
+    assert rel(host(x0), ref0) < TOL
+
+
+@pytest.mark.parametrize("d,k,ms", [(3, 2, (2, 2, 2)), (3, 4, (4, 3, 2)), (2, 3, (9, 10))])
+def test_coarse_lu_solve(d, k, ms):
+    """Dense LU of the coarse matrix (several 256-blocks and a ragged last block)."""
+    announce("coarse", d, k, ms)
+    m = omesh(d, k, ms, 17)
+    gh = fts.Hierarchy(d, k, m.widths, 1, "vertex", [0.0], m.gamma_hat)
+    A = sipg.assemble(m).toarray()
+    b = random_vector(m.ndofs, 5)
+    xs = sla.lu_solve(sla.lu_factor(A), b)
+    xg = dev(np.zeros(m.ndofs))
+    gh.coarse_solve(dev(b), xg)
+    assert rel(host(xg), xs) < 1e-12 * max(1.0, np.linalg.cond(A) / 1e3)
+
+
+def test_acs_2d_q3_workload():
+    """The 2-D Q3 16x16 workload in full: one damped cell-smoother step plus one
+    residual, against the oracle."""
+    cfg = CONFIGS["acs_2d_q3"]
+    announce("acs_2d_q3 full")
+    m = Mesh(2, cfg["k"], uniform_widths(2, cfg["m"]), cfg["gamma_hat"])
+    A = sipg.assemble(m)
+    sol = schwarz.ExactLocalSolvers(A, schwarz.cell_subdomains(m), cache=False)
+    b, x0 = random_vector(m.ndofs, cfg["seed_b"]), random_vector(m.ndofs, cfg["seed_x"])
+    x1 = schwarz.additive_smooth(A, sol, x0, b, cfg["omega"])
+    r1 = b - A @ x1
+    lv = glevel(m)
+    eg = fts.Eigs(lv, "cell")
+    xg = dev(x0)
+    fts.schwarz_smooth(lv, eg, cfg["omega"], dev(b), xg, 1)
+    rg = dev(np.zeros(m.ndofs))
+    lv.residual(dev(b), xg, rg)
+    assert rel(host(xg), x1) < TOL
+    assert rel(host(rg), r1) < TOL
+
+
+def test_avs_3d_q4_full_size_sampled():
+    """The 3-D Q4 32^3 fine level at full size, as the benchmark launches it:
+    one residual + vertex-patch sweep; the oracle recomputes sampled cells
+    (corners, faces, interior) exactly from their neighbourhoods."""
+    cfg = CONFIGS["avs_3d_q4"]
+    announce("avs_3d_q4 full-size sampled")
+    m = Mesh(3, cfg["k"], uniform_widths(3, cfg["m"]), cfg["gamma_hat"])
+    b, x0 = random_vector(m.ndofs, cfg["seed_b"]), random_vector(m.ndofs, cfg["seed_x"])
+    lv = glevel(m)
+    eg = fts.Eigs(lv, "vertex")
+    rg = dev(np.zeros(m.ndofs))
+    lv.residual(dev(b), dev(x0), rg)
+    xg = dev(x0)
+    fts.schwarz_smooth(lv, eg, cfg["omega"], dev(b), xg, 1)
+    r_h, x_h = host(rg), host(xg)
+    from oracle import sampled
+    mm = cfg["m"] - 1
+    cells = [(0, 0, 0), (mm, mm, mm), (0, 5, mm), (16, 16, 16), (1, 30, 7), (31, 0, 15), (13, 1, 29)]
+    rs = sampled.residual_cells(m, x0, b, cells)
+    for c, rv in rs.items():
+        assert rel(r_h[m.cell_dofs(c)], rv) < TOL
+    xs = sampled.smooth_cells(m, x0, b, cfg["omega"], "vertex", cells[:5])
+    for c, xv in xs.items():
+        assert rel(x_h[m.cell_dofs(c)], xv) < TOL
+
+
+@pytest.mark.parametrize("d,k,ms", [(3, 4, (4, 3, 3))])
+def test_f32_contractions_error_bound(d, k, ms):
+    """FP32 contractions (FP64 residual and accumulation): error of one sweep
+    against the FP64 oracle within a few FP32 unit roundoffs times the local
+    condition number; reported, not exact."""
+    announce("f32", d, k, ms)
+    m = omesh(d, k, ms, 18)
+    A = sipg.assemble(m)
+    sol = schwarz.ExactLocalSolvers(A, schwarz.vertex_patch_subdomains(m), cache=False)
+    x, b = random_vector(m.ndofs, 1), random_vector(m.ndofs, 0)
+    ref = schwarz.additive_smooth(A, sol, x, b, 0.3)
+    lv = glevel(m)
+    eg = fts.Eigs(lv, "vertex")
+    xg = dev(x)
+    fts.schwarz_smooth(lv, eg, 0.3, dev(b), xg, 1, prec="f32")
+    err = rel(host(xg) - x, ref - x)
+    print("f32 relative error of the correction", err)
+    assert err < 1e-4
