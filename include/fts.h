@@ -163,11 +163,13 @@ fts_status fts_prolongate_add(const fts_level *coarse, const fts_level *fine, co
  * axis are merged; every level but the coarsest needs >= 2 cells per axis for
  * vertex patches), 1-D eigen-data of every level > 0, the level vectors, and
  * the dense FP64 LU factorisation of the coarsest matrix A_0 on the device
- * (no pivoting: A_0 is symmetric positive definite).  omega_per_level and
+ * (no pivoting: A_0 is symmetric positive definite) together with the
+ * inverses of its two triangular factors.  omega_per_level and
  * penalty_per_level: host arrays of nlevels entries, index 0 = coarsest
  * (omega[0] unused); penalty_per_level may be NULL (then the mesh's
- * penalty_factor on every level).  Allocates device memory: ~8 N_0^2 bytes
- * for the coarse factor plus the level vectors. */
+ * penalty_factor on every level).  Allocates device memory: 8 N_0^2 bytes
+ * for the coarse factors (16 N_0^2 transiently during setup) plus the level
+ * vectors. */
 fts_status fts_hierarchy_create(const fts_mesh_desc *finest, int32_t nlevels, fts_patch_kind kind,
                                 const double *omega_per_level, const double *penalty_per_level,
                                 int32_t m_pre, int32_t m_post, fts_hierarchy **out);
@@ -181,7 +183,10 @@ const fts_eigs *fts_hierarchy_eigs(const fts_hierarchy *hier, int32_t l);
  * after the coarse solve on level 0.  b, x: finest-level vectors. */
 fts_status fts_vcycle(fts_hierarchy *hier, fts_prec prec, const double *b, double *x, void *stream);
 
-/* x0 = A_0^-1 b0 by the two triangular solves with the stored LU factors. */
+/* x0 = A_0^-1 b0 with the stored LU factorisation: x0 = inv(U) (inv(L) b0),
+ * the inverse triangular factors being formed once at hierarchy creation, so
+ * each of the two triangular stages is a parallel mat-vec reading its
+ * triangle once (8 N_0^2 bytes per solve).  x0 may alias b0. */
 fts_status fts_coarse_solve(fts_hierarchy *hier, const double *b0, double *x0, void *stream);
 
 #ifdef __cplusplus

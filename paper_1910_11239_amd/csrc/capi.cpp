@@ -5,11 +5,10 @@
 #include "fts_internal.h"
 
 namespace fts {
-fts_status coarse_factor(double *A, int64_t N, double *Linv, double *Uinv, hipStream_t stream);
-fts_status coarse_solve(const double *LU, int64_t N, const double *Linv, const double *Uinv, const double *b,
-                        double *x, hipStream_t stream);
-int coarse_nblk(int64_t N);
-int coarse_nb();
+fts_status coarse_factor(double *A, int64_t N, hipStream_t stream);
+fts_status coarse_solve(const double *F, int64_t N, const double *b, double *x, double *y, double *P,
+                        hipStream_t stream);
+int coarse_ncb(int64_t N);
 }  // namespace fts
 
 using namespace fts;
@@ -22,7 +21,8 @@ struct fts_hierarchy {
     std::vector<fts_level *> levels;  // 0 = coarsest
     std::vector<fts_eigs *> eigs;     // eigs[0] = nullptr
     std::vector<double *> vb, vx, vr;  // per-level vectors (b, x for l < L; r for every l)
-    double *LU = nullptr, *Linv = nullptr, *Uinv = nullptr;
+    double *LU = nullptr;   // inverse triangular factors of A_0 (see coarse.hip)
+    double *cy = nullptr, *cP = nullptr;  // coarse-solve workspaces
     int64_t N0 = 0;
 };
 
@@ -105,8 +105,8 @@ fts_status fts_hierarchy_destroy(fts_hierarchy *h) {
     for (auto *p : h->vx) if (p) hipFree(p);
     for (auto *p : h->vr) if (p) hipFree(p);
     if (h->LU) hipFree(h->LU);
-    if (h->Linv) hipFree(h->Linv);
-    if (h->Uinv) hipFree(h->Uinv);
+    if (h->cy) hipFree(h->cy);
+    if (h->cP) hipFree(h->cP);
     delete h;
     return FTS_OK;
 }
@@ -180,15 +180,14 @@ fts_status fts_hierarchy_create(const fts_mesh_desc *finest, int32_t nlevels, ft
         const fts_level *l0 = h->levels[0];
         const int64_t N = l0->ndofs;
         h->N0 = N;
-        const int nblk = coarse_nblk(N), nb = coarse_nb();
         if (hipMalloc(&h->LU, (size_t)N * N * sizeof(double)) != hipSuccess ||
-            hipMalloc(&h->Linv, (size_t)nblk * nb * nb * sizeof(double)) != hipSuccess ||
-            hipMalloc(&h->Uinv, (size_t)nblk * nb * nb * sizeof(double)) != hipSuccess)
+            hipMalloc(&h->cy, (size_t)N * sizeof(double)) != hipSuccess ||
+            hipMalloc(&h->cP, (size_t)coarse_ncb(N) * N * sizeof(double)) != hipSuccess)
             st = fail(FTS_E_HIP, "hipMalloc of the coarse factor failed");
         hipStream_t s0 = nullptr;
         if (st == FTS_OK) st = launch_fill(h->LU, N * N, 0.0, s0);
         if (st == FTS_OK) st = launch_assemble_dense(l0, h->LU, s0);
-        if (st == FTS_OK) st = coarse_factor(h->LU, N, h->Linv, h->Uinv, s0);
+        if (st == FTS_OK) st = coarse_factor(h->LU, N, s0);
     }
     if (st != FTS_OK) {
         fts_hierarchy_destroy(h);
@@ -207,11 +206,11 @@ const fts_eigs *fts_hierarchy_eigs(const fts_hierarchy *h, int32_t l) {
 
 fts_status fts_coarse_solve(fts_hierarchy *h, const double *b0, double *x0, void *stream) {
     if (!h || !b0 || !x0) return fail(FTS_E_INVAL, "fts_coarse_solve: NULL argument");
-    return coarse_solve(h->LU, h->N0, h->Linv, h->Uinv, b0, x0, S(stream));
+    return coarse_solve(h->LU, h->N0, b0, x0, h->cy, h->cP, S(stream));
 }
 
 static fts_status vcycle_level(fts_hierarchy *h, int l, fts_prec prec, const double *b, double *x, hipStream_t s) {
-    if (l == 0) return coarse_solve(h->LU, h->N0, h->Linv, h->Uinv, b, x, s);
+    if (l == 0) return coarse_solve(h->LU, h->N0, b, x, h->cy, h->cP, s);
     const fts_level *lv = h->levels[l];
     const fts_eigs *eg = h->eigs[l];
     double *r = h->vr[l];

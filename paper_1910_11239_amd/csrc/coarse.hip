@@ -41,130 +41,74 @@ __global__ void __launch_bounds__(1024) k_lu_diag(double *__restrict__ A, int64_
     }
 }
 
-// Inverses of the diagonal blocks: thread c computes column c of inv(L_ss)
-// (unit lower) and inv(U_ss) by substitution.  Stored column-major nb x nb.
-__global__ void __launch_bounds__(kNB) k_tri_inv(const double *__restrict__ LU, int64_t N, double *__restrict__ Linv,
-                                                  double *__restrict__ Uinv) {
-    const int s = blockIdx.x, c = threadIdx.x;
-    const int64_t k0 = (int64_t)s * kNB;
-    const int kb = (int)std::min<int64_t>(kNB, N - k0);
-    double *X = Linv + (size_t)s * kNB * kNB + (size_t)c * kNB;
-    double *Y = Uinv + (size_t)s * kNB * kNB + (size_t)c * kNB;
-    auto at = [&](int i, int j) { return LU[(k0 + i) + (k0 + j) * N]; };
-    if (c >= kb) {
-        for (int i = 0; i < kNB; ++i) X[i] = Y[i] = 0.0;
-        return;
+// Triangular matrix-vector products with the inverted factors stored in the
+// LU buffer: strictly below the diagonal inv(L) (unit diagonal implied), on
+// and above it inv(U).  Tiles of TR rows x TC columns; a workgroup owns one
+// tile, thread = row, columns streamed with coalesced column-major reads and
+// independent partial sums; tile results go to P[column block][row] and are
+// summed in a fixed order by k_tri_reduce (deterministic).
+constexpr int kTR = 256, kTC = 1024, kUnroll = 8;
+
+template <bool LOWER>
+__global__ void __launch_bounds__(kTR) k_tri_partial(const double *__restrict__ F, int64_t N,
+                                                     const double *__restrict__ v, double *__restrict__ P) {
+    __shared__ double vs[kTC];
+    const int64_t r0 = (int64_t)blockIdx.y * kTR, c0 = (int64_t)blockIdx.x * kTC;
+    // tiles outside the triangle do nothing; k_tri_reduce uses the same test
+    if (LOWER ? (c0 >= r0 + kTR) : (c0 + kTC <= r0)) return;
+    for (int j = threadIdx.x; j < kTC; j += kTR) vs[j] = (c0 + j < N) ? v[c0 + j] : 0.0;
+    __syncthreads();
+    const int64_t i = r0 + threadIdx.x;
+    if (i >= N) return;
+    // column range of this row inside the tile
+    int jlo = 0, jhi = (int)std::min<int64_t>(kTC, N - c0);
+    if (LOWER) jhi = (int)std::min<int64_t>(jhi, std::max<int64_t>(0, i - c0));      // j < i
+    else jlo = (int)std::min<int64_t>(kTC, std::max<int64_t>(0, i - c0));           // j >= i
+    const double *col = F + i + c0 * N;
+    double acc[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) acc[u] = 0.0;
+    int j = jlo;
+    for (; j + kUnroll <= jhi; j += kUnroll) {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) acc[u] = fma(col[(int64_t)(j + u) * N], vs[j + u], acc[u]);
     }
-    for (int i = 0; i < c; ++i) X[i] = 0.0;
-    X[c] = 1.0;
-    for (int i = c + 1; i < kb; ++i) {
-        double sum = 0.0;
-        for (int p = c; p < i; ++p) sum += at(i, p) * X[p];
-        X[i] = -sum;
-    }
-    for (int i = kb; i < kNB; ++i) X[i] = 0.0;
-    for (int i = c + 1; i < kNB; ++i) Y[i] = 0.0;
-    Y[c] = 1.0 / at(c, c);
-    for (int i = c - 1; i >= 0; --i) {
-        double sum = 0.0;
-        for (int p = i + 1; p <= c; ++p) sum += at(i, p) * Y[p];
-        Y[i] = -sum / at(i, i);
-    }
+    for (; j < jhi; ++j) acc[0] = fma(col[(int64_t)j * N], vs[j], acc[0]);
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) s += acc[u];
+    P[(int64_t)blockIdx.x * N + i] = s;
 }
 
-// Forward step s: see file comment.
-__global__ void __launch_bounds__(256) k_trsv_fwd(const double *__restrict__ LU, int64_t N,
-                                                   const double *__restrict__ Linv, double *__restrict__ y, int s) {
-    __shared__ double yp[kNB];
-    __shared__ double red[kColGroups][kRowsPerWG];
-    __shared__ double ys[kNB];
-    const int tid = threadIdx.x;
-    const int64_t k0 = (int64_t)s * kNB;
-    const int kb = (int)std::min<int64_t>(kNB, N - k0);
-    const int64_t p0 = k0 - kNB;  // previous column block (valid when s > 0)
-    if (s > 0) {
-        yp[tid] = y[p0 + tid];  // previous block is always full
+template <bool LOWER>
+__global__ void __launch_bounds__(256) k_tri_reduce(const double *__restrict__ P, int64_t N, int ncb,
+                                                    const double *__restrict__ v, double *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= N) return;
+    const int64_t rb0 = (i / kTR) * kTR;  // first row of this row tile
+    double s = LOWER ? v[i] : 0.0;
+    for (int cb = 0; cb < ncb; ++cb) {
+        const int64_t c0 = (int64_t)cb * kTC;
+        const bool live = LOWER ? (c0 < rb0 + kTR) : (c0 + kTC > rb0);
+        if (live) s += P[(int64_t)cb * N + i];
     }
-    __syncthreads();
-    if (blockIdx.x == 0) {
-        double v = 0.0;
-        if (tid < kb) {
-            v = y[k0 + tid];
-            if (s > 0) {
-                const double *col = LU + (k0 + tid) + p0 * N;
-                double acc = 0.0;
-                for (int c = 0; c < kNB; ++c) acc = fma(col[c * N], yp[c], acc);
-                v -= acc;
-            }
-        }
-        ys[tid] = v;
-        __syncthreads();
-        if (tid < kb) {
-            const double *Li = Linv + (size_t)s * kNB * kNB + tid;
-            double out = 0.0;
-            for (int c = 0; c < kb; ++c) out = fma(Li[(size_t)c * kNB], ys[c], out);
-            y[k0 + tid] = out;
-        }
-        return;
-    }
-    // rows below block s, column block s-1
-    const int r = tid % kRowsPerWG, g = tid / kRowsPerWG;
-    const int64_t row = k0 + kNB + (int64_t)(blockIdx.x - 1) * kRowsPerWG + r;
-    double acc = 0.0;
-    if (row < N) {
-        const double *col = LU + row + p0 * N;
-        for (int c = g; c < kNB; c += kColGroups) acc = fma(col[c * N], yp[c], acc);
-    }
-    red[g][r] = acc;
-    __syncthreads();
-    if (g == 0 && row < N) y[row] -= red[0][r] + red[1][r] + red[2][r] + red[3][r];
+    out[i] = s;
 }
 
-// Backward step s (s from the last block down to 0).
-__global__ void __launch_bounds__(256) k_trsv_bwd(const double *__restrict__ LU, int64_t N,
-                                                   const double *__restrict__ Uinv, double *__restrict__ x, int s,
-                                                   int nblk) {
-    __shared__ double xn[kNB];
-    __shared__ double red[kColGroups][kRowsPerWG];
-    __shared__ double xs[kNB];
-    const int tid = threadIdx.x;
-    const int64_t k0 = (int64_t)s * kNB;
-    const int kb = (int)std::min<int64_t>(kNB, N - k0);
-    const int64_t n0 = k0 + kNB;  // next column block
-    const int kn = s + 1 < nblk ? (int)std::min<int64_t>(kNB, N - n0) : 0;
-    xn[tid] = tid < kn ? x[n0 + tid] : 0.0;
-    __syncthreads();
-    if (blockIdx.x == 0) {
-        double v = 0.0;
-        if (tid < kb) {
-            v = x[k0 + tid];
-            if (kn > 0) {
-                const double *col = LU + (k0 + tid) + n0 * N;
-                double acc = 0.0;
-                for (int c = 0; c < kn; ++c) acc = fma(col[c * N], xn[c], acc);
-                v -= acc;
-            }
-        }
-        xs[tid] = v;
-        __syncthreads();
-        if (tid < kb) {
-            const double *Ui = Uinv + (size_t)s * kNB * kNB + tid;
-            double out = 0.0;
-            for (int c = 0; c < kb; ++c) out = fma(Ui[(size_t)c * kNB], xs[c], out);
-            x[k0 + tid] = out;
-        }
-        return;
+__global__ void k_set_identity(double *__restrict__ X, int64_t N) {
+    const int64_t nn = N * N;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (int64_t)gridDim.x * blockDim.x)
+        X[e] = (e % N == e / N) ? 1.0 : 0.0;
+}
+
+// LU[i + jN] <- X[i + jN] on the strict lower (LOWER) or upper-with-diagonal part.
+template <bool LOWER>
+__global__ void k_pack_triangle(double *__restrict__ LU, const double *__restrict__ X, int64_t N) {
+    const int64_t nn = N * N;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e % N, j = e / N;
+        if (LOWER ? (i > j) : (i <= j)) LU[e] = X[e];
     }
-    const int r = tid % kRowsPerWG, g = tid / kRowsPerWG;
-    const int64_t row = (int64_t)(blockIdx.x - 1) * kRowsPerWG + r;
-    double acc = 0.0;
-    if (row < k0) {
-        const double *col = LU + row + n0 * N;
-        for (int c = g; c < kn; c += kColGroups) acc = fma(col[c * N], xn[c], acc);
-    }
-    red[g][r] = acc;
-    __syncthreads();
-    if (g == 0 && row < k0) x[row] -= red[0][r] + red[1][r] + red[2][r] + red[3][r];
 }
 
 static fts_status rb_check(rocblas_status st, const char *what) {
@@ -173,9 +117,10 @@ static fts_status rb_check(rocblas_status st, const char *what) {
     return FTS_OK;
 }
 
-// Factor A (N x N, column-major, lda = N) in place and form the diagonal-block
-// inverses.  Linv, Uinv: nblk * NB * NB doubles each.
-fts_status coarse_factor(double *A, int64_t N, double *Linv, double *Uinv, hipStream_t stream) {
+// Factor A (N x N, column-major, lda = N) in place, then replace the factors
+// by their inverses: strict lower part inv(L), upper part inv(U).  Needs one
+// temporary N x N buffer (allocated and freed here, setup only).
+fts_status coarse_factor(double *A, int64_t N, hipStream_t stream) {
     if (N > 2147483647LL) return fail(FTS_E_SIZE, "coarse matrix too large for the BLAS interface");
     rocblas_handle h = nullptr;
     if (rocblas_create_handle(&h) != rocblas_status_success) return fail(FTS_E_HIP, "rocblas_create_handle failed");
@@ -206,36 +151,45 @@ fts_status coarse_factor(double *A, int64_t N, double *Linv, double *Uinv, hipSt
                                     (int)N, A12, (int)N, &one, A22, (int)N),
                       "dgemm (trailing update)");
     }
-    if (st == FTS_OK) {
-        const int nblk = (int)((N + kNB - 1) / kNB);
-        k_tri_inv<<<nblk, kNB, 0, stream>>>(A, N, Linv, Uinv);
-        if (hipGetLastError() != hipSuccess) st = fail(FTS_E_HIP, "k_tri_inv launch failed");
+    double *X = nullptr;
+    if (st == FTS_OK && hipMalloc(&X, (size_t)N * N * sizeof(double)) != hipSuccess)
+        st = fail(FTS_E_HIP, "hipMalloc of the inversion buffer failed");
+    const int grid = (int)std::min<int64_t>((N * N + 255) / 256, 1 << 20);
+    for (int pass = 0; pass < 2 && st == FTS_OK; ++pass) {
+        const bool lower = pass == 0;
+        k_set_identity<<<grid, 256, 0, stream>>>(X, N);
+        st = rb_check(rocblas_dtrsm(h, rocblas_side_left, lower ? rocblas_fill_lower : rocblas_fill_upper,
+                                    rocblas_operation_none, lower ? rocblas_diagonal_unit : rocblas_diagonal_non_unit,
+                                    (int)N, (int)N, &one, A, (int)N, X, (int)N),
+                      "dtrsm (triangular inverse)");
+        if (st != FTS_OK) break;
+        if (lower) k_pack_triangle<true><<<grid, 256, 0, stream>>>(A, X, N);
+        else k_pack_triangle<false><<<grid, 256, 0, stream>>>(A, X, N);
+        if (hipGetLastError() != hipSuccess) st = fail(FTS_E_HIP, "packing of the inverse factors failed");
     }
-    if (st == FTS_OK && hipStreamSynchronize(stream) != hipSuccess) st = fail(FTS_E_HIP, "coarse factorisation failed");
+    if (hipStreamSynchronize(stream) != hipSuccess && st == FTS_OK) st = fail(FTS_E_HIP, "coarse factorisation failed");
+    if (X) hipFree(X);
     rocblas_destroy_handle(h);
     return st;
 }
 
-int coarse_nblk(int64_t N) { return (int)((N + kNB - 1) / kNB); }
-int coarse_nb() { return kNB; }
+int coarse_ncb(int64_t N) { return (int)((N + kTC - 1) / kTC); }
 
-// x = A^-1 b with the stored factors; x may alias b.
-fts_status coarse_solve(const double *LU, int64_t N, const double *Linv, const double *Uinv, const double *b,
-                        double *x, hipStream_t stream) {
-    const int nblk = coarse_nblk(N);
-    if (x != b) FTS_HIP_CHECK(hipMemcpyAsync(x, b, N * sizeof(double), hipMemcpyDeviceToDevice, stream));
-    for (int s = 0; s < nblk; ++s) {
-        const int64_t below = s == 0 ? 0 : std::max<int64_t>(0, N - (int64_t)(s + 1) * kNB);
-        const int grid = 1 + (int)((below + kRowsPerWG - 1) / kRowsPerWG);
-        k_trsv_fwd<<<grid, 256, 0, stream>>>(LU, N, Linv, x, s);
-    }
-    for (int s = nblk - 1; s >= 0; --s) {
-        const int64_t above = s + 1 < nblk ? (int64_t)s * kNB : 0;
-        const int grid = 1 + (int)((above + kRowsPerWG - 1) / kRowsPerWG);
-        k_trsv_bwd<<<grid, 256, 0, stream>>>(LU, N, Uinv, x, s, nblk);
-    }
+// x = inv(U) (inv(L) b): two tiled triangular mat-vecs, each reading its
+// triangle of the stored inverse factors once.  P: workspace of ncb * N
+// doubles; y: workspace of N doubles.  x must not alias y or P.
+fts_status coarse_solve(const double *F, int64_t N, const double *b, double *x, double *y, double *P,
+                        hipStream_t stream) {
+    const int ncb = coarse_ncb(N);
+    const int nrb = (int)((N + kTR - 1) / kTR);
+    const dim3 grid(ncb, nrb);
+    const int rgrid = (int)((N + 255) / 256);
+    k_tri_partial<true><<<grid, kTR, 0, stream>>>(F, N, b, P);
+    k_tri_reduce<true><<<rgrid, 256, 0, stream>>>(P, N, ncb, b, y);
+    k_tri_partial<false><<<grid, kTR, 0, stream>>>(F, N, y, P);
+    k_tri_reduce<false><<<rgrid, 256, 0, stream>>>(P, N, ncb, y, x);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "coarse triangular solves");
+    if (e != hipSuccess) return hip_fail(e, "coarse triangular mat-vecs");
     return FTS_OK;
 }
 

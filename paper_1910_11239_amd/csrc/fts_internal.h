@@ -65,8 +65,10 @@ struct LevelView {
 struct EigView {
     int count[3];             // positions per axis
     const double *S[3];       // per axis: count blocks of n x n, row-major [i][m]
+    const double *ST[3];      // transposes, row-major [m][i]
     const double *lam[3];     // per axis: count blocks of n
     const float *S32[3];
+    const float *ST32[3];
     const float *lam32[3];
 };
 

@@ -203,43 +203,69 @@ struct SubGrid {
 };
 
 template <typename T>
-__device__ __forceinline__ const T *eig_S(const EigView &e, int a);
+struct EigTab;
 template <>
-__device__ __forceinline__ const double *eig_S<double>(const EigView &e, int a) { return e.S[a]; }
+struct EigTab<double> {
+    static __device__ __forceinline__ const double *S(const EigView &e, int a) { return e.S[a]; }
+    static __device__ __forceinline__ const double *ST(const EigView &e, int a) { return e.ST[a]; }
+    static __device__ __forceinline__ const double *L(const EigView &e, int a) { return e.lam[a]; }
+};
 template <>
-__device__ __forceinline__ const float *eig_S<float>(const EigView &e, int a) { return e.S32[a]; }
-template <typename T>
-__device__ __forceinline__ const T *eig_L(const EigView &e, int a);
-template <>
-__device__ __forceinline__ const double *eig_L<double>(const EigView &e, int a) { return e.lam[a]; }
-template <>
-__device__ __forceinline__ const float *eig_L<float>(const EigView &e, int a) { return e.lam32[a]; }
+struct EigTab<float> {
+    static __device__ __forceinline__ const float *S(const EigView &e, int a) { return e.S32[a]; }
+    static __device__ __forceinline__ const float *ST(const EigView &e, int a) { return e.ST32[a]; }
+    static __device__ __forceinline__ const float *L(const EigView &e, int a) { return e.lam32[a]; }
+};
 
-template <int D, int N, bool FWD, typename T>
-__device__ __forceinline__ void contract_line(T *Tq, int a, int l, const T *__restrict__ S) {
+// Read-only tables addressed uniformly by a whole workgroup are read through
+// the constant address space, so the compiler issues scalar loads and the
+// FMAs take their matrix operand from scalar registers.
+template <typename T>
+using cptr = const T __attribute__((address_space(4))) *;
+template <typename T>
+__device__ __forceinline__ cptr<T> uniform_table(const T *p) {
+    return (cptr<T>)(p);
+}
+
+// out[o] = sum_j Mat[o][j] in[j] on one line (Mat row-major, rows contiguous).
+template <int N, typename T, typename P>
+__device__ __forceinline__ void matvec_regs(const T *in, T *out, P Mat) {
+#pragma unroll
+    for (int o = 0; o < N; ++o) {
+        T s = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) s = fma((T)Mat[o * N + j], in[j], s);
+        out[o] = s;
+    }
+}
+
+template <int D, int N, typename T, typename P>
+__device__ __forceinline__ void contract_line(T *Tq, int a, int l, P Mat) {
     const int base = line_base<D, N>(a, l), st = line_stride<N>(a);
     T in[N], out[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) in[i] = Tq[base + i * st];
-    if constexpr (FWD) {
-#pragma unroll
-        for (int m = 0; m < N; ++m) {
-            T s = 0;
-#pragma unroll
-            for (int i = 0; i < N; ++i) s = fma(S[i * N + m], in[i], s);
-            out[m] = s;
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < N; ++i) {
-            T s = 0;
-#pragma unroll
-            for (int m = 0; m < N; ++m) s = fma(S[i * N + m], in[m], s);
-            out[i] = s;
-        }
-    }
+    matvec_regs<N>(in, out, Mat);
 #pragma unroll
     for (int i = 0; i < N; ++i) Tq[base + i * st] = out[i];
+}
+
+// Last axis: forward transform, eigenvalue scaling and backward transform of
+// the same line, kept in registers.  lam_rest = lambda of the other axes at
+// this line's fixed mode indices.
+template <int D, int N, typename T, typename P, typename Q>
+__device__ __forceinline__ void last_axis_solve(T *Tq, int l, P ST, P S, Q lam_last, T lam_rest, T omega) {
+    constexpr int a = D - 1;
+    const int base = line_base<D, N>(a, l), st = line_stride<N>(a);
+    T in[N], mid[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) in[i] = Tq[base + i * st];
+    matvec_regs<N>(in, mid, ST);
+#pragma unroll
+    for (int m = 0; m < N; ++m) mid[m] = mid[m] * (omega / (lam_rest + (T)lam_last[m]));
+    matvec_regs<N>(mid, in, S);
+#pragma unroll
+    for (int i = 0; i < N; ++i) Tq[base + i * st] = in[i];
 }
 
 template <int D, int N1, int KIND, typename T>
@@ -280,32 +306,62 @@ k_schwarz(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r, doub
     __syncthreads();
     const int64_t s = s0 + q;
     const bool act = (q < PPB) && (s < sg.nsub);
-    int pos[3] = {0, 0, 0};
-    if (act) position(s, pos);
     T *Tq = Ts + q * NT;
-    // forward transform (S^T along every axis)
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        if (act) contract_line<D, N, true, T>(Tq, a, l, eig_S<T>(e, a) + (size_t)pos[a] * N * N);
+    const T om = (T)omega;
+    // mode indices of this thread's line along the last axis (fixed coordinates of the other axes)
+    const int ml0 = l % N, ml1 = (l / N) % N;
+    if constexpr (PPB == 1) {
+        // one subdomain per workgroup: every table address is uniform
+        int pos[3];
+        position(s0, pos);
+        for (int a = 0; a < 3; ++a) pos[a] = __builtin_amdgcn_readfirstlane(pos[a]);
+        const int nn = N * N;
+        if (act) contract_line<D, N, T>(Tq, 0, l, uniform_table(EigTab<T>::ST(e, 0) + (size_t)pos[0] * nn));
         __syncthreads();
-    }
-    // eigenvalue scaling omega / (lambda_x + lambda_y (+ lambda_z))
-    for (int p = t; p < PPB * NT; p += TH) {
-        const int qq = p / NT, mm = p % NT;
-        const int64_t ss = s0 + qq;
-        if (ss >= sg.nsub) continue;
-        int ps[3];
-        position(ss, ps);
-        const int m0 = mm % N, m1 = (mm / N) % N, m2 = D == 3 ? mm / (N * N) : 0;
-        T lam = eig_L<T>(e, 0)[(size_t)ps[0] * N + m0] + eig_L<T>(e, 1)[(size_t)ps[1] * N + m1];
-        if constexpr (D == 3) lam += eig_L<T>(e, 2)[(size_t)ps[2] * N + m2];
-        Ts[p] = Ts[p] * ((T)omega / lam);
-    }
-    __syncthreads();
-    // backward transform (S along every axis)
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        if (act) contract_line<D, N, false, T>(Tq, a, l, eig_S<T>(e, a) + (size_t)pos[a] * N * N);
+        if constexpr (D == 3) {
+            if (act) contract_line<D, N, T>(Tq, 1, l, uniform_table(EigTab<T>::ST(e, 1) + (size_t)pos[1] * nn));
+            __syncthreads();
+        }
+        if (act) {
+            constexpr int a = D - 1;
+            cptr<T> L0 = uniform_table(EigTab<T>::L(e, 0) + (size_t)pos[0] * N);
+            T lr = (T)L0[ml0];
+            if constexpr (D == 3) lr += (T)uniform_table(EigTab<T>::L(e, 1) + (size_t)pos[1] * N)[ml1];
+            last_axis_solve<D, N, T>(Tq, l, uniform_table(EigTab<T>::ST(e, a) + (size_t)pos[a] * nn),
+                                     uniform_table(EigTab<T>::S(e, a) + (size_t)pos[a] * nn),
+                                     uniform_table(EigTab<T>::L(e, a) + (size_t)pos[a] * N), lr, om);
+        }
+        __syncthreads();
+        if constexpr (D == 3) {
+            if (act) contract_line<D, N, T>(Tq, 1, l, uniform_table(EigTab<T>::S(e, 1) + (size_t)pos[1] * nn));
+            __syncthreads();
+        }
+        if (act) contract_line<D, N, T>(Tq, 0, l, uniform_table(EigTab<T>::S(e, 0) + (size_t)pos[0] * nn));
+        __syncthreads();
+    } else {
+        int pos[3] = {0, 0, 0};
+        if (act) position(s, pos);
+        const int nn = N * N;
+        if (act) contract_line<D, N, T>(Tq, 0, l, EigTab<T>::ST(e, 0) + (size_t)pos[0] * nn);
+        __syncthreads();
+        if constexpr (D == 3) {
+            if (act) contract_line<D, N, T>(Tq, 1, l, EigTab<T>::ST(e, 1) + (size_t)pos[1] * nn);
+            __syncthreads();
+        }
+        if (act) {
+            constexpr int a = D - 1;
+            T lr = EigTab<T>::L(e, 0)[(size_t)pos[0] * N + ml0];
+            if constexpr (D == 3) lr += EigTab<T>::L(e, 1)[(size_t)pos[1] * N + ml1];
+            last_axis_solve<D, N, T>(Tq, l, EigTab<T>::ST(e, a) + (size_t)pos[a] * nn,
+                                     EigTab<T>::S(e, a) + (size_t)pos[a] * nn,
+                                     EigTab<T>::L(e, a) + (size_t)pos[a] * N, lr, om);
+        }
+        __syncthreads();
+        if constexpr (D == 3) {
+            if (act) contract_line<D, N, T>(Tq, 1, l, EigTab<T>::S(e, 1) + (size_t)pos[1] * nn);
+            __syncthreads();
+        }
+        if (act) contract_line<D, N, T>(Tq, 0, l, EigTab<T>::S(e, 0) + (size_t)pos[0] * nn);
         __syncthreads();
     }
     // scatter-add R_j^T

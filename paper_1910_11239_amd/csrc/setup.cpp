@@ -453,7 +453,7 @@ fts_status fts_setup_1d_eigs(const fts_level *lv, fts_patch_kind kind, fts_eigs 
                 return st;
             }
         }
-        total += eg->S[a].size() + eg->lam[a].size();
+        total += 2 * eg->S[a].size() + eg->lam[a].size();
     }
     if (hipMalloc(&eg->d_tab, std::max<size_t>(total, 1) * sizeof(double)) != hipSuccess ||
         hipMalloc(&eg->d_tab32, std::max<size_t>(total, 1) * sizeof(float)) != hipSuccess) {
@@ -469,6 +469,11 @@ fts_status fts_setup_1d_eigs(const fts_level *lv, fts_patch_kind kind, fts_eigs 
         eg->view.S[a] = eg->d_tab + off;
         eg->view.S32[a] = eg->d_tab32 + off;
         for (double v : eg->S[a]) host[off++] = v;
+        eg->view.ST[a] = eg->d_tab + off;
+        eg->view.ST32[a] = eg->d_tab32 + off;
+        for (int s = 0; s < eg->count[a]; ++s)
+            for (int m = 0; m < n; ++m)
+                for (int i = 0; i < n; ++i) host[off++] = eg->S[a][(size_t)s * nn + i * n + m];
         eg->view.lam[a] = eg->d_tab + off;
         eg->view.lam32[a] = eg->d_tab32 + off;
         for (double v : eg->lam[a]) host[off++] = v;
