@@ -118,6 +118,21 @@ fts_status fts_eigs_get(const fts_eigs *eigs, int32_t axis, int32_t index, doubl
 /* n of the subdomains (k+1 or 2(k+1)). */
 int32_t fts_eigs_n(const fts_eigs *eigs);
 
+/* How overlapping vertex patches are summed (both give the additive operator
+ * of eq. additiveschwarz; they differ only in rounding order):
+ *   FTS_SCHEDULE_STAGED  (default) one launch over all patches writes each
+ *        patch's correction to a staging buffer owned by the eigs handle
+ *        (2^d (k+1)^d doubles per patch, allocated by fts_setup_1d_eigs);
+ *        a second launch adds, per cell, the corrections of its 2^d patches
+ *        in a fixed order.  Deterministic.  Calls using one eigs handle must
+ *        be ordered on one stream (they share the staging buffer).
+ *   FTS_SCHEDULE_COLORED 2^d launches, one per parquet color (patches of one
+ *        color share no cell, Sec. 2.3), each adding into x directly.
+ * Ignored for cells (disjoint, one launch). */
+#define FTS_SCHEDULE_STAGED 0
+#define FTS_SCHEDULE_COLORED 1
+fts_status fts_eigs_set_schedule(fts_eigs *eigs, int32_t schedule);
+
 /* ---- a4: matrix-free SIPG operator --------------------------------------- */
 
 /* y = A x, the SIPG matrix of eq. (bfsipg) on this level (x, y: ndofs FP64,
@@ -136,9 +151,9 @@ size_t fts_smooth_ws_bytes(const fts_level *level);
  * damping of eq. (additiveschwarz):
  *     r = b - A x;   x <- x + omega * sum_j R_j^T A_j^-1 R_j r
  * with A_j^-1 = (S x..x S) diag(1/Lambda) (S x..x S)^T (eq. fastinverse).
- * Overlapping vertex patches are processed in 2^d parquet colors (patches of
- * one color share no cell), which is the same operator as the uncolored sum
- * (Sec. 2.3).  ws: device workspace of fts_smooth_ws_bytes bytes. */
+ * Overlapping vertex patches are summed as set by fts_eigs_set_schedule
+ * (default: staged, deterministic).  ws: device workspace of
+ * fts_smooth_ws_bytes bytes. */
 fts_status fts_schwarz_smooth(const fts_level *level, const fts_eigs *eigs, double omega,
                               fts_prec prec, const double *b, double *x, int32_t nsweeps, void *ws,
                               size_t ws_bytes, void *stream);

@@ -41,6 +41,7 @@ _SIGS = {
     "fts_eigs_destroy": (_I32, [_VP]),
     "fts_eigs_get": (_I32, [_VP, _I32, _I32, _VP, _VP, _VP, _VP]),
     "fts_eigs_n": (_I32, [_VP]),
+    "fts_eigs_set_schedule": (_I32, [_VP, _I32]),
     "fts_apply_operator": (_I32, [_VP, _VP, _VP, _VP]),
     "fts_residual": (_I32, [_VP, _VP, _VP, _VP, _VP]),
     "fts_smooth_ws_bytes": (_SZ, [_VP]),
@@ -162,6 +163,11 @@ class Eigs:
         if getattr(self, "_owner", None) is None and getattr(self, "_h", None) is not None and _lib is not None:
             _lib.fts_eigs_destroy(self._h)
             self._h = None
+
+    def set_schedule(self, schedule):
+        """'staged' (default, deterministic) or 'colored' (2^d parquet colors)."""
+        _check(lib().fts_eigs_set_schedule(self._h, {"staged": 0, "colored": 1}[schedule]),
+               "fts_eigs_set_schedule")
 
     def get(self, axis, index):
         n = self.n

@@ -44,40 +44,86 @@ __global__ void __launch_bounds__(1024) k_lu_diag(double *__restrict__ A, int64_
 // Triangular matrix-vector products with the inverted factors stored in the
 // LU buffer: strictly below the diagonal inv(L) (unit diagonal implied), on
 // and above it inv(U).  Tiles of TR rows x TC columns; a workgroup owns one
-// tile, thread = row, columns streamed with coalesced column-major reads and
-// independent partial sums; tile results go to P[column block][row] and are
-// summed in a fixed order by k_tri_reduce (deterministic).
-constexpr int kTR = 256, kTC = 1024, kUnroll = 8;
+// tile, each thread two consecutive rows (16-byte loads), columns streamed
+// with non-temporal coalesced column-major reads and independent partial
+// sums; tile results go to P[column block][row] and are summed in a fixed
+// order by k_tri_reduce (deterministic).  A tile is live when it holds an
+// entry of the triangle; both kernels use the same column-block range.
+constexpr int kTR = 512, kTC = 1024, kUnroll = 8;
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ int live_lo(bool lower, int64_t rb0) { return lower ? 0 : (int)(rb0 / kTC); }
+__device__ __forceinline__ int live_hi(bool lower, int64_t rb0, int ncb) {
+    return lower ? (int)std::min<int64_t>(ncb, (rb0 + kTR + kTC - 1) / kTC) : ncb;
+}
 
 template <bool LOWER>
-__global__ void __launch_bounds__(kTR) k_tri_partial(const double *__restrict__ F, int64_t N,
+__global__ void __launch_bounds__(256) k_tri_partial(const double *__restrict__ F, int64_t N,
                                                      const double *__restrict__ v, double *__restrict__ P) {
     __shared__ double vs[kTC];
-    const int64_t r0 = (int64_t)blockIdx.y * kTR, c0 = (int64_t)blockIdx.x * kTC;
-    // tiles outside the triangle do nothing; k_tri_reduce uses the same test
-    if (LOWER ? (c0 >= r0 + kTR) : (c0 + kTC <= r0)) return;
-    for (int j = threadIdx.x; j < kTC; j += kTR) vs[j] = (c0 + j < N) ? v[c0 + j] : 0.0;
+    const int64_t r0 = (int64_t)blockIdx.y * kTR;
+    const int cb = blockIdx.x;
+    if (cb < live_lo(LOWER, r0) || cb >= live_hi(LOWER, r0, gridDim.x)) return;
+    const int64_t c0 = (int64_t)cb * kTC;
+    for (int j = threadIdx.x; j < kTC; j += 256) vs[j] = (c0 + j < N) ? v[c0 + j] : 0.0;
     __syncthreads();
-    const int64_t i = r0 + threadIdx.x;
+    const int64_t i = r0 + 2 * threadIdx.x;  // rows i, i+1
     if (i >= N) return;
-    // column range of this row inside the tile
-    int jlo = 0, jhi = (int)std::min<int64_t>(kTC, N - c0);
-    if (LOWER) jhi = (int)std::min<int64_t>(jhi, std::max<int64_t>(0, i - c0));      // j < i
-    else jlo = (int)std::min<int64_t>(kTC, std::max<int64_t>(0, i - c0));           // j >= i
-    const double *col = F + i + c0 * N;
-    double acc[kUnroll];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) acc[u] = 0.0;
-    int j = jlo;
-    for (; j + kUnroll <= jhi; j += kUnroll) {
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) acc[u] = fma(col[(int64_t)(j + u) * N], vs[j + u], acc[u]);
+    const bool pair = (i + 1 < N) && ((N & 1) == 0);  // 16-byte aligned row pairs
+    // Column range (tile-relative) shared by rows i and i+1, and the one column
+    // jd = i - c0 that belongs to only one of them (row i+1 for the strict
+    // lower part, row i for the upper part including the diagonal).
+    const int ncol = (int)std::min<int64_t>(kTC, N - c0);
+    int jlo, jhi;
+    if (LOWER) {
+        jlo = 0;
+        jhi = (int)std::min<int64_t>(ncol, std::max<int64_t>(0, i - c0));
+    } else {
+        jlo = (int)std::min<int64_t>(ncol, std::max<int64_t>(0, i + 1 - c0));
+        jhi = ncol;
     }
-    for (; j < jhi; ++j) acc[0] = fma(col[(int64_t)j * N], vs[j], acc[0]);
-    double s = 0.0;
+    const int64_t jd = i - c0;
+    const bool extra = jd >= 0 && jd < ncol;
+    double a0[kUnroll], a1[kUnroll];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) s += acc[u];
-    P[(int64_t)blockIdx.x * N + i] = s;
+    for (int u = 0; u < kUnroll; ++u) a0[u] = a1[u] = 0.0;
+    const double *col = F + i + c0 * N;
+    if (pair) {
+        int j = jlo;
+        for (; j + kUnroll <= jhi; j += kUnroll) {
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const dvec2 m = __builtin_nontemporal_load((const dvec2 *)(col + (int64_t)(j + u) * N));
+                a0[u] = fma(m.x, vs[j + u], a0[u]);
+                a1[u] = fma(m.y, vs[j + u], a1[u]);
+            }
+        }
+        for (; j < jhi; ++j) {
+            const dvec2 m = *(const dvec2 *)(col + (int64_t)j * N);
+            a0[0] = fma(m.x, vs[j], a0[0]);
+            a1[0] = fma(m.y, vs[j], a1[0]);
+        }
+    } else {
+        for (int j = jlo; j < jhi; ++j) {
+            a0[0] = fma(col[(int64_t)j * N], vs[j], a0[0]);
+            if (i + 1 < N) a1[0] = fma(col[(int64_t)j * N + 1], vs[j], a1[0]);
+        }
+    }
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+        s0 += a0[u];
+        s1 += a1[u];
+    }
+    if (extra) {
+        if (LOWER) {
+            if (i + 1 < N) s1 = fma(col[jd * N + 1], vs[jd], s1);
+        } else {
+            s0 = fma(col[jd * N], vs[jd], s0);
+        }
+    }
+    P[(int64_t)cb * N + i] = s0;
+    if (i + 1 < N) P[(int64_t)cb * N + i + 1] = s1;
 }
 
 template <bool LOWER>
@@ -86,13 +132,15 @@ __global__ void __launch_bounds__(256) k_tri_reduce(const double *__restrict__ P
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= N) return;
     const int64_t rb0 = (i / kTR) * kTR;  // first row of this row tile
-    double s = LOWER ? v[i] : 0.0;
-    for (int cb = 0; cb < ncb; ++cb) {
-        const int64_t c0 = (int64_t)cb * kTC;
-        const bool live = LOWER ? (c0 < rb0 + kTR) : (c0 + kTC > rb0);
-        if (live) s += P[(int64_t)cb * N + i];
+    const int lo = live_lo(LOWER, rb0), hi = live_hi(LOWER, rb0, ncb);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int cb = lo;
+    for (; cb + 4 <= hi; cb += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] += P[(int64_t)(cb + u) * N + i];
     }
-    out[i] = s;
+    for (; cb < hi; ++cb) acc[0] += P[(int64_t)cb * N + i];
+    out[i] = (LOWER ? v[i] : 0.0) + ((acc[0] + acc[1]) + (acc[2] + acc[3]));
 }
 
 __global__ void k_set_identity(double *__restrict__ X, int64_t N) {
@@ -184,9 +232,9 @@ fts_status coarse_solve(const double *F, int64_t N, const double *b, double *x, 
     const int nrb = (int)((N + kTR - 1) / kTR);
     const dim3 grid(ncb, nrb);
     const int rgrid = (int)((N + 255) / 256);
-    k_tri_partial<true><<<grid, kTR, 0, stream>>>(F, N, b, P);
+    k_tri_partial<true><<<grid, 256, 0, stream>>>(F, N, b, P);
     k_tri_reduce<true><<<rgrid, 256, 0, stream>>>(P, N, ncb, b, y);
-    k_tri_partial<false><<<grid, kTR, 0, stream>>>(F, N, y, P);
+    k_tri_partial<false><<<grid, 256, 0, stream>>>(F, N, y, P);
     k_tri_reduce<false><<<rgrid, 256, 0, stream>>>(P, N, ncb, y, x);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "coarse triangular mat-vecs");

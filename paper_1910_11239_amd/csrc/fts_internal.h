@@ -93,6 +93,8 @@ struct fts_eigs {
     std::vector<double> A[3], M[3], S[3], lam[3];
     double *d_tab = nullptr;
     float *d_tab32 = nullptr;
+    double *d_stage = nullptr;  // staged corrections of all vertex patches (one per cell of each)
+    int schedule = FTS_SCHEDULE_STAGED;
     fts::EigView view{};
 };
 

@@ -268,9 +268,14 @@ __device__ __forceinline__ void last_axis_solve(T *Tq, int l, P ST, P S, Q lam_l
     for (int i = 0; i < N; ++i) Tq[base + i * st] = in[i];
 }
 
-template <int D, int N1, int KIND, typename T>
+// STAGE = false: x += correction (the subdomains of one launch must not share
+// cells: cells, or one parquet color of vertex patches).  STAGE = true: the
+// correction of subdomain s is written to W[s][cell of the subdomain][DoF]
+// and k_patch_gather adds the contributions to x in a fixed order.
+template <int D, int N1, int KIND, typename T, bool STAGE>
 __global__ void __launch_bounds__((SwCfg<D, N1, KIND>::THREADS))
-k_schwarz(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r, double *__restrict__ x, double omega) {
+k_schwarz(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r, double *__restrict__ x,
+          double *__restrict__ W, double omega) {
     using C = SwCfg<D, N1, KIND>;
     constexpr int N = C::N, NT = C::NT, NC1 = C::NC1, NSC = C::NSC, LINES = C::LINES, PPB = C::PPB,
                   TH = C::THREADS;
@@ -375,9 +380,39 @@ k_schwarz(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r, doub
         const int64_t cell = (ps[0] + o0) + (ps[1] + o1) * cs1 + (D == 3 ? (ps[2] + o2) * cs2 : 0);
         const int i0 = i % N1, i1 = (i / N1) % N1, i2 = D == 3 ? i / (N1 * N1) : 0;
         const int lds = (o0 * N1 + i0) + (o1 * N1 + i1) * N + (D == 3 ? (o2 * N1 + i2) * N * N : 0);
-        const int64_t gi = cell * NC1 + i;
-        x[gi] = x[gi] + (double)Ts[qq * NT + lds];
+        if constexpr (STAGE) {
+            W[ss * (NSC * NC1) + rem] = (double)Ts[qq * NT + lds];
+        } else {
+            const int64_t gi = cell * NC1 + i;
+            x[gi] = x[gi] + (double)Ts[qq * NT + lds];
+        }
     }
+}
+
+// x += sum over the 2^d vertex patches containing each cell of that patch's
+// staged correction (Sec. 2.3, eq. additiveschwarz), in the fixed order of the
+// cell's position inside the patch: deterministic, no write conflicts.
+template <int D, int N1>
+__global__ void __launch_bounds__(256) k_patch_gather(LevelView g, const double *__restrict__ W, double *__restrict__ x) {
+    constexpr int NC1 = ipow(N1, D), NSC = 1 << D;
+    const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (gid >= g.ncells * NC1) return;
+    const int64_t cell = gid / NC1;
+    const int i = (int)(gid % NC1);
+    int c[3];
+    cell_coords(cell, g.m, c);
+    const int cnt0 = g.m[0] - 1, cnt1 = g.m[1] - 1;
+    double acc = 0.0;
+#pragma unroll
+    for (int o = 0; o < NSC; ++o) {
+        const int a0 = c[0] - (o & 1), a1 = c[1] - ((o >> 1) & 1), a2 = D == 3 ? c[2] - ((o >> 2) & 1) : 0;
+        const bool in = a0 >= 0 && a0 < cnt0 && a1 >= 0 && a1 < cnt1 && (D == 2 || (a2 >= 0 && a2 < g.m[2] - 1));
+        if (in) {
+            const int64_t sidx = a0 + (int64_t)cnt0 * (a1 + (int64_t)cnt1 * a2);
+            acc += W[sidx * (NSC * NC1) + o * NC1 + i];
+        }
+    }
+    x[gid] += acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -568,10 +603,11 @@ struct RunSchwarz {
     static fts_status go(const fts_level *lv, const fts_eigs *eg, double omega, const double *r, double *x,
                          hipStream_t st) {
         using C = SwCfg<D, N1, KIND>;
-        const int ncolor = KIND ? (1 << D) : 1;
+        const bool staged = KIND == 1 && eg->schedule == FTS_SCHEDULE_STAGED;
+        const int ncolor = (KIND && !staged) ? (1 << D) : 1;
         for (int color = 0; color < ncolor; ++color) {
             SubGrid sg{};
-            sg.step = KIND ? 2 : 1;
+            sg.step = (KIND && !staged) ? 2 : 1;
             sg.nsub = 1;
             for (int a = 0; a < 3; ++a) {
                 if (a >= D) {
@@ -580,16 +616,25 @@ struct RunSchwarz {
                     continue;
                 }
                 const int npos = eg->count[a];  // positions along the axis
-                sg.first[a] = KIND ? ((color >> a) & 1) : 0;
+                sg.first[a] = (KIND && !staged) ? ((color >> a) & 1) : 0;
                 sg.cnt[a] = npos > sg.first[a] ? (npos - sg.first[a] + sg.step - 1) / sg.step : 0;
                 sg.nsub *= sg.cnt[a];
             }
             if (sg.nsub == 0) continue;
             const int64_t blocks = (sg.nsub + C::PPB - 1) / C::PPB;
-            k_schwarz<D, N1, KIND, T><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(lv->view, eg->view, sg,
-                                                                                       r, x, omega);
+            if (staged)
+                k_schwarz<D, N1, KIND, T, true><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(
+                    lv->view, eg->view, sg, r, x, eg->d_stage, omega);
+            else
+                k_schwarz<D, N1, KIND, T, false><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(
+                    lv->view, eg->view, sg, r, x, nullptr, omega);
             fts_status s = check_launch("k_schwarz");
             if (s != FTS_OK) return s;
+        }
+        if (staged) {
+            const int64_t n = lv->ndofs;
+            k_patch_gather<D, N1><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(lv->view, eg->d_stage, x);
+            return check_launch("k_patch_gather");
         }
         return FTS_OK;
     }

@@ -486,7 +486,26 @@ fts_status fts_setup_1d_eigs(const fts_level *lv, fts_patch_kind kind, fts_eigs 
         delete eg;
         return fail(FTS_E_HIP, "upload of eigen tables failed");
     }
+    if (kind == FTS_VERTEX_PATCH) {
+        int64_t nsub = 1;
+        for (int a = 0; a < lv->dim; ++a) nsub *= eg->count[a];
+        const size_t bytes = (size_t)nsub * (1u << lv->dim) * (lv->ndofs / lv->ncells) * sizeof(double);
+        if (hipMalloc(&eg->d_stage, std::max<size_t>(bytes, 8)) != hipSuccess) {
+            hipFree(eg->d_tab);
+            hipFree(eg->d_tab32);
+            delete eg;
+            return fail(FTS_E_HIP, "hipMalloc of the patch staging buffer failed");
+        }
+    }
     *out = eg;
+    return FTS_OK;
+}
+
+fts_status fts_eigs_set_schedule(fts_eigs *eigs, int32_t schedule) {
+    if (!eigs) return fail(FTS_E_INVAL, "fts_eigs_set_schedule: NULL handle");
+    if (schedule != FTS_SCHEDULE_STAGED && schedule != FTS_SCHEDULE_COLORED)
+        return fail(FTS_E_INVAL, "fts_eigs_set_schedule: unknown schedule");
+    eigs->schedule = schedule;
     return FTS_OK;
 }
 
@@ -494,6 +513,7 @@ fts_status fts_eigs_destroy(fts_eigs *eigs) {
     if (!eigs) return FTS_OK;
     if (eigs->d_tab) hipFree(eigs->d_tab);
     if (eigs->d_tab32) hipFree(eigs->d_tab32);
+    if (eigs->d_stage) hipFree(eigs->d_stage);
     delete eigs;
     return FTS_OK;
 }

@@ -92,16 +92,32 @@ def test_schwarz_smooth(kind, d, k, ms):
     x2 = schwarz.additive_smooth(A, sol, x1, b, omega)
     lv = glevel(m)
     eg = fts.Eigs(lv, kind)
-    xg = dev(x)
-    fts.schwarz_smooth(lv, eg, omega, dev(b), xg, nsweeps=1)
-    assert rel(host(xg), x1) < TOL
-    fts.schwarz_smooth(lv, eg, omega, dev(b), xg, nsweeps=1)
-    assert rel(host(xg), x2) < TOL
-    # local-solver part alone
     r = b - A @ x
-    xa = dev(np.zeros(m.ndofs))
-    fts.schwarz_apply(lv, eg, 1.0, dev(r), xa)
-    assert rel(host(xa), sol.apply(r)) < TOL
+    for schedule in (("staged", "colored") if kind == "vertex" else ("staged",)):
+        eg.set_schedule(schedule)
+        xg = dev(x)
+        fts.schwarz_smooth(lv, eg, omega, dev(b), xg, nsweeps=1)
+        assert rel(host(xg), x1) < TOL, schedule
+        fts.schwarz_smooth(lv, eg, omega, dev(b), xg, nsweeps=1)
+        assert rel(host(xg), x2) < TOL, schedule
+        # local-solver part alone
+        xa = dev(np.zeros(m.ndofs))
+        fts.schwarz_apply(lv, eg, 1.0, dev(r), xa)
+        assert rel(host(xa), sol.apply(r)) < TOL, schedule
+
+
+def test_staged_schedule_is_deterministic():
+    """Repeated staged applications give bit-identical results."""
+    m = omesh(3, 3, (5, 4, 3), 19)
+    lv = glevel(m)
+    eg = fts.Eigs(lv, "vertex")
+    r = dev(random_vector(m.ndofs, 2))
+    outs = []
+    for _ in range(3):
+        xa = dev(np.zeros(m.ndofs))
+        fts.schwarz_apply(lv, eg, 0.5, r, xa)
+        outs.append(host(xa))
+    assert all(np.array_equal(outs[0], o) for o in outs[1:])
 
 
 @pytest.mark.parametrize("d,k", [(2, 4), (3, 9)])
