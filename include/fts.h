@@ -198,6 +198,24 @@ const fts_eigs *fts_hierarchy_eigs(const fts_hierarchy *hier, int32_t l);
  * after the coarse solve on level 0.  b, x: finest-level vectors. */
 fts_status fts_vcycle(fts_hierarchy *hier, fts_prec prec, const double *b, double *x, void *stream);
 
+/* ---- a11: outer FP64 CG --------------------------------------------------- */
+
+/* Workspace bytes of fts_pcg: 5 finest-level vectors plus reduction partials. */
+size_t fts_pcg_ws_bytes(const fts_hierarchy *hier);
+
+/* Conjugate gradients on the finest level preconditioned by one V-cycle
+ * z = MG_L(0, r) (Sec. 2.4), FP64 vectors, residuals and reductions, with the
+ * flexible (Polak-Ribiere) beta so that a preconditioner with reduced-
+ * precision contractions (prec != FTS_PREC_F64) is tolerated.  x holds the
+ * initial guess on entry and the iterate on exit; iterates until
+ * ||b - A x|| <= rtol ||b|| or maxit steps.  Dot products are deterministic
+ * two-stage reductions; each is read back to the host (the only
+ * synchronisations).  history: NULL or maxit+1 doubles of ||r_i||/||b||.
+ * iters, relres: NULL or outputs. */
+fts_status fts_pcg(fts_hierarchy *hier, fts_prec prec, const double *b, double *x, double rtol,
+                   int32_t maxit, void *ws, size_t ws_bytes, int32_t *iters, double *relres,
+                   double *history, void *stream);
+
 /* x0 = A_0^-1 b0 with the stored LU factorisation: x0 = inv(U) (inv(L) b0),
  * the inverse triangular factors being formed once at hierarchy creation, so
  * each of the two triangular stages is a parallel mat-vec reading its

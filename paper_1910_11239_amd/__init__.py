@@ -55,6 +55,8 @@ _SIGS = {
     "fts_hierarchy_eigs": (_VP, [_VP, _I32]),
     "fts_vcycle": (_I32, [_VP, _I32, _VP, _VP, _VP]),
     "fts_coarse_solve": (_I32, [_VP, _VP, _VP, _VP]),
+    "fts_pcg_ws_bytes": (_SZ, [_VP]),
+    "fts_pcg": (_I32, [_VP, _I32, _VP, _VP, _D, _I32, _VP, _SZ, _VP, _VP, _VP, _VP]),
 }
 
 
@@ -240,6 +242,21 @@ class Hierarchy:
         _check(lib().fts_vcycle(self._h, PREC[prec], _ptr(b, self.ndofs, "b"), _ptr(x, self.ndofs, "x"),
                                 _stream()), "fts_vcycle")
         return x
+
+    def pcg(self, b, x, rtol=1e-10, maxit=200, prec="f64", ws=None):
+        """Flexible PCG with one V-cycle as preconditioner; x: initial guess, updated.
+        Returns (iterations, final relative residual, history of relative residuals)."""
+        import torch
+        nbytes = int(lib().fts_pcg_ws_bytes(self._h))
+        if ws is None:
+            ws = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=x.device)
+        hist = np.zeros(maxit + 1)
+        it = ctypes.c_int32()
+        rel = ctypes.c_double()
+        _check(lib().fts_pcg(self._h, PREC[prec], _ptr(b, self.ndofs, "b"), _ptr(x, self.ndofs, "x"),
+                             float(rtol), int(maxit), _ptr(ws, None, "ws"), ws.numel() * 8, ctypes.byref(it),
+                             ctypes.byref(rel), hist.ctypes.data, _stream()), "fts_pcg")
+        return it.value, rel.value, hist[:it.value + 1]
 
     def coarse_solve(self, b0, x0):
         n0 = self.levels[0].ndofs

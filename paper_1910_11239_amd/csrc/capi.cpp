@@ -24,6 +24,7 @@ struct fts_hierarchy {
     double *LU = nullptr;   // inverse triangular factors of A_0 (see coarse.hip)
     double *cy = nullptr, *cP = nullptr;  // coarse-solve workspaces
     int64_t N0 = 0;
+    double *host_scalars = nullptr;       // pinned readback buffer of the CG reductions
 };
 
 static hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
@@ -107,6 +108,7 @@ fts_status fts_hierarchy_destroy(fts_hierarchy *h) {
     if (h->LU) hipFree(h->LU);
     if (h->cy) hipFree(h->cy);
     if (h->cP) hipFree(h->cP);
+    if (h->host_scalars) hipHostFree(h->host_scalars);
     delete h;
     return FTS_OK;
 }
@@ -188,6 +190,8 @@ fts_status fts_hierarchy_create(const fts_mesh_desc *finest, int32_t nlevels, ft
         if (st == FTS_OK) st = launch_fill(h->LU, N * N, 0.0, s0);
         if (st == FTS_OK) st = launch_assemble_dense(l0, h->LU, s0);
         if (st == FTS_OK) st = coarse_factor(h->LU, N, s0);
+        if (st == FTS_OK && hipHostMalloc(&h->host_scalars, 4 * sizeof(double)) != hipSuccess)
+            st = fail(FTS_E_HIP, "hipHostMalloc of the readback buffer failed");
     }
     if (st != FTS_OK) {
         fts_hierarchy_destroy(h);
@@ -229,6 +233,81 @@ static fts_status vcycle_level(fts_hierarchy *h, int l, fts_prec prec, const dou
         if (st == FTS_OK) st = launch_schwarz(lv, eg, h->omega[l], prec, r, x, s);
     }
     return st;
+}
+
+size_t fts_pcg_ws_bytes(const fts_hierarchy *h) {
+    if (!h) return 0;
+    return (size_t)(5 * h->levels.back()->ndofs + 2 * red_partials() + 2) * sizeof(double);
+}
+
+static fts_status readback(fts_hierarchy *h, const double *dev, hipStream_t s, double *out2) {
+    FTS_HIP_CHECK(hipMemcpyAsync(h->host_scalars, dev, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    FTS_HIP_CHECK(hipStreamSynchronize(s));
+    out2[0] = h->host_scalars[0];
+    out2[1] = h->host_scalars[1];
+    return FTS_OK;
+}
+
+fts_status fts_pcg(fts_hierarchy *h, fts_prec prec, const double *b, double *x, double rtol, int32_t maxit,
+                   void *ws, size_t ws_bytes, int32_t *iters, double *relres, double *history, void *stream) {
+    if (!h || !b || !x || !ws) return fail(FTS_E_INVAL, "fts_pcg: NULL argument");
+    if (ws_bytes < fts_pcg_ws_bytes(h)) return fail(FTS_E_SIZE, "fts_pcg: workspace too small");
+    if (!(rtol >= 0.0) || maxit < 0) return fail(FTS_E_INVAL, "fts_pcg: invalid rtol or maxit");
+    hipStream_t s = S(stream);
+    const fts_level *lv = h->levels.back();
+    const int64_t N = lv->ndofs;
+    double *r = static_cast<double *>(ws), *z = r + N, *zo = z + N, *p = zo + N, *q = p + N;
+    double *part = q + N, *dout = part + 2 * red_partials();
+    double v[2];
+    fts_status st;
+#define FTS_TRY(expr)        \
+    do {                     \
+        st = (expr);         \
+        if (st != FTS_OK) return st; \
+    } while (0)
+    FTS_TRY(launch_operator(lv, x, b, r, true, s));
+    FTS_TRY(launch_dot2(b, b, nullptr, N, part, dout, s));
+    FTS_TRY(readback(h, dout, s, v));
+    const double bb = v[0];
+    FTS_TRY(launch_dot2(r, r, nullptr, N, part, dout, s));
+    FTS_TRY(readback(h, dout, s, v));
+    double rel = bb > 0.0 ? std::sqrt(v[0] / bb) : 0.0;
+    if (history) history[0] = rel;
+    int it = 0;
+    if (rel > rtol && maxit > 0) {
+        FTS_TRY(launch_fill(z, N, 0.0, s));
+        FTS_TRY(vcycle_level(h, h->nlevels - 1, prec, r, z, s));
+        FTS_HIP_CHECK(hipMemcpyAsync(p, z, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        FTS_TRY(launch_dot2(r, z, nullptr, N, part, dout, s));
+        FTS_TRY(readback(h, dout, s, v));
+        double rz = v[0];
+        while (it < maxit) {
+            FTS_TRY(launch_operator(lv, p, nullptr, q, false, s));
+            FTS_TRY(launch_dot2(p, q, nullptr, N, part, dout, s));
+            FTS_TRY(readback(h, dout, s, v));
+            const double alpha = rz / v[0];
+            FTS_TRY(launch_cg_update(x, r, p, q, alpha, N, s));
+            FTS_TRY(launch_dot2(r, r, nullptr, N, part, dout, s));
+            FTS_TRY(readback(h, dout, s, v));
+            rel = std::sqrt(v[0] / bb);
+            ++it;
+            if (history) history[it] = rel;
+            if (!(rel > rtol)) break;
+            std::swap(z, zo);
+            FTS_TRY(launch_fill(z, N, 0.0, s));
+            FTS_TRY(vcycle_level(h, h->nlevels - 1, prec, r, z, s));
+            FTS_TRY(launch_dot2(r, z, zo, N, part, dout, s));
+            FTS_TRY(readback(h, dout, s, v));
+            // flexible (Polak-Ribiere) update: beta = r.(z - z_old) / rz_old
+            const double beta = (v[0] - v[1]) / rz;
+            rz = v[0];
+            FTS_TRY(launch_xpby(p, z, beta, N, s));
+        }
+    }
+#undef FTS_TRY
+    if (iters) *iters = it;
+    if (relres) *relres = rel;
+    return FTS_OK;
 }
 
 fts_status fts_vcycle(fts_hierarchy *h, fts_prec prec, const double *b, double *x, void *stream) {

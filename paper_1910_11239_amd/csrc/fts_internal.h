@@ -110,4 +110,11 @@ fts_status launch_prolongate(const fts_level *coarse, const fts_level *fine, con
                              double *xf, hipStream_t stream);
 fts_status launch_assemble_dense(const fts_level *lv, double *A, hipStream_t stream);
 fts_status launch_fill(double *p, int64_t n, double v, hipStream_t stream);
+// out[0] = x.y, out[1] = x.z (z may be NULL); part: 2 * red_partials() doubles
+fts_status launch_dot2(const double *x, const double *y, const double *z, int64_t n, double *part, double *out,
+                       hipStream_t stream);
+fts_status launch_cg_update(double *x, double *r, const double *p, const double *q, double alpha, int64_t n,
+                            hipStream_t stream);
+fts_status launch_xpby(double *p, const double *z, double beta, int64_t n, hipStream_t stream);
+int red_partials();
 }  // namespace fts

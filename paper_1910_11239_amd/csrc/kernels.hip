@@ -699,3 +699,97 @@ fts_status launch_fill(double *p, int64_t n, double v, hipStream_t stream) {
 }
 
 }  // namespace fts
+
+namespace fts {
+
+// ---------------------------------------------------------------------------
+// Level-1 vector kernels for the outer CG.  Dot products are deterministic
+// two-stage reductions: fixed grid of kRedBlocks partial sums, then one block
+// sums the partials in a fixed order.
+constexpr int kRedBlocks = 1024;
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += sh[i];
+    return s;
+}
+
+// partial[b][0] = sum x.y, partial[b][1] = sum x.z (z may be null)
+__global__ void __launch_bounds__(256) k_dot2_partial(const double *__restrict__ x, const double *__restrict__ y,
+                                                      const double *__restrict__ z, int64_t n, double *__restrict__ part) {
+    __shared__ double sh[8];
+    double a = 0.0, c = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        a = fma(x[i], y[i], a);
+        if (z) c = fma(x[i], z[i], c);
+    }
+    const double sa = block_sum(a, sh);
+    __syncthreads();
+    const double sc = block_sum(c, sh);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sa;
+        part[2 * blockIdx.x + 1] = sc;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_dot2_final(const double *__restrict__ part, int nb, double *__restrict__ out) {
+    __shared__ double sh[8];
+    double a = 0.0, c = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) {
+        a += part[2 * i];
+        c += part[2 * i + 1];
+    }
+    const double sa = block_sum(a, sh);
+    __syncthreads();
+    const double sc = block_sum(c, sh);
+    if (threadIdx.x == 0) {
+        out[0] = sa;
+        out[1] = sc;
+    }
+}
+
+// x += alpha p; r -= alpha q
+__global__ void __launch_bounds__(256) k_cg_update(double *__restrict__ x, double *__restrict__ r,
+                                                   const double *__restrict__ p, const double *__restrict__ q,
+                                                   double alpha, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        x[i] = fma(alpha, p[i], x[i]);
+        r[i] = fma(-alpha, q[i], r[i]);
+    }
+}
+
+// p = z + beta p
+__global__ void __launch_bounds__(256) k_xpby(double *__restrict__ p, const double *__restrict__ z, double beta,
+                                              int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        p[i] = fma(beta, p[i], z[i]);
+}
+
+static unsigned vec_grid(int64_t n) { return (unsigned)std::min<int64_t>((n + 255) / 256, 8192); }
+
+fts_status launch_dot2(const double *x, const double *y, const double *z, int64_t n, double *part, double *out,
+                       hipStream_t st) {
+    k_dot2_partial<<<kRedBlocks, 256, 0, st>>>(x, y, z, n, part);
+    k_dot2_final<<<1, 256, 0, st>>>(part, kRedBlocks, out);
+    return check_launch("dot products");
+}
+
+fts_status launch_cg_update(double *x, double *r, const double *p, const double *q, double alpha, int64_t n,
+                            hipStream_t st) {
+    k_cg_update<<<vec_grid(n), 256, 0, st>>>(x, r, p, q, alpha, n);
+    return check_launch("k_cg_update");
+}
+
+fts_status launch_xpby(double *p, const double *z, double beta, int64_t n, hipStream_t st) {
+    k_xpby<<<vec_grid(n), 256, 0, st>>>(p, z, beta, n);
+    return check_launch("k_xpby");
+}
+
+int red_partials() { return kRedBlocks; }
+
+}  // namespace fts

@@ -255,3 +255,49 @@ def test_f32_contractions_error_bound(d, k, ms):
     err = rel(host(xg) - x, ref - x)
     print("f32 relative error of the correction", err)
     assert err < 1e-4
+
+
+@pytest.mark.parametrize("kind,d,k,ms,nl,omega", [("vertex", 3, 3, (8, 8, 8), 3, 0.125), ("cell", 2, 4, (16, 16), 4, 0.7)])
+def test_pcg(kind, d, k, ms, nl, omega):
+    """FP64 flexible PCG with the V-cycle preconditioner: residual history of
+    the first iterations equals the oracle's (same algorithm), the iteration
+    counts agree and the final iterate solves the system (checked against the
+    exact discrete solution by global fast diagonalisation)."""
+    announce("pcg", kind, d, k, ms, nl)
+    from oracle import krylov
+    from oracle.mesh import refine
+    fine = uniform_mesh(d, k, tuple(mm >> (nl - 1) for mm in ms))
+    for _ in range(nl - 1):
+        fine = refine(fine)
+    omegas = [0.0] + [omega] * (nl - 1)
+    oh = multigrid.Hierarchy(fine, nl, kind, omegas, m_pre=2, m_post=2)
+    b = random_vector(fine.ndofs, 0)
+    xo, ito, histo = krylov.pcg(oh.A[-1], b, lambda r: oh.vcycle(np.zeros_like(r), r), rtol=1e-10, flexible=True)
+    gh = fts.Hierarchy(d, k, fine.widths, nl, kind, omegas, fine.gamma_hat, m_pre=2, m_post=2)
+    xg = dev(np.zeros(fine.ndofs))
+    it, relres, hist = gh.pcg(dev(b), xg, rtol=1e-10, maxit=200)
+    print("pcg iterations gpu", it, "oracle", ito, "final", relres)
+    assert abs(it - ito) <= 1 and relres <= 1e-10
+    nh = min(6, len(hist), len(histo))
+    assert np.allclose(hist[:nh], histo[:nh], rtol=1e-9, atol=0)
+    xs = onedim.global_fastdiag_solve(fine, b)
+    assert rel(host(xg), xs) < 1e-8
+    assert rel(host(xg), xo) < 1e-8
+
+
+def test_pcg_mixed_precision_reaches_fp64_residual():
+    """FP32 contractions in the preconditioner, FP64 CG: reaches 1e-10 with at
+    most a few more iterations than the FP64 preconditioner."""
+    announce("pcg mixed")
+    from oracle.mesh import refine
+    fine = refine(refine(uniform_mesh(3, 3, 2)))
+    omegas = [0.0, 0.125, 0.125]
+    gh = fts.Hierarchy(3, 3, fine.widths, 3, "vertex", omegas, 1.0, 2, 2)
+    b = dev(random_vector(fine.ndofs, 0))
+    x64 = dev(np.zeros(fine.ndofs))
+    it64, r64, _ = gh.pcg(b, x64, rtol=1e-10)
+    x32 = dev(np.zeros(fine.ndofs))
+    it32, r32, _ = gh.pcg(b, x32, rtol=1e-10, prec="f32")
+    print("iterations f64", it64, "f32", it32)
+    assert r32 <= 1e-10 and it32 <= it64 + 3
+    assert rel(host(x32), host(x64)) < 1e-8
