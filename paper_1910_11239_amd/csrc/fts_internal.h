@@ -70,6 +70,12 @@ struct EigView {
     const float *S32[3];
     const float *ST32[3];
     const float *lam32[3];
+    // 16-bit operands of the MFMA path (n <= 16, padded to 16 x 16): for each
+    // axis and position the forward matrix F[o][k] = S[k][o] / s and the
+    // backward matrix B[o][k] = S[o][k] / s with s = max |S|; FP16 and BF16
+    // bit patterns.  mscale = s, lmin = smallest eigenvalue (FP32).
+    const uint16_t *Ff16[3], *Bf16[3], *Fbf16[3], *Bbf16[3];
+    const float *mscale[3], *lmin[3];
 };
 
 }  // namespace fts
@@ -94,6 +100,7 @@ struct fts_eigs {
     double *d_tab = nullptr;
     float *d_tab32 = nullptr;
     double *d_stage = nullptr;  // staged corrections of all vertex patches (one per cell of each)
+    void *d_mfma = nullptr;     // 16-bit MFMA tables (n <= 16 only)
     int schedule = FTS_SCHEDULE_STAGED;
     fts::EigView view{};
 };

@@ -416,6 +416,209 @@ __global__ void __launch_bounds__(256) k_patch_gather(LevelView g, const double 
 }
 
 // ---------------------------------------------------------------------------
+// Local solves with 16-bit MFMA contractions (3-D, n <= 16, tensor padded to
+// 16^3).  Each 1-D contraction of 16 lines is one v_mfma_f32_16x16x16 in the
+// orientation Out^T = Mat * In^T: lane l holds Mat[l%16][4(l/16)+v] (A), the
+// line l%16 at indices 4(l/16)+v (B) and receives the output line l%16 at
+// indices 4(l/16)+v (D).  Because D has the layout of B, the last axis runs
+// forward transform, eigenvalue scaling and backward transform in registers.
+// Range control (FP16): the gathered residual is divided by its max-norm, the
+// 1-D matrices are stored divided by s = max|S|, and the eigenvalue scaling
+// uses Lambda_min / Lambda(m) <= 1; the factor
+// F = |r|_max * omega * (s_x s_y s_z)^2 / Lambda_min is applied in FP64 when
+// the correction is written.  Accumulation in FP32, update of x in FP64.
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kPy = 20, kPz = 324;  // padded LDS pitches (conflict-free strided reads)
+
+__device__ __forceinline__ int mline_base(int a, int L) {
+    const int u = L & 15, v = L >> 4;
+    if (a == 0) return u * kPy + v * kPz;
+    if (a == 1) return u + v * kPz;
+    return u + v * kPy;
+}
+__device__ __forceinline__ int mline_stride(int a) { return a == 0 ? 1 : (a == 1 ? kPy : kPz); }
+
+__device__ __forceinline__ short f32_to_bf16(float f) {
+    unsigned u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
+template <int BF>
+struct Mfma16;
+template <>
+struct Mfma16<0> {
+    typedef f16x4 vec;
+    static __device__ __forceinline__ vec pack(const float *v) {
+        vec r;
+        r[0] = (_Float16)v[0];
+        r[1] = (_Float16)v[1];
+        r[2] = (_Float16)v[2];
+        r[3] = (_Float16)v[3];
+        return r;
+    }
+    static __device__ __forceinline__ vec load(const uint16_t *p) {
+        const uint2 u = *reinterpret_cast<const uint2 *>(p);
+        vec r;
+        __builtin_memcpy(&r, &u, 8);
+        return r;
+    }
+    static __device__ __forceinline__ f32x4 mma(vec a, vec b) {
+        const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+        return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, z, 0, 0, 0);
+    }
+};
+template <>
+struct Mfma16<1> {
+    typedef s16x4 vec;
+    static __device__ __forceinline__ vec pack(const float *v) {
+        vec r;
+        r[0] = f32_to_bf16(v[0]);
+        r[1] = f32_to_bf16(v[1]);
+        r[2] = f32_to_bf16(v[2]);
+        r[3] = f32_to_bf16(v[3]);
+        return r;
+    }
+    static __device__ __forceinline__ vec load(const uint16_t *p) {
+        const uint2 u = *reinterpret_cast<const uint2 *>(p);
+        vec r;
+        __builtin_memcpy(&r, &u, 8);
+        return r;
+    }
+    static __device__ __forceinline__ f32x4 mma(vec a, vec b) {
+        const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, z, 0, 0, 0);
+    }
+};
+
+template <int N1, int KIND, int BF, bool STAGE>
+__global__ void __launch_bounds__(256)
+k_schwarz_mfma(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r, double *__restrict__ x,
+               double *__restrict__ W, double omega) {
+    using M = Mfma16<BF>;
+    constexpr int D = 3;
+    constexpr int N = KIND ? 2 * N1 : N1;
+    static_assert(N <= 16, "MFMA path needs n <= 16");
+    constexpr int NC1 = N1 * N1 * N1, NSC = KIND ? 8 : 1;
+    __shared__ float Ts[16 * kPz];
+    __shared__ float wmax[4];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int64_t s = blockIdx.x;
+    int pos[3];
+    {
+        const int j0 = (int)(s % sg.cnt[0]);
+        const int64_t rr = s / sg.cnt[0];
+        const int j1 = (int)(rr % sg.cnt[1]);
+        const int j2 = (int)(rr / sg.cnt[1]);
+        pos[0] = __builtin_amdgcn_readfirstlane(sg.first[0] + sg.step * j0);
+        pos[1] = __builtin_amdgcn_readfirstlane(sg.first[1] + sg.step * j1);
+        pos[2] = __builtin_amdgcn_readfirstlane(sg.first[2] + sg.step * j2);
+    }
+    const int64_t cs1 = g.m[0], cs2 = (int64_t)g.m[0] * g.m[1];
+    if (N < 16)
+        for (int p = t; p < 16 * kPz; p += 256) Ts[p] = 0.f;
+    __syncthreads();
+    float amax = 0.f;
+    for (int p = t; p < NSC * NC1; p += 256) {
+        const int sc = p / NC1, i = p % NC1;
+        const int o0 = sc & 1, o1 = (sc >> 1) & 1, o2 = (sc >> 2) & 1;
+        const int64_t cell = (pos[0] + o0) + (pos[1] + o1) * cs1 + (pos[2] + o2) * cs2;
+        const int i0 = i % N1, i1 = (i / N1) % N1, i2 = i / (N1 * N1);
+        const float v = (float)r[cell * NC1 + i];
+        Ts[(o0 * N1 + i0) + (o1 * N1 + i1) * kPy + (o2 * N1 + i2) * kPz] = v;
+        amax = fmaxf(amax, fabsf(v));
+    }
+    for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off, 64));
+    if (lane == 0) wmax[wv] = amax;
+    __syncthreads();
+    const float rmax = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+    const float inv = rmax > 0.f ? 1.f / rmax : 0.f;
+    const int c4 = 4 * (lane >> 4), j = lane & 15;
+    auto mat = [&](const uint16_t *const *tab, int a) {
+        return M::load(tab[a] + (size_t)pos[a] * 256 + j * 16 + c4);
+    };
+    const uint16_t *const *Ftab = BF ? e.Fbf16 : e.Ff16;
+    const uint16_t *const *Btab = BF ? e.Bbf16 : e.Bf16;
+    // forward transforms along x and y
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const typename M::vec A = mat(Ftab, a);
+        const int st = mline_stride(a);
+        for (int tt = wv; tt < 16; tt += 4) {
+            const int base = mline_base(a, 16 * tt + j) + c4 * st;
+            float v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = Ts[base + q * st] * (a == 0 ? inv : 1.f);
+            const f32x4 d = M::mma(A, M::pack(v));
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Ts[base + q * st] = d[q];
+        }
+        __syncthreads();
+    }
+    // z: forward, scaling Lambda_min / Lambda(m), backward, in registers
+    {
+        const typename M::vec Af = mat(Ftab, 2), Ab = mat(Btab, 2);
+        const float *lx = e.lam32[0] + (size_t)pos[0] * N, *ly = e.lam32[1] + (size_t)pos[1] * N;
+        const float *lz = e.lam32[2] + (size_t)pos[2] * N;
+        const float lmin = e.lmin[0][pos[0]] + e.lmin[1][pos[1]] + e.lmin[2][pos[2]];
+        for (int tt = wv; tt < 16; tt += 4) {
+            const int base = mline_base(2, 16 * tt + j) + c4 * kPz;
+            float v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = Ts[base + q * kPz];
+            f32x4 d = M::mma(Af, M::pack(v));
+            const int mx = j, my = tt;  // this line's fixed mode indices
+            const bool inxy = mx < N && my < N;
+            const float lxy = inxy ? lx[mx] + ly[my] : 0.f;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int mz = c4 + q;
+                v[q] = (inxy && mz < N) ? d[q] * (lmin / (lxy + lz[mz])) : 0.f;
+            }
+            d = M::mma(Ab, M::pack(v));
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Ts[base + q * kPz] = d[q];
+        }
+        __syncthreads();
+    }
+    // backward transforms along y and x
+#pragma unroll
+    for (int a = 1; a >= 0; --a) {
+        const typename M::vec A = mat(Btab, a);
+        const int st = mline_stride(a);
+        for (int tt = wv; tt < 16; tt += 4) {
+            const int base = mline_base(a, 16 * tt + j) + c4 * st;
+            float v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q] = Ts[base + q * st];
+            const f32x4 d = M::mma(A, M::pack(v));
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Ts[base + q * st] = d[q];
+        }
+        __syncthreads();
+    }
+    const double sx = e.mscale[0][pos[0]], sy = e.mscale[1][pos[1]], sz = e.mscale[2][pos[2]];
+    const double lmin = (double)e.lmin[0][pos[0]] + e.lmin[1][pos[1]] + e.lmin[2][pos[2]];
+    const double F = (double)rmax * omega * (sx * sy * sz) * (sx * sy * sz) / lmin;
+    for (int p = t; p < NSC * NC1; p += 256) {
+        const int sc = p / NC1, i = p % NC1;
+        const int o0 = sc & 1, o1 = (sc >> 1) & 1, o2 = (sc >> 2) & 1;
+        const int i0 = i % N1, i1 = (i / N1) % N1, i2 = i / (N1 * N1);
+        const double v = F * (double)Ts[(o0 * N1 + i0) + (o1 * N1 + i1) * kPy + (o2 * N1 + i2) * kPz];
+        if constexpr (STAGE) {
+            W[s * (NSC * NC1) + p] = v;
+        } else {
+            const int64_t cell = (pos[0] + o0) + (pos[1] + o1) * cs1 + (pos[2] + o2) * cs2;
+            const int64_t gi = cell * NC1 + i;
+            x[gi] = x[gi] + v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Transfers (Sec. 2.2).  Child c of a coarse cell sits at offset o in
 // {0,1}^d; its coefficients are (E_{o_d} x..x E_{o_1}) applied to the coarse
 // coefficients, E_o[i][j] = phi_j((xi_i + o)/2).  Restriction applies the
@@ -638,8 +841,51 @@ struct RunSchwarz {
         }
         return FTS_OK;
     }
+    template <int KIND, int BF>
+    static fts_status go_mfma(const fts_level *lv, const fts_eigs *eg, double omega, const double *r, double *x,
+                              hipStream_t st) {
+        if constexpr (D != 3 || (KIND ? 2 * N1 : N1) > 16) {
+            return fail(FTS_E_UNSUPPORTED, "16-bit MFMA contractions need d = 3 and n <= 16");
+        } else {
+            const bool staged = KIND == 1 && eg->schedule == FTS_SCHEDULE_STAGED;
+            const int ncolor = (KIND && !staged) ? 8 : 1;
+            for (int color = 0; color < ncolor; ++color) {
+                SubGrid sg{};
+                sg.step = (KIND && !staged) ? 2 : 1;
+                sg.nsub = 1;
+                for (int a = 0; a < 3; ++a) {
+                    sg.first[a] = (KIND && !staged) ? ((color >> a) & 1) : 0;
+                    const int npos = eg->count[a];
+                    sg.cnt[a] = npos > sg.first[a] ? (npos - sg.first[a] + sg.step - 1) / sg.step : 0;
+                    sg.nsub *= sg.cnt[a];
+                }
+                if (sg.nsub == 0) continue;
+                if (staged)
+                    k_schwarz_mfma<N1, KIND, BF, true><<<dim3((unsigned)sg.nsub), dim3(256), 0, st>>>(
+                        lv->view, eg->view, sg, r, x, eg->d_stage, omega);
+                else
+                    k_schwarz_mfma<N1, KIND, BF, false><<<dim3((unsigned)sg.nsub), dim3(256), 0, st>>>(
+                        lv->view, eg->view, sg, r, x, nullptr, omega);
+                fts_status s = check_launch("k_schwarz_mfma");
+                if (s != FTS_OK) return s;
+            }
+            if (staged) {
+                const int64_t n = lv->ndofs;
+                k_patch_gather<D, N1><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(lv->view, eg->d_stage, x);
+                return check_launch("k_patch_gather");
+            }
+            return FTS_OK;
+        }
+    }
     static fts_status run(const fts_level *lv, const fts_eigs *eg, double omega, fts_prec prec, const double *r,
                           double *x, hipStream_t st) {
+        if (prec == FTS_PREC_F16 || prec == FTS_PREC_BF16) {
+            if (!eg->d_mfma) return fail(FTS_E_UNSUPPORTED, "16-bit MFMA contractions need n <= 16");
+            const bool bf = prec == FTS_PREC_BF16;
+            if (eg->kind == FTS_CELL)
+                return bf ? go_mfma<0, 1>(lv, eg, omega, r, x, st) : go_mfma<0, 0>(lv, eg, omega, r, x, st);
+            return bf ? go_mfma<1, 1>(lv, eg, omega, r, x, st) : go_mfma<1, 0>(lv, eg, omega, r, x, st);
+        }
         if (prec == FTS_PREC_F64)
             return eg->kind == FTS_CELL ? go<0, double>(lv, eg, omega, r, x, st) : go<1, double>(lv, eg, omega, r, x, st);
         if (prec == FTS_PREC_F32)

@@ -486,6 +486,74 @@ fts_status fts_setup_1d_eigs(const fts_level *lv, fts_patch_kind kind, fts_eigs 
         delete eg;
         return fail(FTS_E_HIP, "upload of eigen tables failed");
     }
+    if (n <= 16) {
+        // 16-bit MFMA tables: 4 matrices of 256 entries per (axis, position), plus 2 floats
+        size_t cnt_all = 0;
+        for (int a = 0; a < 3; ++a) cnt_all += eg->count[a];
+        const size_t mats = cnt_all * 4 * 256 * sizeof(uint16_t);
+        const size_t flts = cnt_all * 2 * sizeof(float);
+        std::vector<unsigned char> host16(std::max<size_t>(mats + flts, 4));
+        uint16_t *m16 = reinterpret_cast<uint16_t *>(host16.data());
+        float *f32 = reinterpret_cast<float *>(host16.data() + mats);
+        if (hipMalloc(&eg->d_mfma, host16.size()) != hipSuccess) {
+            hipFree(eg->d_tab);
+            hipFree(eg->d_tab32);
+            delete eg;
+            return fail(FTS_E_HIP, "hipMalloc of the MFMA tables failed");
+        }
+        const uint16_t *dm = static_cast<const uint16_t *>(eg->d_mfma);
+        const float *df = reinterpret_cast<const float *>(static_cast<const unsigned char *>(eg->d_mfma) + mats);
+        size_t mo = 0, fo = 0;
+        auto to_f16 = [](double v) {
+            _Float16 hv = (_Float16)(float)v;
+            uint16_t u;
+            std::memcpy(&u, &hv, 2);
+            return u;
+        };
+        auto to_bf16 = [](double v) {
+            float f = (float)v;
+            uint32_t u;
+            std::memcpy(&u, &f, 4);
+            u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+            return (uint16_t)(u >> 16);
+        };
+        for (int a = 0; a < 3; ++a) {
+            const int cnt = eg->count[a];
+            eg->view.Ff16[a] = dm + mo;
+            eg->view.Bf16[a] = dm + mo + (size_t)cnt * 256;
+            eg->view.Fbf16[a] = dm + mo + (size_t)cnt * 512;
+            eg->view.Bbf16[a] = dm + mo + (size_t)cnt * 768;
+            eg->view.mscale[a] = df + fo;
+            eg->view.lmin[a] = df + fo + cnt;
+            for (int s = 0; s < cnt; ++s) {
+                const double *S = &eg->S[a][(size_t)s * nn];
+                double smax = 0.0, lmn = eg->lam[a][(size_t)s * n];
+                for (int i = 0; i < nn; ++i) smax = std::max(smax, std::fabs(S[i]));
+                for (int i = 0; i < n; ++i) lmn = std::min(lmn, eg->lam[a][(size_t)s * n + i]);
+                for (int o = 0; o < 16; ++o)
+                    for (int k2 = 0; k2 < 16; ++k2) {
+                        const double fv = (o < n && k2 < n) ? S[k2 * n + o] / smax : 0.0;
+                        const double bv = (o < n && k2 < n) ? S[o * n + k2] / smax : 0.0;
+                        const size_t e = (size_t)s * 256 + o * 16 + k2;
+                        m16[mo + e] = to_f16(fv);
+                        m16[mo + (size_t)cnt * 256 + e] = to_f16(bv);
+                        m16[mo + (size_t)cnt * 512 + e] = to_bf16(fv);
+                        m16[mo + (size_t)cnt * 768 + e] = to_bf16(bv);
+                    }
+                f32[fo + s] = (float)smax;
+                f32[fo + cnt + s] = (float)lmn;
+            }
+            mo += (size_t)cnt * 1024;
+            fo += (size_t)cnt * 2;
+        }
+        if (hipMemcpy(eg->d_mfma, host16.data(), host16.size(), hipMemcpyHostToDevice) != hipSuccess) {
+            hipFree(eg->d_tab);
+            hipFree(eg->d_tab32);
+            hipFree(eg->d_mfma);
+            delete eg;
+            return fail(FTS_E_HIP, "upload of the MFMA tables failed");
+        }
+    }
     if (kind == FTS_VERTEX_PATCH) {
         int64_t nsub = 1;
         for (int a = 0; a < lv->dim; ++a) nsub *= eg->count[a];
@@ -493,6 +561,7 @@ fts_status fts_setup_1d_eigs(const fts_level *lv, fts_patch_kind kind, fts_eigs 
         if (hipMalloc(&eg->d_stage, std::max<size_t>(bytes, 8)) != hipSuccess) {
             hipFree(eg->d_tab);
             hipFree(eg->d_tab32);
+            if (eg->d_mfma) hipFree(eg->d_mfma);
             delete eg;
             return fail(FTS_E_HIP, "hipMalloc of the patch staging buffer failed");
         }
@@ -514,6 +583,7 @@ fts_status fts_eigs_destroy(fts_eigs *eigs) {
     if (eigs->d_tab) hipFree(eigs->d_tab);
     if (eigs->d_tab32) hipFree(eigs->d_tab32);
     if (eigs->d_stage) hipFree(eigs->d_stage);
+    if (eigs->d_mfma) hipFree(eigs->d_mfma);
     delete eigs;
     return FTS_OK;
 }

@@ -301,3 +301,44 @@ def test_pcg_mixed_precision_reaches_fp64_residual():
     print("iterations f64", it64, "f32", it32)
     assert r32 <= 1e-10 and it32 <= it64 + 3
     assert rel(host(x32), host(x64)) < 1e-8
+
+
+@pytest.mark.parametrize("kind,k,ms", [("vertex", 3, (4, 3, 5)), ("vertex", 4, (3, 4, 3)), ("vertex", 7, (3, 2, 2)),
+                                       ("cell", 4, (3, 2, 3)), ("cell", 9, (2, 2, 1))])
+@pytest.mark.parametrize("prec,bound", [("f16", 1.5e-3), ("bf16", 1.2e-2)])
+def test_mfma_contractions_error_bound(kind, k, ms, prec, bound):
+    """16-bit MFMA contractions (FP32 accumulation, FP64 update of x): the
+    correction of one local-solver application against the FP64 oracle, in
+    both schedules; bounded by a few units of the 16-bit roundoff."""
+    announce("mfma", prec, kind, k, ms)
+    m = omesh(3, k, ms, 20)
+    A = sipg.assemble(m)
+    subs = schwarz.cell_subdomains(m) if kind == "cell" else schwarz.vertex_patch_subdomains(m)
+    sol = schwarz.ExactLocalSolvers(A, subs, cache=False)
+    r = random_vector(m.ndofs, 3) * 1e-7  # small residuals must not underflow FP16
+    ref = 0.4 * sol.apply(r)
+    lv = glevel(m)
+    eg = fts.Eigs(lv, kind)
+    for schedule in (("staged", "colored") if kind == "vertex" else ("staged",)):
+        eg.set_schedule(schedule)
+        xa = dev(np.zeros(m.ndofs))
+        fts.schwarz_apply(lv, eg, 0.4, dev(r), xa, prec=prec)
+        err = rel(host(xa), ref)
+        print(prec, kind, k, schedule, "relative error", err)
+        assert err < bound
+
+
+@pytest.mark.parametrize("prec", ["f16", "bf16"])
+def test_pcg_mfma_preconditioner_reaches_fp64_residual(prec):
+    announce("pcg", prec)
+    from oracle.mesh import refine
+    fine = refine(refine(uniform_mesh(3, 3, 2)))
+    gh = fts.Hierarchy(3, 3, fine.widths, 3, "vertex", [0.0, 0.125, 0.125], 1.0, 2, 2)
+    b = dev(random_vector(fine.ndofs, 0))
+    x64 = dev(np.zeros(fine.ndofs))
+    it64, _, _ = gh.pcg(b, x64, rtol=1e-10)
+    xl = dev(np.zeros(fine.ndofs))
+    itl, rl, _ = gh.pcg(b, xl, rtol=1e-10, prec=prec)
+    print("iterations f64", it64, prec, itl)
+    assert rl <= 1e-10 and itl <= it64 + 8
+    assert rel(host(xl), host(x64)) < 1e-8
