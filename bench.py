@@ -67,12 +67,62 @@ def cpu_baseline(cfg):
                       "workload reduced to 8^3 fine cells (64,000 DoFs), median of 3, setup excluded"}
 
 
+def mixed_vs_fp64(steps_hint=1):
+    """3-D Q7 on 48^3 cells (56,623,104 DoFs): FP64 CG preconditioned by one
+    V-cycle (5 levels 48^3..3^3, vertex patches, omega = 2^-3, 2+2 sweeps,
+    dense LU on 13,824 coarse DoFs) to ||r|| <= 1e-10 ||b||, with the smoother
+    contractions in FP64, FP32, FP16-MFMA and BF16-MFMA.  Times are
+    time-to-solution (setup excluded); error = ||x_prec - x_f64|| / ||x_f64||."""
+    import torch
+    import paper_1910_11239_amd as fts
+    cfg = CONFIGS["mixed_3d_q7"]
+    dim, k, m, nl = cfg["dim"], cfg["k"], cfg["m"], cfg["nlevels"]
+    omegas = [0.0] + [cfg["omega"]] * (nl - 1)
+    t0 = time.perf_counter()
+    hier = fts.Hierarchy(dim, k, uniform_widths(dim, m), nl, "vertex", omegas, cfg["gamma_hat"],
+                         cfg["m_pre"], cfg["m_post"])
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    N = hier.ndofs
+    b = torch.as_tensor(random_vector(N, cfg["seed_b"])).cuda()
+    ws = torch.empty((int(fts.lib().fts_pcg_ws_bytes(hier._h)) + 7) // 8, dtype=torch.float64, device="cuda")
+    out, sol = {}, {}
+    fine, eg = hier.levels[-1], hier.eigs[-1]
+    r = torch.as_tensor(random_vector(N, 5)).cuda()
+    xa = torch.zeros_like(r)
+    patch_flops = wm.smoother_flops(dim, k, (m,) * dim, "vertex")
+    for prec in ("f64", "f32", "f16", "bf16"):
+        x = torch.zeros(N, dtype=torch.float64, device="cuda")
+        hier.pcg(b, x, rtol=cfg["rtol"], maxit=3, prec=prec, ws=ws)  # warm-up
+        x.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        it, rel, _ = hier.pcg(b, x, rtol=cfg["rtol"], maxit=400, prec=prec, ws=ws)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        t_apply = _events_time(lambda: fts.schwarz_apply(fine, eg, cfg["omega"], r, xa, prec=prec), 3)
+        sol[prec] = x
+        out[prec] = {"iterations": it, "seconds": dt, "final_relres": rel,
+                     "patch_apply_ms": t_apply,
+                     "patch_apply_tflops": patch_flops / (t_apply * 1e-3) / 1e12}
+    for prec in out:
+        out[prec]["rel_diff_vs_f64"] = float(torch.linalg.norm(sol[prec] - sol["f64"]) /
+                                             torch.linalg.norm(sol["f64"]))
+        out[prec]["speedup_vs_f64"] = out["f64"]["seconds"] / out[prec]["seconds"]
+    del hier, sol
+    torch.cuda.empty_cache()
+    return {"workload": "mixed_3d_q7: 3-D DG Q7, 48^3 cells (56,623,104 DoFs), CG to 1e-10 with a 5-level "
+                        "vertex-patch V-cycle (omega 0.125, 2+2 sweeps, dense LU on 13,824 DoFs)",
+            "setup_s": setup_s, "by_precision": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the 48^3 Q7 mixed-precision CG comparison")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + steps of the V-cycle only (for rocprofv3)")
     args = ap.parse_args()
@@ -177,6 +227,10 @@ def main():
                            "algorithmic_hbm_gbs": wm.smoother_sweep_bytes(dim, k, ncells) / (sweep_ms * 1e-3) / 1e9},
         "setup_s": setup_s,
     }
+    del hier
+    torch.cuda.empty_cache()
+    if not args.no_mixed:
+        out["mixed_vs_fp64"] = mixed_vs_fp64()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out))
