@@ -216,6 +216,33 @@ fts_status fts_pcg(fts_hierarchy *hier, fts_prec prec, const double *b, double *
                    int32_t maxit, void *ws, size_t ws_bytes, int32_t *iters, double *relres,
                    double *history, void *stream);
 
+/* Replaces the per-level damping (host array of nlevels, index 0 unused). */
+fts_status fts_hierarchy_set_omega(fts_hierarchy *hier, const double *omega_per_level);
+
+/* ---- a14: adjoint of the V-cycle ------------------------------------------- */
+
+/* Allocates the adjoint workspaces of the hierarchy (per level: the inputs of
+ * all smoothing steps of one V-cycle, 5 work vectors; small reduction
+ * buffers).  Idempotent. */
+fts_status fts_hierarchy_enable_adjoint(fts_hierarchy *hier);
+
+/* Reverse mode of one FP64 V-cycle x_out = MG_L(x_in, b) (Alg. gmg).  Recomputes
+ * the forward sweeps of the cycle from x_in (instead of storing them across
+ * cycles), then propagates lambda_out = dL/dx_out backwards through every
+ * smoothing step x' = x + omega_l C_l (b_l - A_l x) (C_l = sum_j R_j^T A_j^-1 R_j),
+ * the transfers and the coarse solve.  Outputs:
+ *   lambda_b  (device, ndofs; may be NULL)   += dL/db
+ *   lambda_x  (device, ndofs; may be NULL)    = dL/dx_in
+ *   d_omega   (host, nlevels; may be NULL)   += dL/d omega_l (index 0: 0)
+ *   d_penalty (host, nlevels; may be NULL)   += dL/d gamma_hat_l, through the
+ *             level operators, the local solvers (d A_j^-1 = -A_j^-1 dA_j A_j^-1,
+ *             evaluated in the eigenbasis) and the coarse solve.
+ * The matrices are affine in gamma_hat, so dA/dgamma_hat is the penalty part
+ * at gamma_hat = 1.  Synchronises the stream once (gradient readback). */
+fts_status fts_vcycle_adjoint(fts_hierarchy *hier, const double *b, const double *x_in,
+                              const double *lambda_out, double *lambda_b, double *lambda_x,
+                              double *d_omega, double *d_penalty, void *stream);
+
 /* x0 = A_0^-1 b0 with the stored LU factorisation: x0 = inv(U) (inv(L) b0),
  * the inverse triangular factors being formed once at hierarchy creation, so
  * each of the two triangular stages is a parallel mat-vec reading its

@@ -56,6 +56,9 @@ _SIGS = {
     "fts_vcycle": (_I32, [_VP, _I32, _VP, _VP, _VP]),
     "fts_coarse_solve": (_I32, [_VP, _VP, _VP, _VP]),
     "fts_pcg_ws_bytes": (_SZ, [_VP]),
+    "fts_hierarchy_set_omega": (_I32, [_VP, _VP]),
+    "fts_hierarchy_enable_adjoint": (_I32, [_VP]),
+    "fts_vcycle_adjoint": (_I32, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "fts_pcg": (_I32, [_VP, _I32, _VP, _VP, _D, _I32, _VP, _SZ, _VP, _VP, _VP, _VP]),
 }
 
@@ -258,8 +261,96 @@ class Hierarchy:
                              ctypes.byref(rel), hist.ctypes.data, _stream()), "fts_pcg")
         return it.value, rel.value, hist[:it.value + 1]
 
+    def set_omega(self, omegas):
+        om = np.ascontiguousarray(np.broadcast_to(np.asarray(omegas, dtype=np.float64), (self.nlevels,)))
+        _check(lib().fts_hierarchy_set_omega(self._h, om.ctypes.data), "fts_hierarchy_set_omega")
+
+    def vcycle_adjoint(self, b, x_in, lam_out, lam_b=None, lam_x=None):
+        """Reverse mode of x_out = MG(x_in, b).  lam_b (+=) and lam_x (=) are CUDA
+        tensors or None; returns (d_omega, d_penalty) per level (numpy, level 0 first)."""
+        _check(lib().fts_hierarchy_enable_adjoint(self._h), "fts_hierarchy_enable_adjoint")
+        dom, dpen = np.zeros(self.nlevels), np.zeros(self.nlevels)
+        n = self.ndofs
+        _check(lib().fts_vcycle_adjoint(self._h, _ptr(b, n, "b"), _ptr(x_in, n, "x_in"), _ptr(lam_out, n, "lam_out"),
+                                        None if lam_b is None else _ptr(lam_b, n, "lam_b"),
+                                        None if lam_x is None else _ptr(lam_x, n, "lam_x"),
+                                        dom.ctypes.data, dpen.ctypes.data, _stream()), "fts_vcycle_adjoint")
+        return dom, dpen
+
     def coarse_solve(self, b0, x0):
         n0 = self.levels[0].ndofs
         _check(lib().fts_coarse_solve(self._h, _ptr(b0, n0, "b0"), _ptr(x0, n0, "x0"), _stream()),
                "fts_coarse_solve")
         return x0
+
+
+class VCycleIterations:
+    """u_{i+1} = MG_L(u_i, b), u_0 = 0, for ``ncycles`` V-cycles, differentiable
+    with respect to b, the per-level damping omega_l and the per-level penalty
+    factor gamma_hat_l through a hand-written adjoint (fts_vcycle_adjoint),
+    which recomputes each cycle's sweeps from the stored cycle inputs.  The
+    hierarchy of a penalty vector is built once and cached (the 1-D eigen-data
+    and the coarse factor depend on it; omega is set per call)."""
+
+    def __init__(self, dim, k, widths, nlevels, kind="vertex", m_pre=2, m_post=2, ncycles=4):
+        self.args = (dim, k, widths, nlevels, kind, m_pre, m_post)
+        self.ncycles = ncycles
+        self._cache = {}
+
+    def hierarchy(self, gammas):
+        key = tuple(float(g) for g in gammas)
+        if key not in self._cache:
+            dim, k, widths, nlevels, kind, m_pre, m_post = self.args
+            self._cache[key] = Hierarchy(dim, k, widths, nlevels, kind, 0.5, np.asarray(key), m_pre, m_post)
+        return self._cache[key]
+
+    def __call__(self, b, omegas, gammas):
+        return _VCycleFn.apply(b, omegas, gammas, self)
+
+
+def _vcycle_fn():
+    import torch
+
+    class VCycleFn(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, b, omegas, gammas, solver):
+            h = solver.hierarchy(gammas.detach().cpu().numpy())
+            h.set_omega(omegas.detach().cpu().numpy())
+            u = torch.zeros_like(b)
+            inputs = []
+            for _ in range(solver.ncycles):
+                inputs.append(u.clone())
+                h.vcycle(b, u)
+            ctx.h, ctx.inputs = h, inputs
+            ctx.save_for_backward(b)
+            return u
+
+        @staticmethod
+        def backward(ctx, grad_u):
+            (b,) = ctx.saved_tensors
+            h = ctx.h
+            lam = grad_u.contiguous().clone()
+            lam_b = torch.zeros_like(b)
+            lam_x = torch.empty_like(b)
+            dom = np.zeros(h.nlevels)
+            dpen = np.zeros(h.nlevels)
+            for x_in in reversed(ctx.inputs):
+                o, pnl = h.vcycle_adjoint(b, x_in, lam, lam_b, lam_x)
+                dom += o
+                dpen += pnl
+                lam, lam_x = lam_x, lam
+            return lam_b, torch.as_tensor(dom), torch.as_tensor(dpen), None
+
+    return VCycleFn
+
+
+class _LazyFn:
+    _fn = None
+
+    def apply(self, *args):
+        if _LazyFn._fn is None:
+            _LazyFn._fn = _vcycle_fn()
+        return _LazyFn._fn.apply(*args)
+
+
+_VCycleFn = _LazyFn()

@@ -25,6 +25,12 @@ struct fts_hierarchy {
     double *cy = nullptr, *cP = nullptr;  // coarse-solve workspaces
     int64_t N0 = 0;
     double *host_scalars = nullptr;       // pinned readback buffer of the CG reductions
+    // adjoint workspaces (fts_hierarchy_enable_adjoint)
+    bool adj = false;
+    std::vector<std::vector<double *>> xs;  // per level: inputs of every smoothing step and the output
+    std::vector<double *> lam, lamb, aq, atr, at;
+    double *apart = nullptr, *ared = nullptr, *agrad = nullptr;
+    double *host_grad = nullptr;
 };
 
 static hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
@@ -109,6 +115,14 @@ fts_status fts_hierarchy_destroy(fts_hierarchy *h) {
     if (h->cy) hipFree(h->cy);
     if (h->cP) hipFree(h->cP);
     if (h->host_scalars) hipHostFree(h->host_scalars);
+    for (auto &v : h->xs)
+        for (auto *p : v) if (p) hipFree(p);
+    for (auto *vv : {&h->lam, &h->lamb, &h->aq, &h->atr, &h->at})
+        for (auto *p : *vv) if (p) hipFree(p);
+    if (h->apart) hipFree(h->apart);
+    if (h->ared) hipFree(h->ared);
+    if (h->agrad) hipFree(h->agrad);
+    if (h->host_grad) hipHostFree(h->host_grad);
     delete h;
     return FTS_OK;
 }
@@ -307,6 +321,166 @@ fts_status fts_pcg(fts_hierarchy *h, fts_prec prec, const double *b, double *x, 
 #undef FTS_TRY
     if (iters) *iters = it;
     if (relres) *relres = rel;
+    return FTS_OK;
+}
+
+fts_status fts_hierarchy_set_omega(fts_hierarchy *h, const double *omega_per_level) {
+    if (!h || !omega_per_level) return fail(FTS_E_INVAL, "fts_hierarchy_set_omega: NULL argument");
+    h->omega.assign(omega_per_level, omega_per_level + h->nlevels);
+    return FTS_OK;
+}
+
+fts_status fts_hierarchy_enable_adjoint(fts_hierarchy *h) {
+    if (!h) return fail(FTS_E_INVAL, "fts_hierarchy_enable_adjoint: NULL handle");
+    if (h->adj) return FTS_OK;
+    const int L = h->nlevels;
+    h->xs.assign(L, {});
+    int64_t maxcells = 1;
+    auto alloc = [&](int64_t n, double **p) {
+        return hipMalloc(p, (size_t)std::max<int64_t>(n, 1) * sizeof(double)) == hipSuccess;
+    };
+    bool ok = true;
+    for (int l = 0; l < L && ok; ++l) {
+        const int64_t n = h->levels[l]->ndofs;
+        maxcells = std::max(maxcells, h->levels[l]->ncells);
+        const int nstates = l == 0 ? 1 : h->m_pre + h->m_post + 2;
+        for (int i = 0; i < nstates && ok; ++i) {
+            double *p = nullptr;
+            ok = alloc(n, &p);
+            h->xs[l].push_back(p);
+        }
+        for (auto *vv : {&h->lam, &h->lamb, &h->aq, &h->atr, &h->at}) {
+            double *p = nullptr;
+            if (ok) ok = alloc(n, &p);
+            vv->push_back(p);
+        }
+    }
+    if (ok) ok = alloc(maxcells, &h->apart) && alloc(2 * red_partials(), &h->ared) && alloc(2 * L, &h->agrad);
+    if (ok) ok = hipHostMalloc(&h->host_grad, 2 * L * sizeof(double)) == hipSuccess;
+    if (!ok) return fail(FTS_E_HIP, "allocation of the adjoint workspaces failed");
+    h->adj = true;
+    return FTS_OK;
+}
+
+// Forward V-cycle on level l from x_in (NULL = zero) recording the input of
+// every smoothing step and the output in h->xs[l]; b_l is b (finest) or vb.
+static fts_status adj_forward(fts_hierarchy *h, int l, const double *x_in, const double *b, hipStream_t s) {
+    const fts_level *lv = h->levels[l];
+    const int64_t n = lv->ndofs;
+    auto &X = h->xs[l];
+    fts_status st = FTS_OK;
+    if (l == 0) return coarse_solve(h->LU, h->N0, b, X[0], h->cy, h->cP, s);
+    if (x_in) {
+        FTS_HIP_CHECK(hipMemcpyAsync(X[0], x_in, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    } else {
+        st = launch_fill(X[0], n, 0.0, s);
+    }
+    const fts_eigs *eg = h->eigs[l];
+    double *r = h->atr[l];
+    int k = 0;
+    for (int i = 0; i < h->m_pre && st == FTS_OK; ++i, ++k) {
+        FTS_HIP_CHECK(hipMemcpyAsync(X[k + 1], X[k], n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        st = launch_operator(lv, X[k], b, r, true, s);
+        if (st == FTS_OK) st = launch_schwarz(lv, eg, h->omega[l], FTS_PREC_F64, r, X[k + 1], s);
+    }
+    if (st == FTS_OK) st = launch_operator(lv, X[k], b, r, true, s);
+    if (st == FTS_OK) st = launch_restrict(h->levels[l - 1], lv, r, h->vb[l - 1], s);
+    if (st == FTS_OK) st = adj_forward(h, l - 1, nullptr, h->vb[l - 1], s);
+    if (st == FTS_OK) {
+        FTS_HIP_CHECK(hipMemcpyAsync(X[k + 1], X[k], n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        st = launch_prolongate(h->levels[l - 1], lv, h->xs[l - 1].back(), X[k + 1], s);
+        ++k;
+    }
+    for (int i = 0; i < h->m_post && st == FTS_OK; ++i, ++k) {
+        FTS_HIP_CHECK(hipMemcpyAsync(X[k + 1], X[k], n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        st = launch_operator(lv, X[k], b, r, true, s);
+        if (st == FTS_OK) st = launch_schwarz(lv, eg, h->omega[l], FTS_PREC_F64, r, X[k + 1], s);
+    }
+    return st;
+}
+
+// Reverse of one smoothing step x' = x + omega C (b - A x) on level l, with
+// lam[l] = adjoint of x' on entry and of x on exit; accumulates the adjoint
+// of b in lamb[l], d omega_l and d gamma_l in agrad.
+static fts_status adj_smooth_step(fts_hierarchy *h, int l, const double *xin, const double *b, hipStream_t s) {
+    const fts_level *lv = h->levels[l];
+    const fts_eigs *eg = h->eigs[l];
+    const int64_t n = lv->ndofs;
+    const double om = h->omega[l];
+    double *lam = h->lam[l], *q = h->aq[l], *r = h->atr[l], *t = h->at[l];
+    double *dom = h->agrad + 2 * l, *dga = h->agrad + 2 * l + 1;
+    fts_status st = launch_operator(lv, xin, b, r, true, s);        // r = b - A x
+    if (st == FTS_OK) st = launch_fill(q, n, 0.0, s);
+    if (st == FTS_OK) st = launch_schwarz(lv, eg, 1.0, FTS_PREC_F64, lam, q, s);  // q = C lam
+    if (st == FTS_OK) st = launch_dot_acc(q, r, n, 1.0, h->ared, dom, s);        // d omega += q.r
+    if (st == FTS_OK) st = launch_axpy(om, q, h->lamb[l], n, s);                  // lam_b += omega q
+    int64_t np = 0;
+    if (st == FTS_OK) st = launch_schwarz_dgamma(lv, eg, lam, r, h->apart, &np, s);
+    if (st == FTS_OK) st = launch_sum_acc(h->apart, np, -om, h->ared, dga, s);    // -omega sum_j u~ D v~
+    if (st == FTS_OK) st = launch_operator_penalty(lv, xin, t, s);                // t = A1 x
+    if (st == FTS_OK) st = launch_dot_acc(q, t, n, -om, h->ared, dga, s);         // -omega q.(A1 x)
+    if (st == FTS_OK) st = launch_operator(lv, q, nullptr, t, false, s);          // t = A q
+    if (st == FTS_OK) st = launch_axpy(-om, t, lam, n, s);                        // lam -= omega A q
+    return st;
+}
+
+// Reverse of MG_l(x, b): lam[l] = adjoint of the output on entry, of x on exit;
+// lamb[l] = adjoint of b (overwritten).
+static fts_status adj_reverse(fts_hierarchy *h, int l, const double *b, hipStream_t s) {
+    const fts_level *lv = h->levels[l];
+    const int64_t n = lv->ndofs;
+    fts_status st = FTS_OK;
+    if (l == 0) {
+        // x0 = A0^-1 b0: lam_b0 = A0^-1 lam; d gamma_0 -= lam_b0 . (A1 x0); lam_x = 0
+        st = coarse_solve(h->LU, h->N0, h->lam[0], h->lamb[0], h->cy, h->cP, s);
+        if (st == FTS_OK) st = launch_operator_penalty(lv, h->xs[0][0], h->at[0], s);
+        if (st == FTS_OK) st = launch_dot_acc(h->lamb[0], h->at[0], n, -1.0, h->ared, h->agrad + 1, s);
+        if (st == FTS_OK) st = launch_fill(h->lam[0], n, 0.0, s);
+        return st;
+    }
+    auto &X = h->xs[l];
+    st = launch_fill(h->lamb[l], n, 0.0, s);
+    const int kc = h->m_pre;  // index of the state before the coarse correction
+    for (int i = h->m_post; i >= 1 && st == FTS_OK; --i) st = adj_smooth_step(h, l, X[kc + i], b, s);
+    // x_{kc+1} = x_kc + P e
+    if (st == FTS_OK) st = launch_restrict(h->levels[l - 1], lv, h->lam[l], h->lam[l - 1], s);
+    if (st == FTS_OK) st = adj_reverse(h, l - 1, h->vb[l - 1], s);
+    // b_{l-1} = P^T (b - A x_kc)
+    double *tr = h->atr[l];
+    if (st == FTS_OK) st = launch_fill(tr, n, 0.0, s);
+    if (st == FTS_OK) st = launch_prolongate(h->levels[l - 1], lv, h->lamb[l - 1], tr, s);
+    if (st == FTS_OK) st = launch_axpy(1.0, tr, h->lamb[l], n, s);
+    if (st == FTS_OK) st = launch_operator(lv, tr, nullptr, h->at[l], false, s);
+    if (st == FTS_OK) st = launch_axpy(-1.0, h->at[l], h->lam[l], n, s);
+    if (st == FTS_OK) st = launch_operator_penalty(lv, X[kc], h->aq[l], s);
+    if (st == FTS_OK) st = launch_dot_acc(tr, h->aq[l], n, -1.0, h->ared, h->agrad + 2 * l + 1, s);
+    for (int i = h->m_pre; i >= 1 && st == FTS_OK; --i) st = adj_smooth_step(h, l, X[i - 1], b, s);
+    return st;
+}
+
+fts_status fts_vcycle_adjoint(fts_hierarchy *h, const double *b, const double *x_in, const double *lambda_out,
+                              double *lambda_b, double *lambda_x, double *d_omega, double *d_penalty, void *stream) {
+    if (!h || !b || !x_in || !lambda_out) return fail(FTS_E_INVAL, "fts_vcycle_adjoint: NULL argument");
+    if (!h->adj) return fail(FTS_E_INVAL, "fts_vcycle_adjoint: call fts_hierarchy_enable_adjoint first");
+    if (h->kind != FTS_VERTEX_PATCH && h->kind != FTS_CELL) return fail(FTS_E_INVAL, "bad hierarchy");
+    hipStream_t s = S(stream);
+    const int L = h->nlevels - 1;
+    const int64_t n = h->levels[L]->ndofs;
+    fts_status st = launch_fill(h->agrad, 2 * h->nlevels, 0.0, s);
+    if (st == FTS_OK) st = adj_forward(h, L, x_in, b, s);
+    if (st == FTS_OK)
+        FTS_HIP_CHECK(hipMemcpyAsync(h->lam[L], lambda_out, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (st == FTS_OK) st = adj_reverse(h, L, b, s);
+    if (st == FTS_OK && lambda_b) st = launch_axpy(1.0, h->lamb[L], lambda_b, n, s);
+    if (st == FTS_OK && lambda_x)
+        FTS_HIP_CHECK(hipMemcpyAsync(lambda_x, h->lam[L], n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (st != FTS_OK) return st;
+    FTS_HIP_CHECK(hipMemcpyAsync(h->host_grad, h->agrad, 2 * h->nlevels * sizeof(double), hipMemcpyDeviceToHost, s));
+    FTS_HIP_CHECK(hipStreamSynchronize(s));
+    for (int l = 0; l < h->nlevels; ++l) {
+        if (d_omega) d_omega[l] += h->host_grad[2 * l];
+        if (d_penalty) d_penalty[l] += h->host_grad[2 * l + 1];
+    }
     return FTS_OK;
 }
 

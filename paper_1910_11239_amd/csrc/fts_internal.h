@@ -43,6 +43,10 @@ struct Ref1D {
     void cell_operator(double h, double h_left, double h_right, double gamma_hat,
                        double *A) const;
     void interface_block(double hl, double hr, double gamma_hat, double *B) const;
+    // Derivatives with respect to gamma_hat (the operators are affine in it):
+    // the penalty terms alone, evaluated at gamma_hat = 1.
+    void cell_penalty(double h, double h_left, double h_right, double *A) const;
+    void interface_penalty(double hl, double hr, double *B) const;
 };
 
 // Generalised symmetric-definite eigenproblem A S = M S diag(lam), S^T M S = I,
@@ -76,6 +80,8 @@ struct EigView {
     // bit patterns.  mscale = s, lmin = smallest eigenvalue (FP32).
     const uint16_t *Ff16[3], *Bf16[3], *Fbf16[3], *Bbf16[3];
     const float *mscale[3], *lmin[3];
+    // S^T (dA/dgamma_hat) S per axis position (n x n, FP64), for the adjoint
+    const double *DG[3];
 };
 
 }  // namespace fts
@@ -90,13 +96,14 @@ struct fts_level {
     std::vector<double> host_cellop[3], host_iface[3];
     double *d_tab = nullptr;  // single device allocation holding every table
     fts::LevelView view{};
+    fts::LevelView view_pen{};  // same mesh, 1-D tables of dA/dgamma_hat (penalty terms)
 };
 
 struct fts_eigs {
     const fts_level *level = nullptr;
     int kind = 0, n = 0;
     int count[3] = {0, 0, 0};
-    std::vector<double> A[3], M[3], S[3], lam[3];
+    std::vector<double> A[3], M[3], S[3], lam[3], DG[3];
     double *d_tab = nullptr;
     float *d_tab32 = nullptr;
     double *d_stage = nullptr;  // staged corrections of all vertex patches (one per cell of each)
@@ -109,6 +116,19 @@ namespace fts {
 // Launchers (kernels.hip).  All asynchronous on `stream`.
 fts_status launch_operator(const fts_level *lv, const double *x, const double *b, double *y,
                            bool residual, hipStream_t stream);
+// y = (dA/dgamma_hat) x on the level (penalty terms at gamma_hat = 1)
+fts_status launch_operator_penalty(const fts_level *lv, const double *x, double *y, hipStream_t stream);
+// out[blockIdx] partial sums of sum_j (L^-1 Z^T R_j u)^T (sum_t I x D_t x I) (L^-1 Z^T R_j v)
+// over the subdomains; returns the number of partials in *npart.  FP64.
+fts_status launch_schwarz_dgamma(const fts_level *lv, const fts_eigs *eg, const double *u, const double *v,
+                                 double *partials, int64_t *npart, hipStream_t stream);
+// out[0] += scale * sum_i x[i] y[i]  (deterministic; part: 2 * red_partials())
+fts_status launch_dot_acc(const double *x, const double *y, int64_t n, double scale, double *part, double *out,
+                          hipStream_t stream);
+// out[0] += scale * sum_i x[i]
+fts_status launch_sum_acc(const double *x, int64_t n, double scale, double *part, double *out, hipStream_t stream);
+// y += a x
+fts_status launch_axpy(double a, const double *x, double *y, int64_t n, hipStream_t stream);
 fts_status launch_schwarz(const fts_level *lv, const fts_eigs *eg, double omega, fts_prec prec,
                           const double *r, double *x, hipStream_t stream);
 fts_status launch_restrict(const fts_level *coarse, const fts_level *fine, const double *rf,

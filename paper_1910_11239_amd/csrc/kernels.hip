@@ -1039,3 +1039,188 @@ fts_status launch_xpby(double *p, const double *z, double beta, int64_t n, hipSt
 int red_partials() { return kRedBlocks; }
 
 }  // namespace fts
+
+namespace fts {
+
+// ---------------------------------------------------------------------------
+// Adjoint helper: derivative of the local solvers with respect to gamma_hat.
+// For every subdomain j: u~ = Lambda^-1 Z^T R_j u, v~ = Lambda^-1 Z^T R_j v and
+//   c_j = u~^T (sum_t I x..x D_t x..x I) v~,  D_t = Z_t^T (dA_t/dgamma_hat) Z_t,
+// which equals (A_j^-1 R_j u)^T (dA_j/dgamma_hat) (A_j^-1 R_j v) because
+// Z_t^T M_t Z_t = I (eq. generalizedEVP, eq. localsolverEVP).  One partial sum
+// per workgroup.
+template <int D, int N1, int KIND>
+__global__ void __launch_bounds__((SwCfg<D, N1, KIND>::THREADS))
+k_schwarz_dgamma(LevelView g, EigView e, SubGrid sg, const double *__restrict__ u, const double *__restrict__ v,
+                 double *__restrict__ partials) {
+    using C = SwCfg<D, N1, KIND>;
+    constexpr int N = C::N, NT = C::NT, NC1 = C::NC1, NSC = C::NSC, LINES = C::LINES, PPB = C::PPB,
+                  TH = C::THREADS;
+    __shared__ double Tu[PPB * NT];
+    __shared__ double Tv[PPB * NT];
+    __shared__ double red[TH / 64];
+    const int t = threadIdx.x;
+    const int q = t / LINES, l = t % LINES;
+    const int64_t s0 = (int64_t)blockIdx.x * PPB;
+    auto position = [&](int64_t s, int *p) {
+        const int j0 = (int)(s % sg.cnt[0]);
+        const int64_t rr = s / sg.cnt[0];
+        const int j1 = (int)(rr % sg.cnt[1]);
+        const int j2 = (int)(rr / sg.cnt[1]);
+        p[0] = sg.first[0] + sg.step * j0;
+        p[1] = sg.first[1] + sg.step * j1;
+        p[2] = D == 3 ? sg.first[2] + sg.step * j2 : 0;
+    };
+    const int64_t cs1 = g.m[0], cs2 = (int64_t)g.m[0] * g.m[1];
+    for (int p = t; p < PPB * NSC * NC1; p += TH) {
+        const int qq = p / (NSC * NC1), rem = p % (NSC * NC1), sc = rem / NC1, i = rem % NC1;
+        const int64_t s = s0 + qq;
+        if (s >= sg.nsub) continue;
+        int pos[3];
+        position(s, pos);
+        const int o0 = sc & 1, o1 = (sc >> 1) & 1, o2 = (sc >> 2) & 1;
+        const int64_t cell = (pos[0] + o0) + (pos[1] + o1) * cs1 + (D == 3 ? (pos[2] + o2) * cs2 : 0);
+        const int i0 = i % N1, i1 = (i / N1) % N1, i2 = D == 3 ? i / (N1 * N1) : 0;
+        const int lds = (o0 * N1 + i0) + (o1 * N1 + i1) * N + (D == 3 ? (o2 * N1 + i2) * N * N : 0);
+        Tu[qq * NT + lds] = u[cell * NC1 + i];
+        Tv[qq * NT + lds] = v[cell * NC1 + i];
+    }
+    __syncthreads();
+    const int64_t s = s0 + q;
+    const bool act = (q < PPB) && (s < sg.nsub);
+    int pos[3] = {0, 0, 0};
+    if (act) position(s, pos);
+    for (int a = 0; a < D; ++a) {
+        if (act) {
+            contract_line<D, N, double>(Tu + q * NT, a, l, e.ST[a] + (size_t)pos[a] * N * N);
+            contract_line<D, N, double>(Tv + q * NT, a, l, e.ST[a] + (size_t)pos[a] * N * N);
+        }
+        __syncthreads();
+    }
+    for (int p = t; p < PPB * NT; p += TH) {
+        const int qq = p / NT, mm = p % NT;
+        const int64_t ss = s0 + qq;
+        if (ss >= sg.nsub) continue;
+        int ps[3];
+        position(ss, ps);
+        const int m0 = mm % N, m1 = (mm / N) % N, m2 = D == 3 ? mm / (N * N) : 0;
+        double lam = e.lam[0][(size_t)ps[0] * N + m0] + e.lam[1][(size_t)ps[1] * N + m1];
+        if constexpr (D == 3) lam += e.lam[2][(size_t)ps[2] * N + m2];
+        Tu[p] /= lam;
+        Tv[p] /= lam;
+    }
+    __syncthreads();
+    double acc = 0.0;
+    if (act) {
+        for (int a = 0; a < D; ++a) {
+            const int base = line_base<D, N>(a, l), st = line_stride<N>(a);
+            const double *Dt = e.DG[a] + (size_t)pos[a] * N * N;
+            double in[N], out[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) in[i] = Tv[q * NT + base + i * st];
+            matvec_regs<N>(in, out, Dt);
+#pragma unroll
+            for (int i = 0; i < N; ++i) acc = fma(Tu[q * NT + base + i * st], out[i], acc);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if ((t & 63) == 0) red[t >> 6] = acc;
+    __syncthreads();
+    if (t == 0) {
+        double sum = 0.0;
+        for (int w = 0; w < TH / 64; ++w) sum += red[w];
+        partials[blockIdx.x] = sum;
+    }
+}
+
+template <int D, int N1>
+struct RunDgamma {
+    template <int KIND>
+    static fts_status go(const fts_level *lv, const fts_eigs *eg, const double *u, const double *v, double *part,
+                         int64_t *npart, hipStream_t st) {
+        using C = SwCfg<D, N1, KIND>;
+        SubGrid sg{};
+        sg.step = 1;
+        sg.nsub = 1;
+        for (int a = 0; a < 3; ++a) {
+            sg.first[a] = 0;
+            sg.cnt[a] = a < D ? eg->count[a] : 1;
+            sg.nsub *= sg.cnt[a];
+        }
+        const int64_t blocks = (sg.nsub + C::PPB - 1) / C::PPB;
+        *npart = blocks;
+        if (blocks == 0) return FTS_OK;
+        k_schwarz_dgamma<D, N1, KIND><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(lv->view, eg->view, sg,
+                                                                                            u, v, part);
+        return check_launch("k_schwarz_dgamma");
+    }
+    static fts_status run(const fts_level *lv, const fts_eigs *eg, const double *u, const double *v, double *part,
+                          int64_t *npart, hipStream_t st) {
+        return eg->kind == FTS_CELL ? go<0>(lv, eg, u, v, part, npart, st) : go<1>(lv, eg, u, v, part, npart, st);
+    }
+};
+
+fts_status launch_schwarz_dgamma(const fts_level *lv, const fts_eigs *eg, const double *u, const double *v,
+                                 double *partials, int64_t *npart, hipStream_t stream) {
+    return dispatch<RunDgamma>(lv->dim, lv->n1, lv, eg, u, v, partials, npart, stream);
+}
+
+template <int D, int N1>
+struct RunOperatorPen {
+    static fts_status run(const fts_level *lv, const double *x, double *y, hipStream_t st) {
+        using C = OpCfg<D, N1>;
+        const int64_t blocks = (lv->ncells + C::PPB - 1) / C::PPB;
+        if (blocks == 0) return FTS_OK;
+        k_operator<D, N1, false><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(lv->view_pen, x, nullptr, y);
+        return check_launch("k_operator (penalty)");
+    }
+};
+
+fts_status launch_operator_penalty(const fts_level *lv, const double *x, double *y, hipStream_t stream) {
+    return dispatch<RunOperatorPen>(lv->dim, lv->n1, lv, x, y, stream);
+}
+
+__global__ void __launch_bounds__(256) k_dot2_final_acc(const double *__restrict__ part, int nb, double scale,
+                                                        double *__restrict__ out) {
+    __shared__ double sh[8];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 256) a += part[2 * i];
+    const double sa = block_sum(a, sh);
+    if (threadIdx.x == 0) out[0] += scale * sa;
+}
+
+__global__ void __launch_bounds__(256) k_sum_partial(const double *__restrict__ x, int64_t n, double *__restrict__ part) {
+    __shared__ double sh[8];
+    double a = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) a += x[i];
+    const double sa = block_sum(a, sh);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sa;
+        part[2 * blockIdx.x + 1] = 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_axpy(double a, const double *__restrict__ x, double *__restrict__ y, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        y[i] = fma(a, x[i], y[i]);
+}
+
+fts_status launch_dot_acc(const double *x, const double *y, int64_t n, double scale, double *part, double *out,
+                          hipStream_t st) {
+    k_dot2_partial<<<kRedBlocks, 256, 0, st>>>(x, y, nullptr, n, part);
+    k_dot2_final_acc<<<1, 256, 0, st>>>(part, kRedBlocks, scale, out);
+    return check_launch("dot (accumulate)");
+}
+
+fts_status launch_sum_acc(const double *x, int64_t n, double scale, double *part, double *out, hipStream_t st) {
+    k_sum_partial<<<kRedBlocks, 256, 0, st>>>(x, n, part);
+    k_dot2_final_acc<<<1, 256, 0, st>>>(part, kRedBlocks, scale, out);
+    return check_launch("sum (accumulate)");
+}
+
+fts_status launch_axpy(double a, const double *x, double *y, int64_t n, hipStream_t st) {
+    k_axpy<<<vec_grid(n), 256, 0, st>>>(a, x, y, n);
+    return check_launch("k_axpy");
+}
+
+}  // namespace fts

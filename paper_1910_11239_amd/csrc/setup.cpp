@@ -192,6 +192,26 @@ void Ref1D::interface_block(double hl, double hr, double gamma_hat, double *B) c
                             d1[a] * v0[b] / (2.0 * hl);
 }
 
+void Ref1D::cell_penalty(double h, double h_left, double h_right, double *A) const {
+    const double kk = k * (k + 1.0);
+    for (int a = 0; a < n1 * n1; ++a) A[a] = 0.0;
+    for (int p = 0; p < 2; ++p) {
+        const double hn = p == 0 ? h_left : h_right;
+        const bool bdry = !(hn > 0.0);
+        const double eta = bdry ? 1.0 : 0.5;
+        const double gamma = bdry ? kk * 2.0 / h : kk * (1.0 / h + 1.0 / hn);
+        const std::vector<double> &v = p == 0 ? v0 : v1;
+        for (int a = 0; a < n1; ++a)
+            for (int b = 0; b < n1; ++b) A[a * n1 + b] += eta * gamma * v[a] * v[b];
+    }
+}
+
+void Ref1D::interface_penalty(double hl, double hr, double *B) const {
+    const double gamma = k * (k + 1.0) * (1.0 / hl + 1.0 / hr);
+    for (int a = 0; a < n1; ++a)
+        for (int b = 0; b < n1; ++b) B[a * n1 + b] = -0.5 * gamma * v1[a] * v0[b];
+}
+
 fts_status sym_gen_eig(int n, const double *A, const double *M, double *S, double *lam) {
     // Cholesky M = L L^T
     std::vector<double> L(n * n, 0.0);
@@ -337,19 +357,25 @@ fts_status fts_level_create(const fts_mesh_desc *mesh, fts_level **out) {
     const int n1 = lv->n1, nn = n1 * n1;
     // host tables
     size_t total = 0;
+    std::vector<double> pen_cell[3], pen_face[3];
     for (int a = 0; a < 3; ++a) {
         const int m = lv->m[a];
         lv->host_cellop[a].assign((size_t)m * nn, 0.0);
         lv->host_iface[a].assign((size_t)std::max(m - 1, 0) * nn, 0.0);
+        pen_cell[a].assign((size_t)m * nn, 0.0);
+        pen_face[a].assign((size_t)std::max(m - 1, 0) * nn, 0.0);
         for (int c = 0; c < m; ++c) {
             const double hl = c > 0 ? lv->h[a][c - 1] : -1.0;
             const double hr = c + 1 < m ? lv->h[a][c + 1] : -1.0;
             lv->ref.cell_operator(lv->h[a][c], hl, hr, lv->gamma_hat, &lv->host_cellop[a][(size_t)c * nn]);
-            if (c + 1 < m)
+            lv->ref.cell_penalty(lv->h[a][c], hl, hr, &pen_cell[a][(size_t)c * nn]);
+            if (c + 1 < m) {
                 lv->ref.interface_block(lv->h[a][c], lv->h[a][c + 1], lv->gamma_hat,
                                         &lv->host_iface[a][(size_t)c * nn]);
+                lv->ref.interface_penalty(lv->h[a][c], lv->h[a][c + 1], &pen_face[a][(size_t)c * nn]);
+            }
         }
-        total += lv->host_cellop[a].size() + lv->host_iface[a].size() + lv->h[a].size();
+        total += 2 * (lv->host_cellop[a].size() + lv->host_iface[a].size()) + lv->h[a].size();
     }
     total += nn + 2 * nn;
     if (hipMalloc(&lv->d_tab, total * sizeof(double)) != hipSuccess) {
@@ -369,6 +395,8 @@ fts_status fts_level_create(const fts_mesh_desc *mesh, fts_level **out) {
         lv->view.iface[a] = put(lv->host_iface[a]);
         lv->view.h[a] = put(lv->h[a]);
         lv->view.m[a] = lv->m[a];
+        lv->view_pen.cellop[a] = put(pen_cell[a]);
+        lv->view_pen.iface[a] = put(pen_face[a]);
     }
     lv->view.Mhat = put(lv->ref.Mhat);
     std::vector<double> E(2 * nn);
@@ -376,6 +404,13 @@ fts_status fts_level_create(const fts_mesh_desc *mesh, fts_level **out) {
     std::copy(lv->ref.E[1].begin(), lv->ref.E[1].end(), E.begin() + nn);
     lv->view.E = put(E);
     lv->view.ncells = lv->ncells;
+    for (int a = 0; a < 3; ++a) {
+        lv->view_pen.h[a] = lv->view.h[a];
+        lv->view_pen.m[a] = lv->m[a];
+    }
+    lv->view_pen.Mhat = lv->view.Mhat;
+    lv->view_pen.E = lv->view.E;
+    lv->view_pen.ncells = lv->ncells;
     if (hipMemcpy(lv->d_tab, host.data(), total * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
         hipFree(lv->d_tab);
         delete lv;
@@ -452,8 +487,41 @@ fts_status fts_setup_1d_eigs(const fts_level *lv, fts_patch_kind kind, fts_eigs 
                 delete eg;
                 return st;
             }
+            // dA/dgamma_hat of the same 1-D operator, then S^T (dA/dgamma_hat) S
+            std::vector<double> A1(nn, 0.0);
+            if (kind == FTS_CELL) {
+                lv->ref.cell_penalty(h[s], s > 0 ? h[s - 1] : -1.0, s + 1 < m ? h[s + 1] : -1.0, A1.data());
+            } else {
+                const int cl = s, cr = s + 1;
+                lv->ref.cell_penalty(h[cl], cl > 0 ? h[cl - 1] : -1.0, h[cr], tmp.data());
+                for (int i = 0; i < n1; ++i)
+                    for (int j = 0; j < n1; ++j) A1[i * n + j] = tmp[i * n1 + j];
+                lv->ref.cell_penalty(h[cr], h[cl], cr + 1 < m ? h[cr + 1] : -1.0, tmp.data());
+                for (int i = 0; i < n1; ++i)
+                    for (int j = 0; j < n1; ++j) A1[(n1 + i) * n + n1 + j] = tmp[i * n1 + j];
+                lv->ref.interface_penalty(h[cl], h[cr], tmp.data());
+                for (int i = 0; i < n1; ++i)
+                    for (int j = 0; j < n1; ++j) {
+                        A1[i * n + n1 + j] = tmp[i * n1 + j];
+                        A1[(n1 + j) * n + i] = tmp[i * n1 + j];
+                    }
+            }
+            const double *Sd = &eg->S[a][(size_t)s * nn];
+            std::vector<double> T1(nn, 0.0);
+            for (int i = 0; i < n; ++i)
+                for (int m2 = 0; m2 < n; ++m2) {
+                    double t = 0.0;
+                    for (int p = 0; p < n; ++p) t += A1[i * n + p] * Sd[p * n + m2];
+                    T1[i * n + m2] = t;
+                }
+            for (int o = 0; o < n; ++o)
+                for (int m2 = 0; m2 < n; ++m2) {
+                    double t = 0.0;
+                    for (int p = 0; p < n; ++p) t += Sd[p * n + o] * T1[p * n + m2];
+                    eg->DG[a].push_back(t);
+                }
         }
-        total += 2 * eg->S[a].size() + eg->lam[a].size();
+        total += 3 * eg->S[a].size() + eg->lam[a].size();
     }
     if (hipMalloc(&eg->d_tab, std::max<size_t>(total, 1) * sizeof(double)) != hipSuccess ||
         hipMalloc(&eg->d_tab32, std::max<size_t>(total, 1) * sizeof(float)) != hipSuccess) {
@@ -474,6 +542,8 @@ fts_status fts_setup_1d_eigs(const fts_level *lv, fts_patch_kind kind, fts_eigs 
         for (int s = 0; s < eg->count[a]; ++s)
             for (int m = 0; m < n; ++m)
                 for (int i = 0; i < n; ++i) host[off++] = eg->S[a][(size_t)s * nn + i * n + m];
+        eg->view.DG[a] = eg->d_tab + off;
+        for (double v : eg->DG[a]) host[off++] = v;
         eg->view.lam[a] = eg->d_tab + off;
         eg->view.lam32[a] = eg->d_tab32 + off;
         for (double v : eg->lam[a]) host[off++] = v;
