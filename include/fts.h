@@ -249,6 +249,51 @@ fts_status fts_vcycle_adjoint(fts_hierarchy *hier, const double *b, const double
  * triangle once (8 N_0^2 bytes per solve).  x0 may alias b0. */
 fts_status fts_coarse_solve(fts_hierarchy *hier, const double *b0, double *x0, void *stream);
 
+/* ---- a13: batched smoothing of many meshes of mixed degree ------------------ */
+
+typedef struct fts_batch fts_batch;
+
+/* Builds levels and vertex-patch eigen-data (every patch position has its own
+ * 1-D eigenpairs per axis, so anisotropic rectilinear widths are exact) for
+ * nmesh independent 3-D meshes of any degrees 1..9, and the work queue of all
+ * their patches (meshes in decreasing degree, so the largest local solves are
+ * dequeued first).  Vectors of a batch are the meshes' vectors concatenated in
+ * mesh order (offsets: fts_batch_mesh_offset).  Allocates the tables, a
+ * staging buffer of 2^3 (k+1)^3 doubles per patch and the queue. */
+fts_status fts_batch_create(const fts_mesh_desc *meshes, int32_t nmesh, fts_batch **out);
+fts_status fts_batch_destroy(fts_batch *batch);
+int64_t fts_batch_ndofs(const fts_batch *batch);
+fts_status fts_batch_mesh_offset(const fts_batch *batch, int32_t mesh, int64_t *offset, int64_t *ndofs);
+
+/* r = b - A x on every mesh (FP64; one launch per degree present). */
+fts_status fts_batch_residual(fts_batch *batch, const double *b, const double *x, double *r,
+                              void *stream);
+/* x += omega sum_j R_j^T A_j^-1 R_j r on every mesh: ONE persistent launch over
+ * the patches of all meshes (workgroups dequeue chunks of patches with an
+ * atomic counter; a degree switch selects the local solver), then a batched
+ * per-cell gather.  prec: FTS_PREC_F64 or FTS_PREC_F32 contractions (update
+ * of x in FP64).  Calls on one batch must be stream-ordered (shared staging
+ * buffer and counter). */
+fts_status fts_batch_apply(fts_batch *batch, double omega, fts_prec prec, const double *r, double *x,
+                           void *stream);
+/* nsweeps of r = b - A x; x += omega sum_j ...; ws: fts_batch_ws_bytes bytes. */
+size_t fts_batch_ws_bytes(const fts_batch *batch);
+fts_status fts_batch_smooth(fts_batch *batch, double omega, fts_prec prec, const double *b, double *x,
+                            int32_t nsweeps, void *ws, size_t ws_bytes, void *stream);
+
+/* Launch shape of the persistent kernel: threads per workgroup (64, 128 or
+ * 256), number of persistent workgroups, patches dequeued per atomic. */
+fts_status fts_batch_set_launch(fts_batch *batch, int32_t threads, int32_t grid, int32_t chunk);
+fts_status fts_batch_get_launch(const fts_batch *batch, int32_t *threads, int32_t *grid,
+                                int32_t *chunk);
+/* Autotuner: times the persistent kernel (events on `stream`, synchronising)
+ * for threads in {64,128,256} x grid in {1,2,4,8} x (compute units) x chunk
+ * in {1,4,16} on the residual r (device, fts_batch_ndofs doubles), keeps the
+ * fastest shape and writes a per-candidate report into `report` (may be NULL).
+ * Overwrites the batch's staging buffer. */
+fts_status fts_batch_autotune(fts_batch *batch, fts_prec prec, const double *r, void *stream,
+                              char *report, size_t report_len);
+
 #ifdef __cplusplus
 }
 #endif

@@ -59,6 +59,17 @@ _SIGS = {
     "fts_hierarchy_set_omega": (_I32, [_VP, _VP]),
     "fts_hierarchy_enable_adjoint": (_I32, [_VP]),
     "fts_vcycle_adjoint": (_I32, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "fts_batch_create": (_I32, [_VP, _I32, _VP]),
+    "fts_batch_destroy": (_I32, [_VP]),
+    "fts_batch_ndofs": (_I64, [_VP]),
+    "fts_batch_mesh_offset": (_I32, [_VP, _I32, _VP, _VP]),
+    "fts_batch_residual": (_I32, [_VP, _VP, _VP, _VP, _VP]),
+    "fts_batch_apply": (_I32, [_VP, _D, _I32, _VP, _VP, _VP]),
+    "fts_batch_ws_bytes": (_SZ, [_VP]),
+    "fts_batch_smooth": (_I32, [_VP, _D, _I32, _VP, _VP, _I32, _VP, _SZ, _VP]),
+    "fts_batch_set_launch": (_I32, [_VP, _I32, _I32, _I32]),
+    "fts_batch_get_launch": (_I32, [_VP, _VP, _VP, _VP]),
+    "fts_batch_autotune": (_I32, [_VP, _I32, _VP, _VP, ctypes.c_char_p, _SZ]),
     "fts_pcg": (_I32, [_VP, _I32, _VP, _VP, _D, _I32, _VP, _SZ, _VP, _VP, _VP, _VP]),
 }
 
@@ -282,6 +293,71 @@ class Hierarchy:
         _check(lib().fts_coarse_solve(self._h, _ptr(b0, n0, "b0"), _ptr(x0, n0, "x0"), _stream()),
                "fts_coarse_solve")
         return x0
+
+
+class Batch:
+    """Many independent 3-D meshes smoothed together (fts_batch_*).
+    meshes: list of (k, widths, gamma_hat)."""
+
+    def __init__(self, meshes):
+        descs = (MeshDesc * len(meshes))()
+        self._keep = []
+        for i, (k, widths, gh) in enumerate(meshes):
+            d, ws = _desc(3, k, widths, gh)
+            descs[i] = d
+            self._keep.append(ws)
+        h = ctypes.c_void_p()
+        _check(lib().fts_batch_create(descs, len(meshes), ctypes.byref(h)), "fts_batch_create")
+        self._h = h
+        self.nmesh = len(meshes)
+        self.ndofs = int(lib().fts_batch_ndofs(self._h))
+        self.offsets = []
+        for i in range(self.nmesh):
+            off, n = ctypes.c_int64(), ctypes.c_int64()
+            _check(lib().fts_batch_mesh_offset(self._h, i, ctypes.byref(off), ctypes.byref(n)), "fts_batch_mesh_offset")
+            self.offsets.append((off.value, n.value))
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.fts_batch_destroy(self._h)
+            self._h = None
+
+    def residual(self, b, x, r):
+        n = self.ndofs
+        _check(lib().fts_batch_residual(self._h, _ptr(b, n, "b"), _ptr(x, n, "x"), _ptr(r, n, "r"), _stream()),
+               "fts_batch_residual")
+        return r
+
+    def apply(self, omega, r, x, prec="f32"):
+        n = self.ndofs
+        _check(lib().fts_batch_apply(self._h, float(omega), PREC[prec], _ptr(r, n, "r"), _ptr(x, n, "x"),
+                                     _stream()), "fts_batch_apply")
+        return x
+
+    def smooth(self, omega, b, x, nsweeps=1, prec="f32", ws=None):
+        import torch
+        n = self.ndofs
+        if ws is None:
+            ws = torch.empty(n, dtype=torch.float64, device=x.device)
+        _check(lib().fts_batch_smooth(self._h, float(omega), PREC[prec], _ptr(b, n, "b"), _ptr(x, n, "x"),
+                                      int(nsweeps), _ptr(ws, None, "ws"), ws.numel() * 8, _stream()),
+               "fts_batch_smooth")
+        return x
+
+    def set_launch(self, threads, grid, chunk):
+        _check(lib().fts_batch_set_launch(self._h, threads, grid, chunk), "fts_batch_set_launch")
+
+    def get_launch(self):
+        t, g, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().fts_batch_get_launch(self._h, ctypes.byref(t), ctypes.byref(g), ctypes.byref(c)),
+               "fts_batch_get_launch")
+        return t.value, g.value, c.value
+
+    def autotune(self, r, prec="f32"):
+        buf = ctypes.create_string_buffer(8192)
+        _check(lib().fts_batch_autotune(self._h, PREC[prec], _ptr(r, self.ndofs, "r"), _stream(), buf, 8192),
+               "fts_batch_autotune")
+        return buf.value.decode()
 
 
 class VCycleIterations:

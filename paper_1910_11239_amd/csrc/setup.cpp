@@ -429,7 +429,10 @@ fts_status fts_level_destroy(fts_level *level) {
 
 int64_t fts_level_ndofs(const fts_level *level) { return level ? level->ndofs : -1; }
 
-fts_status fts_setup_1d_eigs(const fts_level *lv, fts_patch_kind kind, fts_eigs **out) {
+}  // extern "C"
+
+namespace fts {
+fts_status setup_eigs_internal(const fts_level *lv, fts_patch_kind kind, bool staging, fts_eigs **out) {
     if (!lv || !out) return fail(FTS_E_INVAL, "fts_setup_1d_eigs: NULL argument");
     *out = nullptr;
     if (kind != FTS_CELL && kind != FTS_VERTEX_PATCH) return fail(FTS_E_INVAL, "unknown patch kind");
@@ -624,7 +627,7 @@ fts_status fts_setup_1d_eigs(const fts_level *lv, fts_patch_kind kind, fts_eigs 
             return fail(FTS_E_HIP, "upload of the MFMA tables failed");
         }
     }
-    if (kind == FTS_VERTEX_PATCH) {
+    if (kind == FTS_VERTEX_PATCH && staging) {
         int64_t nsub = 1;
         for (int a = 0; a < lv->dim; ++a) nsub *= eg->count[a];
         const size_t bytes = (size_t)nsub * (1u << lv->dim) * (lv->ndofs / lv->ncells) * sizeof(double);
@@ -640,10 +643,20 @@ fts_status fts_setup_1d_eigs(const fts_level *lv, fts_patch_kind kind, fts_eigs 
     return FTS_OK;
 }
 
+}  // namespace fts
+
+extern "C" {
+
+fts_status fts_setup_1d_eigs(const fts_level *lv, fts_patch_kind kind, fts_eigs **out) {
+    return setup_eigs_internal(lv, kind, true, out);
+}
+
 fts_status fts_eigs_set_schedule(fts_eigs *eigs, int32_t schedule) {
     if (!eigs) return fail(FTS_E_INVAL, "fts_eigs_set_schedule: NULL handle");
     if (schedule != FTS_SCHEDULE_STAGED && schedule != FTS_SCHEDULE_COLORED)
         return fail(FTS_E_INVAL, "fts_eigs_set_schedule: unknown schedule");
+    if (schedule == FTS_SCHEDULE_STAGED && eigs->kind == FTS_VERTEX_PATCH && !eigs->d_stage)
+        return fail(FTS_E_INVAL, "fts_eigs_set_schedule: these eigen-data have no staging buffer");
     eigs->schedule = schedule;
     return FTS_OK;
 }
