@@ -116,6 +116,39 @@ def mixed_vs_fp64(steps_hint=1):
             "setup_s": setup_s, "by_precision": out}
 
 
+def batched_workload():
+    """64 independent 3-D meshes (k ~ U{2..9}, m ~ U{8..24} cells per axis,
+    per-slab widths log-uniform in [0.25, 4]): one sweep = FP64 residual + FP32
+    local solves in one persistent launch + batched gather, after autotuning
+    the persistent launch shape."""
+    import torch
+    import paper_1910_11239_amd as fts
+    from synthetic import batched_meshes
+    specs = batched_meshes()
+    t0 = time.perf_counter()
+    batch = fts.Batch([(k, w, 1.0) for k, w in specs])
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    N = batch.ndofs
+    b = torch.as_tensor(random_vector(N, 0)).cuda()
+    x = torch.zeros(N, dtype=torch.float64, device="cuda")
+    r = torch.empty_like(x)
+    batch.residual(b, x, r)
+    report = batch.autotune(r, prec="f32")
+    flops = sum(wm.smoother_flops(3, k, tuple(len(a) for a in w), "vertex") for k, w in specs)
+    t_apply = _events_time(lambda: batch.apply(0.125, r, x, prec="f32"), 5)
+    t_res = _events_time(lambda: batch.residual(b, x, r), 5)
+    ws = torch.empty_like(x)
+    t_sweep = _events_time(lambda: batch.smooth(0.125, b, x, 1, prec="f32", ws=ws), 5)
+    del batch
+    torch.cuda.empty_cache()
+    return {"workload": "batched: 64 meshes, k ~ U{2..9}, m ~ U{8..24}^3, widths log-uniform [0.25, 4] per slab",
+            "dofs": N, "degrees": sorted({k for k, _ in specs}), "setup_s": setup_s,
+            "sweep_ms": t_sweep, "sweep_dofs_per_s": N / (t_sweep * 1e-3),
+            "apply_ms": t_apply, "apply_fp32_tflops": flops / (t_apply * 1e-3) / 1e12,
+            "residual_ms": t_res, "launch": report.strip().splitlines()[-1]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +156,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the 48^3 Q7 mixed-precision CG comparison")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-mesh batched sweep")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + steps of the V-cycle only (for rocprofv3)")
     args = ap.parse_args()
@@ -231,6 +265,8 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_mixed:
         out["mixed_vs_fp64"] = mixed_vs_fp64()
+    if not args.no_batched:
+        out["batched"] = batched_workload()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out))
