@@ -317,8 +317,7 @@ fts_status fts_batch_create(const fts_mesh_desc *meshes, int32_t nmesh, fts_batc
         std::vector<BatchBlock> blocks;
         for (int i = 0; i < nmesh; ++i) {
             if (host[i].n1 != n1) continue;
-            const int ppb = n1 * n1 <= 64 ? 64 / (n1 * n1) : 1;
-            for (int64_t c = 0; c < bt->levels[i]->ncells; c += ppb) blocks.push_back({i, 0, c});
+            for (int64_t c = 0; c < bt->levels[i]->ncells; ++c) blocks.push_back({i, 0, c});  // one cell per block
         }
         if (blocks.empty()) continue;
         fts_batch::Group g{n1, nullptr, (int64_t)blocks.size()};

@@ -46,21 +46,22 @@ __device__ __forceinline__ void cell_coords(int64_t cell, const int *m, int *c) 
 //   (A x)_K = sum_t (prod_{s != t} h_s) (Mhat x..x W_t x..x Mhat)
 //   W_t = A_t^K x_K + B_t(K, K+e_t) x_{K+e_t} + B_t(K-e_t, K)^T x_{K-e_t}
 // with the 1-D cell operator A_t^K (both faces' Nitsche terms) and the
-// interface blocks B_t.  Each block of PPB cells: 1) every thread applies the
-// 1-D operator along one line of its cell for each axis, reading the
-// neighbour lines from global memory; 2) the transverse mass matrices are
-// applied line by line in LDS.
+// interface blocks B_t.  One cell per workgroup (operator_block below): the
+// cell and its face neighbours are staged in LDS, every thread applies the
+// 1-D operators along one line of the cell for each axis, then the transverse
+// mass matrices are applied line by line in LDS.
 template <int D, int N1>
 struct OpCfg {
     static constexpr int NC = ipow(N1, D);
     static constexpr int LINES = ipow(N1, D - 1);
+    // one cell per workgroup: every 1-D table address is uniform (scalar loads)
     static constexpr int THREADS = LINES <= 64 ? 64 : rup64(LINES);
-    static constexpr int PPB = THREADS / LINES;
+    static constexpr int PPB = 1;
 };
 
-template <int D, int N1>
-__device__ __forceinline__ void mass_line(const double *src, double *dst, int a, int l, double scale,
-                                          const double *Mh, bool acc) {
+template <int D, int N1, typename P>
+__device__ __forceinline__ void mass_line(const double *src, double *dst, int a, int l, double scale, P Mh,
+                                          bool acc) {
     const int base = line_base<D, N1>(a, l), st = line_stride<N1>(a);
     double in[N1];
 #pragma unroll
@@ -69,7 +70,7 @@ __device__ __forceinline__ void mass_line(const double *src, double *dst, int a,
     for (int o = 0; o < N1; ++o) {
         double s = 0.0;
 #pragma unroll
-        for (int i = 0; i < N1; ++i) s = fma(Mh[o * N1 + i], in[i], s);
+        for (int i = 0; i < N1; ++i) s = fma((double)Mh[o * N1 + i], in[i], s);
         s *= scale;
         dst[base + o * st] = acc ? dst[base + o * st] + s : s;
     }
@@ -181,100 +182,155 @@ inline fts_status check_launch(const char *what) {
 
 
 // Body of the operator for the PPB cells cell0.. of the mesh described by g
-// (x, b, y: that mesh's vectors).  Shared by the single-mesh and the batched kernels.
+// (x, b, y: that mesh's vectors).  Shared by the single-mesh and the batched
+// kernels.  The block's cells and their 2d face neighbours are first copied
+// into LDS with coalesced whole-cell loads (slot 0 = the cell, slots 1..2d =
+// neighbours -x, +x, -y, +y, -z, +z; absent neighbours are skipped); each
+// thread then applies the 1-D operators along its line of each axis
+// (cell block + the two interface blocks), keeps the d results in registers,
+// and after a barrier the transverse mass matrices are applied in LDS reusing
+// the neighbour slots.
 template <int D, int N1, bool RES>
 __device__ __forceinline__ void operator_block(const LevelView &g, int64_t cell0, const double *__restrict__ x,
                                                const double *__restrict__ b, double *__restrict__ y) {
     using C = OpCfg<D, N1>;
     constexpr int NC = C::NC, LINES = C::LINES, PPB = C::PPB, TH = C::THREADS;
-    __shared__ double X[PPB * NC];
-    __shared__ double W[D][PPB * NC];
-    __shared__ double U[PPB * NC];
+    constexpr int NS = 2 * D + 1;  // LDS slots per cell
+    __shared__ double S[PPB][NS][NC];
+    __shared__ int64_t src_cell[PPB][NS];  // -1: absent
     const int t = threadIdx.x;
     const int q = t / LINES, l = t % LINES;
-    for (int p = t; p < PPB * NC; p += TH) {
-        const int64_t cc = cell0 + p / NC;
-        X[p] = cc < g.ncells ? x[cc * NC + p % NC] : 0.0;
+    const int64_t cs[3] = {1, g.m[0], (int64_t)g.m[0] * g.m[1]};
+    for (int e = t; e < PPB * NS; e += TH) {
+        const int qq = e / NS, slot = e % NS;
+        const int64_t cc = cell0 + qq;
+        int64_t src = cc < g.ncells ? cc : -1;
+        if (src >= 0 && slot > 0) {
+            int c3[3];
+            cell_coords(cc, g.m, c3);
+            const int a = (slot - 1) >> 1, dir = (slot - 1) & 1;  // dir 0: -e_a, 1: +e_a
+            const int nb = c3[a] + (dir ? 1 : -1);
+            src = (nb < 0 || nb >= g.m[a]) ? -1 : cc + (dir ? cs[a] : -cs[a]);
+        }
+        src_cell[qq][slot] = src;
+    }
+    __syncthreads();
+    // stage cells and neighbours (whole cells, coalesced); loads are issued in
+    // chunks of independent registers before the LDS stores
+    constexpr int TOT = PPB * NS * NC, ITER = (TOT + TH - 1) / TH, CH = 8;
+#pragma unroll
+    for (int k0 = 0; k0 < ITER; k0 += CH) {
+        double v[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int p = t + (k0 + k) * TH;
+            v[k] = 0.0;
+            if (k0 + k < ITER && p < TOT) {
+                const int qs = p / NC, i = p % NC;
+                const int64_t src = src_cell[qs / NS][qs % NS];
+                if (src >= 0) v[k] = x[src * NC + i];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int p = t + (k0 + k) * TH;
+            if (k0 + k < ITER && p < TOT) {
+                const int qs = p / NC, i = p % NC;
+                S[qs / NS][qs % NS][i] = v[k];
+            }
+        }
     }
     __syncthreads();
     const int64_t cell = cell0 + q;
     const bool act = (q < PPB) && (cell < g.ncells);
+    // PPB == 1: the cell, its coordinates and all table addresses are uniform
     int c[3] = {0, 0, 0};
-    if (act) cell_coords(cell, g.m, c);
-    const int64_t cs[3] = {1, g.m[0], (int64_t)g.m[0] * g.m[1]};
-    const double hx = act ? g.h[0][c[0]] : 0.0, hy = act ? g.h[1][c[1]] : 0.0;
-    const double hz = (D == 3 && act) ? g.h[2][c[2]] : 1.0;
-    const int qo = q * NC;
+    cell_coords(cell0 < g.ncells ? cell0 : 0, g.m, c);
+    for (int a = 0; a < 3; ++a) c[a] = __builtin_amdgcn_readfirstlane(c[a]);
+    const double hx = uniform_table(g.h[0])[c[0]], hy = uniform_table(g.h[1])[c[1]];
+    const double hz = D == 3 ? (double)uniform_table(g.h[2])[c[2]] : 1.0;
+    double w[D][N1];
     if (act) {
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             const int base = line_base<D, N1>(a, l), st = line_stride<N1>(a);
-            double in[N1], out[N1];
+            double in[N1];
 #pragma unroll
-            for (int i = 0; i < N1; ++i) in[i] = X[qo + base + i * st];
-            const double *A = g.cellop[a] + (size_t)c[a] * N1 * N1;
+            for (int i = 0; i < N1; ++i) in[i] = S[q][0][base + i * st];
+            cptr<double> A = uniform_table(g.cellop[a] + (size_t)c[a] * N1 * N1);
 #pragma unroll
             for (int o = 0; o < N1; ++o) {
                 double s = 0.0;
 #pragma unroll
-                for (int i = 0; i < N1; ++i) s = fma(A[o * N1 + i], in[i], s);
-                out[o] = s;
+                for (int i = 0; i < N1; ++i) s = fma((double)A[o * N1 + i], in[i], s);
+                w[a][o] = s;
             }
             if (c[a] + 1 < g.m[a]) {
-                const double *nb = x + (cell + cs[a]) * NC;
 #pragma unroll
-                for (int i = 0; i < N1; ++i) in[i] = nb[base + i * st];
-                const double *B = g.iface[a] + (size_t)c[a] * N1 * N1;
+                for (int i = 0; i < N1; ++i) in[i] = S[q][2 + 2 * a][base + i * st];
+                cptr<double> B = uniform_table(g.iface[a] + (size_t)c[a] * N1 * N1);
 #pragma unroll
                 for (int o = 0; o < N1; ++o)
 #pragma unroll
-                    for (int i = 0; i < N1; ++i) out[o] = fma(B[o * N1 + i], in[i], out[o]);
+                    for (int i = 0; i < N1; ++i) w[a][o] = fma((double)B[o * N1 + i], in[i], w[a][o]);
             }
             if (c[a] > 0) {
-                const double *nb = x + (cell - cs[a]) * NC;
 #pragma unroll
-                for (int i = 0; i < N1; ++i) in[i] = nb[base + i * st];
-                const double *B = g.iface[a] + (size_t)(c[a] - 1) * N1 * N1;
+                for (int i = 0; i < N1; ++i) in[i] = S[q][1 + 2 * a][base + i * st];
+                cptr<double> B = uniform_table(g.iface[a] + (size_t)(c[a] - 1) * N1 * N1);
 #pragma unroll
                 for (int o = 0; o < N1; ++o)
 #pragma unroll
-                    for (int i = 0; i < N1; ++i) out[o] = fma(B[i * N1 + o], in[i], out[o]);
+                    for (int i = 0; i < N1; ++i) w[a][o] = fma((double)B[i * N1 + o], in[i], w[a][o]);
             }
+        }
+    }
+    __syncthreads();  // neighbour slots are free from here on
+    double *W0 = S[q][1], *W1 = S[q][2], *U = D == 3 ? S[q][4] : S[q][3];
+    if (act) {
 #pragma unroll
-            for (int o = 0; o < N1; ++o) W[a][qo + base + o * st] = out[o];
+        for (int a = 0; a < D; ++a) {
+            const int base = line_base<D, N1>(a, l), st = line_stride<N1>(a);
+            double *Wa = S[q][1 + a];
+#pragma unroll
+            for (int o = 0; o < N1; ++o) Wa[base + o * st] = w[a][o];
         }
     }
     __syncthreads();
-    const double *Mh = g.Mhat;
+    cptr<double> Mh = uniform_table(g.Mhat);
     double *Y;
     if constexpr (D == 2) {
-        if (act) mass_line<D, N1>(W[0] + qo, U + qo, 1, l, hy, Mh, false);
+        if (act) mass_line<D, N1>(W0, U, 1, l, hy, Mh, false);
         __syncthreads();
-        if (act) mass_line<D, N1>(W[1] + qo, U + qo, 0, l, hx, Mh, true);
+        if (act) mass_line<D, N1>(W1, U, 0, l, hx, Mh, true);
         __syncthreads();
         Y = U;
     } else {
-        // U = hy hz (Mhat_y W_x) + hx hz (Mhat_x W_y);  X = Mhat_y W_z
-        if (act) mass_line<D, N1>(W[0] + qo, U + qo, 1, l, hy * hz, Mh, false);
+        double *W2 = S[q][3], *X2 = S[q][5];
+        // U = hy hz (Mhat_y W_x) + hx hz (Mhat_x W_y);  X2 = Mhat_y W_z
+        if (act) mass_line<D, N1>(W0, U, 1, l, hy * hz, Mh, false);
         __syncthreads();
         if (act) {
-            mass_line<D, N1>(W[1] + qo, U + qo, 0, l, hx * hz, Mh, true);
-            mass_line<D, N1>(W[2] + qo, X + qo, 1, l, 1.0, Mh, false);
+            mass_line<D, N1>(W1, U, 0, l, hx * hz, Mh, true);
+            mass_line<D, N1>(W2, X2, 1, l, 1.0, Mh, false);
         }
         __syncthreads();
-        // W0 = Mhat_z U
-        if (act) mass_line<D, N1>(U + qo, W[0] + qo, 2, l, 1.0, Mh, false);
+        // W0 = Mhat_z U;  W0 += hx hy Mhat_x X2
+        if (act) mass_line<D, N1>(U, W0, 2, l, 1.0, Mh, false);
         __syncthreads();
-        // W0 += hx hy Mhat_x X
-        if (act) mass_line<D, N1>(X + qo, W[0] + qo, 0, l, hx * hy, Mh, true);
+        if (act) mass_line<D, N1>(X2, W0, 0, l, hx * hy, Mh, true);
         __syncthreads();
-        Y = W[0];
+        Y = W0;
     }
+    (void)Y;
     for (int p = t; p < PPB * NC; p += TH) {
-        const int64_t cc = cell0 + p / NC;
+        const int qq = p / NC, i = p % NC;
+        const int64_t cc = cell0 + qq;
         if (cc < g.ncells) {
-            const int64_t gi = cc * NC + p % NC;
-            y[gi] = RES ? b[gi] - Y[p] : Y[p];
+            const int64_t gi = cc * NC + i;
+            const double v = S[qq][1][i];  // W0 of cell qq holds the result (U for 2-D)
+            const double yv = D == 3 ? v : S[qq][3][i];
+            y[gi] = RES ? b[gi] - yv : yv;
         }
     }
 }
