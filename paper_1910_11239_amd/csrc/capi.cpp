@@ -4,13 +4,6 @@
 
 #include "fts_internal.h"
 
-namespace fts {
-fts_status coarse_factor(double *A, int64_t N, hipStream_t stream);
-fts_status coarse_solve(const double *F, int64_t N, const double *b, double *x, double *y, double *P,
-                        hipStream_t stream);
-int coarse_ncb(int64_t N);
-}  // namespace fts
-
 using namespace fts;
 
 struct fts_hierarchy {
@@ -21,8 +14,7 @@ struct fts_hierarchy {
     std::vector<fts_level *> levels;  // 0 = coarsest
     std::vector<fts_eigs *> eigs;     // eigs[0] = nullptr
     std::vector<double *> vb, vx, vr;  // per-level vectors (b, x for l < L; r for every l)
-    double *LU = nullptr;   // inverse triangular factors of A_0 (see coarse.hip)
-    double *cy = nullptr, *cP = nullptr;  // coarse-solve workspaces
+    CoarseLU *coarse = nullptr;  // direct solver of A_0 (coarse.hip)
     int64_t N0 = 0;
     double *host_scalars = nullptr;       // pinned readback buffer of the CG reductions
     // adjoint workspaces (fts_hierarchy_enable_adjoint)
@@ -111,9 +103,7 @@ fts_status fts_hierarchy_destroy(fts_hierarchy *h) {
     for (auto *p : h->vb) if (p) hipFree(p);
     for (auto *p : h->vx) if (p) hipFree(p);
     for (auto *p : h->vr) if (p) hipFree(p);
-    if (h->LU) hipFree(h->LU);
-    if (h->cy) hipFree(h->cy);
-    if (h->cP) hipFree(h->cP);
+    coarse_destroy(h->coarse);
     if (h->host_scalars) hipHostFree(h->host_scalars);
     for (auto &v : h->xs)
         for (auto *p : v) if (p) hipFree(p);
@@ -196,14 +186,7 @@ fts_status fts_hierarchy_create(const fts_mesh_desc *finest, int32_t nlevels, ft
         const fts_level *l0 = h->levels[0];
         const int64_t N = l0->ndofs;
         h->N0 = N;
-        if (hipMalloc(&h->LU, (size_t)N * N * sizeof(double)) != hipSuccess ||
-            hipMalloc(&h->cy, (size_t)N * sizeof(double)) != hipSuccess ||
-            hipMalloc(&h->cP, (size_t)coarse_ncb(N) * N * sizeof(double)) != hipSuccess)
-            st = fail(FTS_E_HIP, "hipMalloc of the coarse factor failed");
-        hipStream_t s0 = nullptr;
-        if (st == FTS_OK) st = launch_fill(h->LU, N * N, 0.0, s0);
-        if (st == FTS_OK) st = launch_assemble_dense(l0, h->LU, s0);
-        if (st == FTS_OK) st = coarse_factor(h->LU, N, s0);
+        st = coarse_create(l0, nullptr, &h->coarse);
         if (st == FTS_OK && hipHostMalloc(&h->host_scalars, 4 * sizeof(double)) != hipSuccess)
             st = fail(FTS_E_HIP, "hipHostMalloc of the readback buffer failed");
     }
@@ -224,11 +207,11 @@ const fts_eigs *fts_hierarchy_eigs(const fts_hierarchy *h, int32_t l) {
 
 fts_status fts_coarse_solve(fts_hierarchy *h, const double *b0, double *x0, void *stream) {
     if (!h || !b0 || !x0) return fail(FTS_E_INVAL, "fts_coarse_solve: NULL argument");
-    return coarse_solve(h->LU, h->N0, b0, x0, h->cy, h->cP, S(stream));
+    return coarse_solve(h->coarse, b0, x0, S(stream));
 }
 
 static fts_status vcycle_level(fts_hierarchy *h, int l, fts_prec prec, const double *b, double *x, hipStream_t s) {
-    if (l == 0) return coarse_solve(h->LU, h->N0, b, x, h->cy, h->cP, s);
+    if (l == 0) return coarse_solve(h->coarse, b, x, s);
     const fts_level *lv = h->levels[l];
     const fts_eigs *eg = h->eigs[l];
     double *r = h->vr[l];
@@ -369,7 +352,7 @@ static fts_status adj_forward(fts_hierarchy *h, int l, const double *x_in, const
     const int64_t n = lv->ndofs;
     auto &X = h->xs[l];
     fts_status st = FTS_OK;
-    if (l == 0) return coarse_solve(h->LU, h->N0, b, X[0], h->cy, h->cP, s);
+    if (l == 0) return coarse_solve(h->coarse, b, X[0], s);
     if (x_in) {
         FTS_HIP_CHECK(hipMemcpyAsync(X[0], x_in, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     } else {
@@ -432,7 +415,7 @@ static fts_status adj_reverse(fts_hierarchy *h, int l, const double *b, hipStrea
     fts_status st = FTS_OK;
     if (l == 0) {
         // x0 = A0^-1 b0: lam_b0 = A0^-1 lam; d gamma_0 -= lam_b0 . (A1 x0); lam_x = 0
-        st = coarse_solve(h->LU, h->N0, h->lam[0], h->lamb[0], h->cy, h->cP, s);
+        st = coarse_solve(h->coarse, h->lam[0], h->lamb[0], s);
         if (st == FTS_OK) st = launch_operator_penalty(lv, h->xs[0][0], h->at[0], s);
         if (st == FTS_OK) st = launch_dot_acc(h->lamb[0], h->at[0], n, -1.0, h->ared, h->agrad + 1, s);
         if (st == FTS_OK) st = launch_fill(h->lam[0], n, 0.0, s);

@@ -1,30 +1,56 @@
-// Dense LU of the coarsest-level matrix and the two triangular solves of the
-// coarse solve (Alg. gmg, level 0).  The factor is column-major with leading
-// dimension N, overwritten in place: unit lower L below the diagonal, U on
-// and above it.  No pivoting: A_0 is symmetric positive definite, for which
-// Gaussian elimination without pivoting is stable.
+// Direct solver of the coarsest level (Alg. gmg, level 0): LU factorisation
+// of A_0 without pivoting, applied by forward and backward substitution.  A_0
+// is symmetric positive definite, for which elimination without pivoting is
+// stable.
 //
-// Factorisation (setup, once): blocks of NB columns; the diagonal block is
-// factored by one workgroup, the two panels by triangular solves and the
-// trailing matrix by a GEMM (library BLAS-3, setup only).  Afterwards the
-// inverses of all diagonal blocks of L and U are formed, so that each step
-// of the triangular solves is a matrix-vector product.
+// Structure.  Unknowns are numbered cell by cell with the last axis slowest,
+// so each slab of cells (one coordinate along the last axis) is a contiguous
+// range of B unknowns and couples only to its two neighbouring slabs: A_0 is
+// block tridiagonal over the nb slabs (SlabBlocks).  Elimination creates no
+// fill outside that band, so the factors are block bidiagonal,
+//     L: diagonal L_ii, below it Lo_i = A_{i+1,i} U_ii^-1,
+//     U: diagonal U_ii, above it Up_i = L_ii^-1 A_{i,i+1},
+// the same numbers a dense LU of A_0 produces, with the exact zeros left out.
+// Between two slabs a cell couples only to the cell at the same position, so
+// Lo_i is zero where the column's cell precedes the row's cell and Up_i is
+// zero where it follows it.
 //
-// Triangular solve (every V-cycle): one launch per block step.  Step s of
-// the forward solve finalises block s (head workgroup: subtract column block
-// s-1, then multiply by inv(L_ss)) while the other workgroups subtract column
-// block s-1 from all rows below block s.  The backward solve mirrors it.
-// Every launch streams its column panel once with coalesced column-major
-// reads, so a full solve reads the factor once (8 N^2 bytes).
+// Setup (once): block elimination over the slabs with library BLAS-3 (GEMM,
+// TRSM) and a one-workgroup kernel for the small diagonal panels; then the
+// diagonal factors are replaced by their inverses (strict lower part
+// inv(L_ii) with unit diagonal implied, upper part inv(U_ii)), so every step
+// of the substitution is a matrix-vector product.
+//
+// Solve (every V-cycle): 2 (2 nb - 1) mat-vec launches
+//     forward   y_0 = inv(L_00) b_0,          y_i = inv(L_ii) (b_i - Lo_{i-1} y_{i-1})
+//     backward  x_last = inv(U) y_last,       x_i = inv(U_ii) (y_i - Up_i x_{i+1})
+// each reading the live part of its block once: 8 B^2 (2 nb - 1) bytes per
+// solve instead of the 8 N^2 of dense triangular factors (N = nb B).
 #include <rocblas/rocblas.h>
 
-#include "fts_internal.h"
+#include <climits>
+
+#include "device_common.h"
 
 namespace fts {
 
-constexpr int kNB = 256;         // block size of factor and solves
-constexpr int kRowsPerWG = 64;   // rows per non-head workgroup in a solve step
-constexpr int kColGroups = 4;    // column groups per workgroup (256 threads)
+struct CoarseLU {
+    int64_t N = 0;
+    int B = 0, nb = 0, nc = 0;  // slab size, number of slabs, unknowns per cell
+    double *D = nullptr;         // nb blocks: packed inv(L_ii), inv(U_ii)
+    double *Lo = nullptr;        // nb - 1 blocks Lo_i
+    double *Up = nullptr;        // nb - 1 blocks Up_i
+    double *y = nullptr;         // N: result of the forward substitution
+    double *t = nullptr;         // B: right-hand side of the current diagonal step
+};
+
+constexpr int kNB = 256;  // panel width of the factorisation
+
+#define COARSE_TRY(expr)                  \
+    do {                                  \
+        const fts_status s_ = (expr);     \
+        if (s_ != FTS_OK) return s_;      \
+    } while (0)
 
 __global__ void __launch_bounds__(1024) k_lu_diag(double *__restrict__ A, int64_t lda, int kb) {
     const int tid = threadIdx.x;
@@ -41,108 +67,166 @@ __global__ void __launch_bounds__(1024) k_lu_diag(double *__restrict__ A, int64_
     }
 }
 
-// Triangular matrix-vector products with the inverted factors stored in the
-// LU buffer: strictly below the diagonal inv(L) (unit diagonal implied), on
-// and above it inv(U).  Tiles of TR rows x TC columns; a workgroup owns one
-// tile, each thread two consecutive rows (16-byte loads), columns streamed
-// with non-temporal coalesced column-major reads and independent partial
-// sums; tile results go to P[column block][row] and are summed in a fixed
-// order by k_tri_reduce (deterministic).  A tile is live when it holds an
-// entry of the triangle; both kernels use the same column-block range.
-constexpr int kTR = 512, kTC = 1024, kUnroll = 8;
+// ---------------------------------------------------------------------------
+// Block mat-vec out = base + sgn * (M v) over one B x B block M stored
+// row-major, restricted to the block's nonzero part.  Row r of each part
+// occupies one contiguous column range:
+//     kLowerInv  strict lower part of a packed diagonal block: [0, r)
+//                (the unit diagonal comes in through base = v)
+//     kUpperInv  upper part of a packed diagonal block:        [r, B)
+//     kBelow     Lo_i, zero left of the row's cell:             [cell(r) nc, B)
+//     kAbove     Up_i, zero right of the row's cell:            [0, (cell(r) + 1) nc)
+// The rows are cut into groups of kRows; a workgroup owns group g and group
+// G-1-g, a short and a long range, so every workgroup streams about the same
+// number of bytes.  Its four waves take interleaved passes of 64 lanes x two
+// columns over the two ranges (16-byte non-temporal loads, one per row and
+// lane), keep one partial per row and lane, reduce across lanes with
+// shuffles and across waves in LDS in a fixed order: no atomics, and the
+// result does not depend on timing.
+constexpr int kRows = 8, kMvWaves = 4;
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ int live_lo(bool lower, int64_t rb0) { return lower ? 0 : (int)(rb0 / kTC); }
-__device__ __forceinline__ int live_hi(bool lower, int64_t rb0, int ncb) {
-    return lower ? (int)std::min<int64_t>(ncb, (rb0 + kTR + kTC - 1) / kTC) : ncb;
+enum BlockPart { kLowerInv = 0, kUpperInv = 1, kBelow = 2, kAbove = 3 };
+
+// Column range [lo, hi) covering the nonzero parts of rows [r0, r1].
+template <int PART>
+__device__ __forceinline__ void group_range(int r0, int r1, int B, int nc, int &lo, int &hi) {
+    if (PART == kLowerInv) lo = 0, hi = r1;
+    else if (PART == kUpperInv) lo = r0, hi = B;
+    else if (PART == kBelow) lo = (r0 / nc) * nc, hi = B;
+    else lo = 0, hi = (r1 / nc + 1) * nc;
 }
 
-template <bool LOWER>
-__global__ void __launch_bounds__(256) k_tri_partial(const double *__restrict__ F, int64_t N,
-                                                     const double *__restrict__ v, double *__restrict__ P) {
-    __shared__ double vs[kTC];
-    const int64_t r0 = (int64_t)blockIdx.y * kTR;
-    const int cb = blockIdx.x;
-    if (cb < live_lo(LOWER, r0) || cb >= live_hi(LOWER, r0, gridDim.x)) return;
-    const int64_t c0 = (int64_t)cb * kTC;
-    for (int j = threadIdx.x; j < kTC; j += 256) vs[j] = (c0 + j < N) ? v[c0 + j] : 0.0;
+// Entry (row, col) of the union range that lies outside the row's own part.
+// Only the packed diagonal blocks need this: the off-diagonal blocks store
+// their zeros.
+template <int PART>
+__device__ __forceinline__ bool outside(int row, int col) {
+    if (PART == kLowerInv) return col >= row;
+    if (PART == kUpperInv) return col < row;
+    return false;
+}
+
+template <int PART, bool PAIR>
+__device__ __forceinline__ void stream_pass(const double *__restrict__ M, int B, const double *__restrict__ v,
+                                            int r0, int r1, int j, bool ok, double *acc) {
+    // rows r0 .. r0 + kRows - 1, clamped to r1 for the loads (their results are dropped)
+    if (PAIR) {
+        const dvec2 x = *(const dvec2 *)(v + j);
+        dvec2 m[kRows];
+#pragma unroll
+        for (int q = 0; q < kRows; ++q)
+            m[q] = __builtin_nontemporal_load((const dvec2 *)(M + (int64_t)min(r0 + q, r1) * B + j));
+#pragma unroll
+        for (int q = 0; q < kRows; ++q) {
+            const double mx = (ok && !outside<PART>(r0 + q, j)) ? m[q].x : 0.0;
+            const double my = (ok && !outside<PART>(r0 + q, j + 1)) ? m[q].y : 0.0;
+            acc[q] = fma(my, x.y, fma(mx, x.x, acc[q]));
+        }
+    } else {
+        const double x = v[j];
+        double m[kRows];
+#pragma unroll
+        for (int q = 0; q < kRows; ++q) m[q] = M[(int64_t)min(r0 + q, r1) * B + j];
+#pragma unroll
+        for (int q = 0; q < kRows; ++q) acc[q] = fma((ok && !outside<PART>(r0 + q, j)) ? m[q] : 0.0, x, acc[q]);
+    }
+}
+
+template <int PART, bool PAIR>
+__global__ void __launch_bounds__(256) k_slab_mv(const double *__restrict__ M, int B, int nc, int G,
+                                                 const double *__restrict__ v, const double *base, double sgn,
+                                                 double *__restrict__ out) {
+    constexpr int CPL = PAIR ? 2 : 1, PC = 64 * CPL;  // columns per lane / per wave pass
+    __shared__ double red[kMvWaves][2 * kRows];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ga = blockIdx.x, gb = G - 1 - blockIdx.x;  // gb == ga: a single group
+    int r0[2], r1[2], lo[2], hi[2], np[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int g = s == 0 ? ga : gb;
+        r0[s] = g * kRows;
+        r1[s] = min(r0[s] + kRows, B) - 1;
+        group_range<PART>(r0[s], r1[s], B, nc, lo[s], hi[s]);
+        if (PAIR) lo[s] &= ~1, hi[s] = min(B, (hi[s] + 1) & ~1);
+        np[s] = (s == 1 && gb == ga) || hi[s] <= lo[s] ? 0 : (hi[s] - lo[s] + PC - 1) / PC;
+    }
+    double acc[2][kRows];
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int q = 0; q < kRows; ++q) acc[s][q] = 0.0;
+    // Passes p = wave, wave + 4, ...: the first np[0] passes cover group a,
+    // the next np[1] group b.  Two passes per iteration keep 2 kRows loads
+    // in flight per lane.
+    const int T = np[0] + np[1];
+    for (int p = wave; p < T; p += 2 * kMvWaves) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int pp = p + u * kMvWaves;
+            if (pp >= T) break;
+            const int s = pp < np[0] ? 0 : 1;
+            const int c = lo[s] + (s == 0 ? pp : pp - np[0]) * PC;
+            const int j = c + CPL * lane;
+            const bool ok = j < hi[s];
+            const int jj = ok ? j : lo[s];
+            if (s == 0) stream_pass<PART, PAIR>(M, B, v, r0[0], r1[0], jj, ok, acc[0]);
+            else stream_pass<PART, PAIR>(M, B, v, r0[1], r1[1], jj, ok, acc[1]);
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int q = 0; q < kRows; ++q) {
+            double a = acc[s][q];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+            acc[s][q] = a;
+        }
+    if (lane == 0) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int q = 0; q < kRows; ++q) red[wave][s * kRows + q] = acc[s][q];
+    }
     __syncthreads();
-    const int64_t i = r0 + 2 * threadIdx.x;  // rows i, i+1
-    if (i >= N) return;
-    const bool pair = (i + 1 < N) && ((N & 1) == 0);  // 16-byte aligned row pairs
-    // Column range (tile-relative) shared by rows i and i+1, and the one column
-    // jd = i - c0 that belongs to only one of them (row i+1 for the strict
-    // lower part, row i for the upper part including the diagonal).
-    const int ncol = (int)std::min<int64_t>(kTC, N - c0);
-    int jlo, jhi;
-    if (LOWER) {
-        jlo = 0;
-        jhi = (int)std::min<int64_t>(ncol, std::max<int64_t>(0, i - c0));
-    } else {
-        jlo = (int)std::min<int64_t>(ncol, std::max<int64_t>(0, i + 1 - c0));
-        jhi = ncol;
-    }
-    const int64_t jd = i - c0;
-    const bool extra = jd >= 0 && jd < ncol;
-    double a0[kUnroll], a1[kUnroll];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) a0[u] = a1[u] = 0.0;
-    const double *col = F + i + c0 * N;
-    if (pair) {
-        int j = jlo;
-        for (; j + kUnroll <= jhi; j += kUnroll) {
-#pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const dvec2 m = __builtin_nontemporal_load((const dvec2 *)(col + (int64_t)(j + u) * N));
-                a0[u] = fma(m.x, vs[j + u], a0[u]);
-                a1[u] = fma(m.y, vs[j + u], a1[u]);
-            }
-        }
-        for (; j < jhi; ++j) {
-            const dvec2 m = *(const dvec2 *)(col + (int64_t)j * N);
-            a0[0] = fma(m.x, vs[j], a0[0]);
-            a1[0] = fma(m.y, vs[j], a1[0]);
-        }
-    } else {
-        for (int j = jlo; j < jhi; ++j) {
-            a0[0] = fma(col[(int64_t)j * N], vs[j], a0[0]);
-            if (i + 1 < N) a1[0] = fma(col[(int64_t)j * N + 1], vs[j], a1[0]);
+    if (threadIdx.x < 2 * kRows) {
+        const int s = threadIdx.x / kRows, q = threadIdx.x % kRows;
+        const int row = r0[s] + q;
+        if ((s == 0 || gb != ga) && row <= r1[s]) {
+            const double sum = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+            out[row] = (base ? base[row] : 0.0) + sgn * sum;
         }
     }
-    double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-        s0 += a0[u];
-        s1 += a1[u];
-    }
-    if (extra) {
-        if (LOWER) {
-            if (i + 1 < N) s1 = fma(col[jd * N + 1], vs[jd], s1);
-        } else {
-            s0 = fma(col[jd * N], vs[jd], s0);
-        }
-    }
-    P[(int64_t)cb * N + i] = s0;
-    if (i + 1 < N) P[(int64_t)cb * N + i + 1] = s1;
 }
 
-template <bool LOWER>
-__global__ void __launch_bounds__(256) k_tri_reduce(const double *__restrict__ P, int64_t N, int ncb,
-                                                    const double *__restrict__ v, double *__restrict__ out) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= N) return;
-    const int64_t rb0 = (i / kTR) * kTR;  // first row of this row tile
-    const int lo = live_lo(LOWER, rb0), hi = live_hi(LOWER, rb0, ncb);
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    int cb = lo;
-    for (; cb + 4 <= hi; cb += 4) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc[u] += P[(int64_t)(cb + u) * N + i];
-    }
-    for (; cb < hi; ++cb) acc[0] += P[(int64_t)cb * N + i];
-    out[i] = (LOWER ? v[i] : 0.0) + ((acc[0] + acc[1]) + (acc[2] + acc[3]));
+template <int PART>
+static void slab_mv(const CoarseLU *c, const double *M, const double *v, const double *base, double sgn,
+                    double *out, hipStream_t s) {
+    const int G = (c->B + kRows - 1) / kRows;
+    const dim3 grid((G + 1) / 2);
+    if (c->B % 2 == 0) k_slab_mv<PART, true><<<grid, 256, 0, s>>>(M, c->B, c->nc, G, v, base, sgn, out);
+    else k_slab_mv<PART, false><<<grid, 256, 0, s>>>(M, c->B, c->nc, G, v, base, sgn, out);
 }
 
+fts_status coarse_solve(CoarseLU *c, const double *b, double *x, hipStream_t s) {
+    const int64_t B = c->B, BB = B * B;
+    for (int i = 0; i < c->nb; ++i) {
+        const double *rhs = i == 0 ? b : c->t;
+        slab_mv<kLowerInv>(c, c->D + i * BB, rhs, rhs, 1.0, c->y + i * B, s);
+        if (i + 1 < c->nb) slab_mv<kBelow>(c, c->Lo + i * BB, c->y + i * B, b + (i + 1) * B, -1.0, c->t, s);
+    }
+    for (int i = c->nb - 1; i >= 0; --i) {
+        const double *rhs = i == c->nb - 1 ? c->y + i * B : c->t;
+        slab_mv<kUpperInv>(c, c->D + i * BB, rhs, nullptr, 1.0, x + i * B, s);
+        if (i > 0) slab_mv<kAbove>(c, c->Up + (i - 1) * BB, x + i * B, c->y + (i - 1) * B, -1.0, c->t, s);
+    }
+    return check_launch("coarse substitution mat-vecs");
+}
+
+// ---------------------------------------------------------------------------
+// Setup.
 __global__ void k_set_identity(double *__restrict__ X, int64_t N) {
     const int64_t nn = N * N;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (int64_t)gridDim.x * blockDim.x)
@@ -159,85 +243,156 @@ __global__ void k_pack_triangle(double *__restrict__ LU, const double *__restric
     }
 }
 
+// out = in^T for B x B blocks: the column-major factors become row-major.
+__global__ void __launch_bounds__(256) k_transpose(const double *__restrict__ in, double *__restrict__ out, int B) {
+    __shared__ double tile[32][33];
+    const int r0 = blockIdx.x * 32, c0 = blockIdx.y * 32, tx = threadIdx.x, ty = threadIdx.y;
+    for (int k = 0; k < 32; k += 8) {
+        const int r = r0 + tx, c = c0 + ty + k;
+        if (r < B && c < B) tile[ty + k][tx] = in[r + (int64_t)c * B];
+    }
+    __syncthreads();
+    for (int k = 0; k < 32; k += 8) {
+        const int r = r0 + ty + k, c = c0 + tx;
+        if (r < B && c < B) out[(int64_t)r * B + c] = tile[tx][ty + k];
+    }
+}
+
 static fts_status rb_check(rocblas_status st, const char *what) {
     if (st != rocblas_status_success)
         return fail(FTS_E_HIP, std::string("rocBLAS failure in ") + what + ": " + rocblas_status_to_string(st));
     return FTS_OK;
 }
 
-// Factor A (N x N, column-major, lda = N) in place, then replace the factors
-// by their inverses: strict lower part inv(L), upper part inv(U).  Needs one
-// temporary N x N buffer (allocated and freed here, setup only).
-fts_status coarse_factor(double *A, int64_t N, hipStream_t stream) {
-    if (N > 2147483647LL) return fail(FTS_E_SIZE, "coarse matrix too large for the BLAS interface");
-    rocblas_handle h = nullptr;
-    if (rocblas_create_handle(&h) != rocblas_status_success) return fail(FTS_E_HIP, "rocblas_create_handle failed");
-    fts_status st = rb_check(rocblas_set_stream(h, stream), "rocblas_set_stream");
+// Blocked LU without pivoting of the n x n matrix A (column-major, lda = n), in place.
+static fts_status lu_inplace(rocblas_handle h, double *A, int n, hipStream_t stream) {
     const double one = 1.0, mone = -1.0;
-    for (int64_t k0 = 0; k0 < N && st == FTS_OK; k0 += kNB) {
-        const int kb = (int)std::min<int64_t>(kNB, N - k0);
-        const int n2 = (int)(N - k0 - kb);
-        double *A11 = A + k0 + k0 * N;
-        k_lu_diag<<<1, 1024, 0, stream>>>(A11, N, kb);
-        if (hipGetLastError() != hipSuccess) {
-            st = fail(FTS_E_HIP, "k_lu_diag launch failed");
-            break;
-        }
+    for (int k0 = 0; k0 < n; k0 += kNB) {
+        const int kb = std::min(kNB, n - k0), n2 = n - k0 - kb;
+        double *A11 = A + k0 + (int64_t)k0 * n;
+        k_lu_diag<<<1, 1024, 0, stream>>>(A11, n, kb);
+        COARSE_TRY(check_launch("k_lu_diag"));
         if (n2 == 0) break;
-        double *A12 = A + k0 + (k0 + kb) * N;
-        double *A21 = A + (k0 + kb) + k0 * N;
-        double *A22 = A + (k0 + kb) + (k0 + kb) * N;
-        st = rb_check(rocblas_dtrsm(h, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
-                                    rocblas_diagonal_unit, kb, n2, &one, A11, (int)N, A12, (int)N),
-                      "dtrsm (L panel)");
-        if (st != FTS_OK) break;
-        st = rb_check(rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
-                                    rocblas_diagonal_non_unit, n2, kb, &one, A11, (int)N, A21, (int)N),
-                      "dtrsm (U panel)");
-        if (st != FTS_OK) break;
-        st = rb_check(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, n2, n2, kb, &mone, A21,
-                                    (int)N, A12, (int)N, &one, A22, (int)N),
-                      "dgemm (trailing update)");
+        double *A12 = A + k0 + (int64_t)(k0 + kb) * n;
+        double *A21 = A + (k0 + kb) + (int64_t)k0 * n;
+        double *A22 = A + (k0 + kb) + (int64_t)(k0 + kb) * n;
+        COARSE_TRY(rb_check(rocblas_dtrsm(h, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
+                                       rocblas_diagonal_unit, kb, n2, &one, A11, n, A12, n),
+                         "dtrsm (L panel)"));
+        COARSE_TRY(rb_check(rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
+                                       rocblas_diagonal_non_unit, n2, kb, &one, A11, n, A21, n),
+                         "dtrsm (U panel)"));
+        COARSE_TRY(rb_check(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, n2, n2, kb, &mone, A21,
+                                       n, A12, n, &one, A22, n),
+                         "dgemm (trailing update)"));
     }
-    double *X = nullptr;
-    if (st == FTS_OK && hipMalloc(&X, (size_t)N * N * sizeof(double)) != hipSuccess)
-        st = fail(FTS_E_HIP, "hipMalloc of the inversion buffer failed");
-    const int grid = (int)std::min<int64_t>((N * N + 255) / 256, 1 << 20);
-    for (int pass = 0; pass < 2 && st == FTS_OK; ++pass) {
-        const bool lower = pass == 0;
-        k_set_identity<<<grid, 256, 0, stream>>>(X, N);
-        st = rb_check(rocblas_dtrsm(h, rocblas_side_left, lower ? rocblas_fill_lower : rocblas_fill_upper,
-                                    rocblas_operation_none, lower ? rocblas_diagonal_unit : rocblas_diagonal_non_unit,
-                                    (int)N, (int)N, &one, A, (int)N, X, (int)N),
-                      "dtrsm (triangular inverse)");
-        if (st != FTS_OK) break;
-        if (lower) k_pack_triangle<true><<<grid, 256, 0, stream>>>(A, X, N);
-        else k_pack_triangle<false><<<grid, 256, 0, stream>>>(A, X, N);
-        if (hipGetLastError() != hipSuccess) st = fail(FTS_E_HIP, "packing of the inverse factors failed");
-    }
-    if (hipStreamSynchronize(stream) != hipSuccess && st == FTS_OK) st = fail(FTS_E_HIP, "coarse factorisation failed");
-    if (X) hipFree(X);
-    rocblas_destroy_handle(h);
-    return st;
+    return FTS_OK;
 }
 
-int coarse_ncb(int64_t N) { return (int)((N + kTC - 1) / kTC); }
+// Replace the factors L, U stored in A (n x n) by inv(L) (strict lower part)
+// and inv(U) (upper part); X is an n x n temporary.
+static fts_status invert_factors(rocblas_handle h, double *A, int n, double *X, hipStream_t stream) {
+    const double one = 1.0;
+    const int64_t nn = (int64_t)n * n;
+    const int grid = (int)std::min<int64_t>((nn + 255) / 256, 1 << 20);
+    for (int pass = 0; pass < 2; ++pass) {
+        const bool lower = pass == 0;
+        k_set_identity<<<grid, 256, 0, stream>>>(X, n);
+        COARSE_TRY(check_launch("k_set_identity"));
+        COARSE_TRY(rb_check(rocblas_dtrsm(h, rocblas_side_left, lower ? rocblas_fill_lower : rocblas_fill_upper,
+                                       rocblas_operation_none,
+                                       lower ? rocblas_diagonal_unit : rocblas_diagonal_non_unit, n, n, &one, A, n,
+                                       X, n),
+                         "dtrsm (triangular inverse)"));
+        if (lower) k_pack_triangle<true><<<grid, 256, 0, stream>>>(A, X, n);
+        else k_pack_triangle<false><<<grid, 256, 0, stream>>>(A, X, n);
+        COARSE_TRY(check_launch("k_pack_triangle"));
+    }
+    return FTS_OK;
+}
 
-// x = inv(U) (inv(L) b): two tiled triangular mat-vecs, each reading its
-// triangle of the stored inverse factors once.  P: workspace of ncb * N
-// doubles; y: workspace of N doubles.  x must not alias y or P.
-fts_status coarse_solve(const double *F, int64_t N, const double *b, double *x, double *y, double *P,
-                        hipStream_t stream) {
-    const int ncb = coarse_ncb(N);
-    const int nrb = (int)((N + kTR - 1) / kTR);
-    const dim3 grid(ncb, nrb);
-    const int rgrid = (int)((N + 255) / 256);
-    k_tri_partial<true><<<grid, 256, 0, stream>>>(F, N, b, P);
-    k_tri_reduce<true><<<rgrid, 256, 0, stream>>>(P, N, ncb, b, y);
-    k_tri_partial<false><<<grid, 256, 0, stream>>>(F, N, y, P);
-    k_tri_reduce<false><<<rgrid, 256, 0, stream>>>(P, N, ncb, y, x);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(e, "coarse triangular mat-vecs");
+// Block elimination over the slabs (see the top of this file).
+static fts_status factor_slabs(rocblas_handle h, CoarseLU *c, double *X, hipStream_t stream) {
+    const int B = c->B;
+    const int64_t BB = (int64_t)B * B;
+    const double one = 1.0, mone = -1.0;
+    COARSE_TRY(rb_check(rocblas_set_stream(h, stream), "rocblas_set_stream"));
+    for (int i = 0; i < c->nb; ++i) {
+        double *Di = c->D + i * BB;
+        if (i > 0)  // D_i <- A_ii - Lo_{i-1} Up_{i-1}
+            COARSE_TRY(rb_check(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, B, B, B, &mone,
+                                           c->Lo + (i - 1) * BB, B, c->Up + (i - 1) * BB, B, &one, Di, B),
+                             "dgemm (slab update)"));
+        COARSE_TRY(lu_inplace(h, Di, B, stream));
+        if (i + 1 < c->nb) {
+            COARSE_TRY(rb_check(rocblas_dtrsm(h, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
+                                           rocblas_diagonal_unit, B, B, &one, Di, B, c->Up + i * BB, B),
+                             "dtrsm (Up)"));
+            COARSE_TRY(rb_check(rocblas_dtrsm(h, rocblas_side_right, rocblas_fill_upper, rocblas_operation_none,
+                                           rocblas_diagonal_non_unit, B, B, &one, Di, B, c->Lo + i * BB, B),
+                             "dtrsm (Lo)"));
+        }
+        COARSE_TRY(invert_factors(h, Di, B, X, stream));
+    }
+    // The substitution kernels read rows: store every block row-major.
+    const dim3 tgrid((B + 31) / 32, (B + 31) / 32), tblock(32, 8);
+    for (int blk = 0; blk < 3 * c->nb - 2; ++blk) {
+        double *Mb = blk < c->nb ? c->D + blk * BB
+                                 : (blk < 2 * c->nb - 1 ? c->Lo + (blk - c->nb) * BB : c->Up + (blk - 2 * c->nb + 1) * BB);
+        k_transpose<<<tgrid, tblock, 0, stream>>>(Mb, X, B);
+        COARSE_TRY(check_launch("k_transpose"));
+        FTS_HIP_CHECK(hipMemcpyAsync(Mb, X, BB * sizeof(double), hipMemcpyDeviceToDevice, stream));
+    }
+    return FTS_OK;
+}
+
+void coarse_destroy(CoarseLU *c) {
+    if (!c) return;
+    for (void *p : {(void *)c->D, (void *)c->Lo, (void *)c->Up, (void *)c->y, (void *)c->t})
+        if (p) hipFree(p);
+    delete c;
+}
+
+fts_status coarse_create(const fts_level *l0, hipStream_t stream, CoarseLU **out) {
+    *out = nullptr;
+    const int d = l0->dim;
+    int64_t nc = 1;
+    for (int a = 0; a < d; ++a) nc *= l0->n1;
+    const int64_t B = nc * l0->m[0] * (d == 3 ? l0->m[1] : 1);
+    const int nb = l0->m[d - 1];
+    if (B > INT_MAX || (int64_t)B * nb != l0->ndofs)
+        return fail(FTS_E_SIZE, "coarse slab too large for the BLAS interface");
+    CoarseLU *c = new CoarseLU;
+    c->N = l0->ndofs;
+    c->B = (int)B;
+    c->nb = nb;
+    c->nc = (int)nc;
+    const size_t blk = (size_t)B * B * sizeof(double);
+    double *X = nullptr;
+    fts_status st = FTS_OK;
+    if (hipMalloc(&c->D, nb * blk) != hipSuccess ||
+        (nb > 1 && (hipMalloc(&c->Lo, (nb - 1) * blk) != hipSuccess ||
+                    hipMalloc(&c->Up, (nb - 1) * blk) != hipSuccess)) ||
+        hipMalloc(&c->y, c->N * sizeof(double)) != hipSuccess || hipMalloc(&c->t, B * sizeof(double)) != hipSuccess ||
+        hipMalloc(&X, blk) != hipSuccess)
+        st = fail(FTS_E_HIP, "hipMalloc of the coarse factors failed");
+    const int64_t nblk = (int64_t)B * B;
+    if (st == FTS_OK) st = launch_fill(c->D, nb * nblk, 0.0, stream);
+    if (st == FTS_OK && nb > 1) st = launch_fill(c->Lo, (nb - 1) * nblk, 0.0, stream);
+    if (st == FTS_OK && nb > 1) st = launch_fill(c->Up, (nb - 1) * nblk, 0.0, stream);
+    if (st == FTS_OK) st = launch_assemble_slabs(l0, SlabBlocks{c->D, c->Lo, c->Up, B}, stream);
+    rocblas_handle h = nullptr;
+    if (st == FTS_OK && rocblas_create_handle(&h) != rocblas_status_success)
+        st = fail(FTS_E_HIP, "rocblas_create_handle failed");
+    if (st == FTS_OK) st = factor_slabs(h, c, X, stream);
+    if (hipStreamSynchronize(stream) != hipSuccess && st == FTS_OK) st = fail(FTS_E_HIP, "coarse factorisation failed");
+    if (h) rocblas_destroy_handle(h);
+    if (X) hipFree(X);
+    if (st != FTS_OK) {
+        coarse_destroy(c);
+        return st;
+    }
+    *out = c;
     return FTS_OK;
 }
 

@@ -66,6 +66,17 @@ struct LevelView {
     const double *E;          // 2 x n1 x n1 embedding matrices
 };
 
+// The coarse matrix stored by slabs of cells (all cells sharing their
+// coordinate along the last axis).  Unknowns are numbered cell by cell with
+// the last axis slowest, so a slab is a contiguous range of B unknowns, and
+// the face couplings of SIPG reach only the two neighbouring slabs: A_0 is
+// block tridiagonal.  Block (i, i) is D + i B^2, block (i, i-1) is
+// Lo + (i-1) B^2 and block (i, i+1) is Up + i B^2, each B x B column-major.
+struct SlabBlocks {
+    double *D, *Lo, *Up;
+    int64_t B;
+};
+
 struct EigView {
     int count[3];             // positions per axis
     const double *S[3];       // per axis: count blocks of n x n, row-major [i][m]
@@ -135,7 +146,7 @@ fts_status launch_restrict(const fts_level *coarse, const fts_level *fine, const
                            double *bc, hipStream_t stream);
 fts_status launch_prolongate(const fts_level *coarse, const fts_level *fine, const double *ec,
                              double *xf, hipStream_t stream);
-fts_status launch_assemble_dense(const fts_level *lv, double *A, hipStream_t stream);
+fts_status launch_assemble_slabs(const fts_level *lv, const SlabBlocks &blk, hipStream_t stream);
 fts_status launch_fill(double *p, int64_t n, double v, hipStream_t stream);
 // out[0] = x.y, out[1] = x.z (z may be NULL); part: 2 * red_partials() doubles
 fts_status launch_dot2(const double *x, const double *y, const double *z, int64_t n, double *part, double *out,
@@ -144,4 +155,12 @@ fts_status launch_cg_update(double *x, double *r, const double *p, const double 
                             hipStream_t stream);
 fts_status launch_xpby(double *p, const double *z, double beta, int64_t n, hipStream_t stream);
 int red_partials();
+
+// Direct solver of the coarsest level (coarse.hip).
+struct CoarseLU;
+fts_status coarse_create(const fts_level *l0, hipStream_t stream, CoarseLU **out);
+void coarse_destroy(CoarseLU *c);
+// x = A_0^-1 b; x must not alias b.  Uses the solver's own workspaces, so
+// solves with one CoarseLU must not overlap.
+fts_status coarse_solve(CoarseLU *c, const double *b, double *x, hipStream_t stream);
 }  // namespace fts

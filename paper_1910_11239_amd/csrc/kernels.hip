@@ -466,11 +466,18 @@ k_transfer(LevelView gc, LevelView gf, const double *__restrict__ src, double *_
 }
 
 // ---------------------------------------------------------------------------
-// Dense coarse matrix, column-major with leading dimension N: entry (row, col)
-// from the same 1-D tables as the operator.  One thread per row; for a fixed
-// column the rows of a wave are consecutive, so the stores coalesce.
+// Coarse matrix in slab blocks (SlabBlocks): entry (row, col) from the same
+// 1-D tables as the operator.  One thread per row; for a fixed column the
+// rows of a wave are consecutive, so the stores coalesce.
+__device__ __forceinline__ double &slab_entry(const SlabBlocks &s, int64_t row, int64_t col) {
+    const int64_t bi = row / s.B, bj = col / s.B;
+    const int64_t off = (row - bi * s.B) + (col - bj * s.B) * s.B;
+    double *blk = bj == bi ? s.D + bi * s.B * s.B : (bj < bi ? s.Lo + (bi - 1) * s.B * s.B : s.Up + bi * s.B * s.B);
+    return blk[off];
+}
+
 template <int D, int N1>
-__global__ void __launch_bounds__(256) k_assemble_dense(LevelView g, double *__restrict__ A, int64_t N) {
+__global__ void __launch_bounds__(256) k_assemble_slabs(LevelView g, SlabBlocks A, int64_t N) {
     constexpr int NC = ipow(N1, D);
     const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (row >= N) return;
@@ -494,18 +501,18 @@ __global__ void __launch_bounds__(256) k_assemble_dense(LevelView g, double *__r
                 if (a != tt) term *= mass[a];
             v += term;
         }
-        A[row + (cell * NC + j) * N] = v;
+        slab_entry(A, row, cell * NC + j) = v;
         for (int tt = 0; tt < D; ++tt) {
             double tr = 1.0;
             for (int a = 0; a < D; ++a)
                 if (a != tt) tr *= mass[a];
             if (c[tt] + 1 < g.m[tt]) {
                 const double bv = g.iface[tt][(size_t)c[tt] * N1 * N1 + ii[tt] * N1 + jj[tt]];
-                A[row + ((cell + cs[tt]) * NC + j) * N] = bv * tr;
+                slab_entry(A, row, (cell + cs[tt]) * NC + j) = bv * tr;
             }
             if (c[tt] > 0) {
                 const double bv = g.iface[tt][(size_t)(c[tt] - 1) * N1 * N1 + jj[tt] * N1 + ii[tt]];
-                A[row + ((cell - cs[tt]) * NC + j) * N] = bv * tr;
+                slab_entry(A, row, (cell - cs[tt]) * NC + j) = bv * tr;
             }
         }
     }
@@ -662,14 +669,14 @@ fts_status launch_prolongate(const fts_level *coarse, const fts_level *fine, con
 
 template <int D, int N1>
 struct RunAssemble {
-    static fts_status run(const fts_level *lv, double *A, hipStream_t st) {
+    static fts_status run(const fts_level *lv, const SlabBlocks &A, hipStream_t st) {
         const int64_t N = lv->ndofs;
-        k_assemble_dense<D, N1><<<dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st>>>(lv->view, A, N);
-        return check_launch("k_assemble_dense");
+        k_assemble_slabs<D, N1><<<dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st>>>(lv->view, A, N);
+        return check_launch("k_assemble_slabs");
     }
 };
 
-fts_status launch_assemble_dense(const fts_level *lv, double *A, hipStream_t stream) {
+fts_status launch_assemble_slabs(const fts_level *lv, const SlabBlocks &A, hipStream_t stream) {
     return dispatch<RunAssemble>(lv->dim, lv->n1, lv, A, stream);
 }
 
