@@ -159,6 +159,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-mesh batched sweep")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + steps of the V-cycle only (for rocprofv3)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy a 1 GiB FP64 buffer on the device --steps times (reference kernel of known "
+                         "traffic for the rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the smoother and V-cycle are single-GPU kernels "
@@ -166,6 +169,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.calibrate_copy:
+        n = 1 << 27  # 2^27 doubles = 1 GiB
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "copies": args.steps}))
+        return
     import paper_1910_11239_amd as fts
 
     cfg = CONFIGS["avs_3d_q4"]

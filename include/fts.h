@@ -177,14 +177,16 @@ fts_status fts_prolongate_add(const fts_level *coarse, const fts_level *fine, co
 /* Builds nlevels levels by coarsening `finest` (pairs of equal children per
  * axis are merged; every level but the coarsest needs >= 2 cells per axis for
  * vertex patches), 1-D eigen-data of every level > 0, the level vectors, and
- * the dense FP64 LU factorisation of the coarsest matrix A_0 on the device
- * (no pivoting: A_0 is symmetric positive definite) together with the
- * inverses of its two triangular factors.  omega_per_level and
- * penalty_per_level: host arrays of nlevels entries, index 0 = coarsest
- * (omega[0] unused); penalty_per_level may be NULL (then the mesh's
- * penalty_factor on every level).  Allocates device memory: 8 N_0^2 bytes
- * for the coarse factors (16 N_0^2 transiently during setup) plus the level
- * vectors. */
+ * the FP64 LU factorisation of the coarsest matrix A_0 on the device (no
+ * pivoting: A_0 is symmetric positive definite).  The factors are stored by
+ * slabs of cells (all cells with one coordinate along the last axis, B
+ * unknowns each, nb slabs): A_0 is block tridiagonal over slabs, so L and U
+ * are block bidiagonal; the diagonal blocks are kept as the inverses of their
+ * triangular factors.  omega_per_level and penalty_per_level: host arrays of
+ * nlevels entries, index 0 = coarsest (omega[0] unused); penalty_per_level
+ * may be NULL (then the mesh's penalty_factor on every level).  Allocates
+ * device memory: 8 (3 nb - 2) B^2 bytes for the coarse factors (plus 8 B^2
+ * transiently during setup) and the level vectors. */
 fts_status fts_hierarchy_create(const fts_mesh_desc *finest, int32_t nlevels, fts_patch_kind kind,
                                 const double *omega_per_level, const double *penalty_per_level,
                                 int32_t m_pre, int32_t m_post, fts_hierarchy **out);
@@ -243,10 +245,14 @@ fts_status fts_vcycle_adjoint(fts_hierarchy *hier, const double *b, const double
                               const double *lambda_out, double *lambda_b, double *lambda_x,
                               double *d_omega, double *d_penalty, void *stream);
 
-/* x0 = A_0^-1 b0 with the stored LU factorisation: x0 = inv(U) (inv(L) b0),
- * the inverse triangular factors being formed once at hierarchy creation, so
- * each of the two triangular stages is a parallel mat-vec reading its
- * triangle once (8 N_0^2 bytes per solve).  x0 may alias b0. */
+/* x0 = A_0^-1 b0 with the stored LU factorisation, by block forward and
+ * backward substitution over the slabs (Alg. gmg, coarse grid solver):
+ *   y_0 = inv(L_00) b_0,  y_i = inv(L_ii) (b_i - L_{i,i-1} y_{i-1}),
+ *   x_last = inv(U) y_last, x_i = inv(U_ii) (y_i - U_{i,i+1} x_{i+1}),
+ * 2 (2 nb - 1) parallel mat-vecs that read 8 B^2 (2 nb - 1) bytes in all
+ * (the off-diagonal blocks are half zero and only their nonzero halves are
+ * read).  x0 may alias b0.  Solves on one hierarchy must not overlap (they
+ * share its workspaces). */
 fts_status fts_coarse_solve(fts_hierarchy *hier, const double *b0, double *x0, void *stream);
 
 /* ---- a13: batched smoothing of many meshes of mixed degree ------------------ */

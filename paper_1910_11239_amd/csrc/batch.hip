@@ -172,7 +172,7 @@ k_batch_residual(const BatchMesh *__restrict__ meshes, const BatchBlock *__restr
     const BatchBlock B = blocks[blockIdx.x];
     const LevelView g = meshes[B.mesh].lv;
     const int64_t off = meshes[B.mesh].dof_off;
-    operator_block<3, N1, true>(g, B.first, x + off, b + off, r + off);
+    operator_cells<3, N1, true>(g, B.first, x + off, b + off, r + off);
 }
 
 template <int D, int N1>
@@ -317,7 +317,8 @@ fts_status fts_batch_create(const fts_mesh_desc *meshes, int32_t nmesh, fts_batc
         std::vector<BatchBlock> blocks;
         for (int i = 0; i < nmesh; ++i) {
             if (host[i].n1 != n1) continue;
-            for (int64_t c = 0; c < bt->levels[i]->ncells; ++c) blocks.push_back({i, 0, c});  // one cell per block
+            const int cpw = operator_cells_per_block(3, n1);
+            for (int64_t c = 0; c < bt->levels[i]->ncells; c += cpw) blocks.push_back({i, 0, c});
         }
         if (blocks.empty()) continue;
         fts_batch::Group g{n1, nullptr, (int64_t)blocks.size()};

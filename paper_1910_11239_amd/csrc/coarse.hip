@@ -78,12 +78,13 @@ __global__ void __launch_bounds__(1024) k_lu_diag(double *__restrict__ A, int64_
 //     kAbove     Up_i, zero right of the row's cell:            [0, (cell(r) + 1) nc)
 // The rows are cut into groups of kRows; a workgroup owns group g and group
 // G-1-g, a short and a long range, so every workgroup streams about the same
-// number of bytes.  Its four waves take interleaved passes of 64 lanes x two
-// columns over the two ranges (16-byte non-temporal loads, one per row and
-// lane), keep one partial per row and lane, reduce across lanes with
-// shuffles and across waves in LDS in a fixed order: no atomics, and the
-// result does not depend on timing.
-constexpr int kRows = 8, kMvWaves = 4;
+// number of bytes.  Its waves take interleaved passes of 64 lanes x two
+// columns over each range (16-byte non-temporal loads, one per row and
+// lane, the loads of kUnroll passes issued before their FMAs), keep one
+// partial per row and lane, and reduce across lanes with shuffles and across
+// waves in LDS in a fixed order: no atomics, and the result does not depend
+// on timing.
+constexpr int kRows = 4, kMvWaves = 8, kUnroll = 2;
 typedef double dvec2 __attribute__((ext_vector_type(2)));
 
 enum BlockPart { kLowerInv = 0, kUpperInv = 1, kBelow = 2, kAbove = 3 };
@@ -107,95 +108,122 @@ __device__ __forceinline__ bool outside(int row, int col) {
     return false;
 }
 
+// acc[q] += sum over this lane's columns of row r0 + q (rows past r1 are
+// loaded from row r1 and their sums dropped by the caller).  Passes
+// p = wave, wave + kMvWaves, ... < np; pass p covers PC columns from lo + p PC.
 template <int PART, bool PAIR>
-__device__ __forceinline__ void stream_pass(const double *__restrict__ M, int B, const double *__restrict__ v,
-                                            int r0, int r1, int j, bool ok, double *acc) {
-    // rows r0 .. r0 + kRows - 1, clamped to r1 for the loads (their results are dropped)
-    if (PAIR) {
-        const dvec2 x = *(const dvec2 *)(v + j);
-        dvec2 m[kRows];
+__device__ __forceinline__ void stream_group(const double *__restrict__ M, int B, const double *__restrict__ v,
+                                             int r0, int r1, int lo, int hi, int np, int wave, int lane,
+                                             double *acc) {
+    constexpr int CPL = PAIR ? 2 : 1, PC = 64 * CPL;
+    const double *rowp[kRows];
 #pragma unroll
-        for (int q = 0; q < kRows; ++q)
-            m[q] = __builtin_nontemporal_load((const dvec2 *)(M + (int64_t)min(r0 + q, r1) * B + j));
+    for (int q = 0; q < kRows; ++q) rowp[q] = M + (int64_t)min(r0 + q, r1) * B;
+    int p = wave;
+    for (; p + (kUnroll - 1) * kMvWaves < np; p += kUnroll * kMvWaves) {
+        int jj[kUnroll];
+        bool ok[kUnroll];
 #pragma unroll
-        for (int q = 0; q < kRows; ++q) {
-            const double mx = (ok && !outside<PART>(r0 + q, j)) ? m[q].x : 0.0;
-            const double my = (ok && !outside<PART>(r0 + q, j + 1)) ? m[q].y : 0.0;
-            acc[q] = fma(my, x.y, fma(mx, x.x, acc[q]));
+        for (int u = 0; u < kUnroll; ++u) {
+            const int j = lo + (p + u * kMvWaves) * PC + CPL * lane;
+            ok[u] = j < hi;
+            jj[u] = ok[u] ? j : lo;
         }
-    } else {
-        const double x = v[j];
-        double m[kRows];
+        if constexpr (PAIR) {
+            dvec2 x[kUnroll], m[kUnroll][kRows];
 #pragma unroll
-        for (int q = 0; q < kRows; ++q) m[q] = M[(int64_t)min(r0 + q, r1) * B + j];
+            for (int u = 0; u < kUnroll; ++u) {
+                x[u] = *(const dvec2 *)(v + jj[u]);
 #pragma unroll
-        for (int q = 0; q < kRows; ++q) acc[q] = fma((ok && !outside<PART>(r0 + q, j)) ? m[q] : 0.0, x, acc[q]);
+                for (int q = 0; q < kRows; ++q) m[u][q] = __builtin_nontemporal_load((const dvec2 *)(rowp[q] + jj[u]));
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+                for (int q = 0; q < kRows; ++q) {
+                    const double mx = (ok[u] && !outside<PART>(r0 + q, jj[u])) ? m[u][q].x : 0.0;
+                    const double my = (ok[u] && !outside<PART>(r0 + q, jj[u] + 1)) ? m[u][q].y : 0.0;
+                    acc[q] = fma(my, x[u].y, fma(mx, x[u].x, acc[q]));
+                }
+        } else {
+            double x[kUnroll], m[kUnroll][kRows];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                x[u] = v[jj[u]];
+#pragma unroll
+                for (int q = 0; q < kRows; ++q) m[u][q] = rowp[q][jj[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+                for (int q = 0; q < kRows; ++q)
+                    acc[q] = fma((ok[u] && !outside<PART>(r0 + q, jj[u])) ? m[u][q] : 0.0, x[u], acc[q]);
+        }
+    }
+    for (; p < np; p += kMvWaves) {
+        const int j = lo + p * PC + CPL * lane;
+        const bool ok = j < hi;
+        const int jj = ok ? j : lo;
+        if constexpr (PAIR) {
+            const dvec2 x = *(const dvec2 *)(v + jj);
+            dvec2 m[kRows];
+#pragma unroll
+            for (int q = 0; q < kRows; ++q) m[q] = __builtin_nontemporal_load((const dvec2 *)(rowp[q] + jj));
+#pragma unroll
+            for (int q = 0; q < kRows; ++q) {
+                const double mx = (ok && !outside<PART>(r0 + q, jj)) ? m[q].x : 0.0;
+                const double my = (ok && !outside<PART>(r0 + q, jj + 1)) ? m[q].y : 0.0;
+                acc[q] = fma(my, x.y, fma(mx, x.x, acc[q]));
+            }
+        } else {
+            const double x = v[jj];
+            double m[kRows];
+#pragma unroll
+            for (int q = 0; q < kRows; ++q) m[q] = rowp[q][jj];
+#pragma unroll
+            for (int q = 0; q < kRows; ++q) acc[q] = fma((ok && !outside<PART>(r0 + q, jj)) ? m[q] : 0.0, x, acc[q]);
+        }
     }
 }
 
 template <int PART, bool PAIR>
-__global__ void __launch_bounds__(256) k_slab_mv(const double *__restrict__ M, int B, int nc, int G,
-                                                 const double *__restrict__ v, const double *base, double sgn,
-                                                 double *__restrict__ out) {
-    constexpr int CPL = PAIR ? 2 : 1, PC = 64 * CPL;  // columns per lane / per wave pass
+__global__ void __launch_bounds__(64 * kMvWaves) k_slab_mv(const double *__restrict__ M, int B, int nc, int G,
+                                                           const double *__restrict__ v, const double *base,
+                                                           double sgn, double *__restrict__ out) {
+    constexpr int PC = PAIR ? 128 : 64;  // columns per wave pass
     __shared__ double red[kMvWaves][2 * kRows];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ga = blockIdx.x, gb = G - 1 - blockIdx.x;  // gb == ga: a single group
-    int r0[2], r1[2], lo[2], hi[2], np[2];
+    int r0[2], r1[2];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-        const int g = s == 0 ? ga : gb;
-        r0[s] = g * kRows;
+        r0[s] = (s == 0 ? ga : gb) * kRows;
         r1[s] = min(r0[s] + kRows, B) - 1;
-        group_range<PART>(r0[s], r1[s], B, nc, lo[s], hi[s]);
-        if (PAIR) lo[s] &= ~1, hi[s] = min(B, (hi[s] + 1) & ~1);
-        np[s] = (s == 1 && gb == ga) || hi[s] <= lo[s] ? 0 : (hi[s] - lo[s] + PC - 1) / PC;
-    }
-    double acc[2][kRows];
+        int lo, hi;
+        group_range<PART>(r0[s], r1[s], B, nc, lo, hi);
+        if (PAIR) lo &= ~1, hi = min(B, (hi + 1) & ~1);
+        const int np = (s == 1 && gb == ga) || hi <= lo ? 0 : (hi - lo + PC - 1) / PC;
+        double acc[kRows];
 #pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int q = 0; q < kRows; ++q) acc[s][q] = 0.0;
-    // Passes p = wave, wave + 4, ...: the first np[0] passes cover group a,
-    // the next np[1] group b.  Two passes per iteration keep 2 kRows loads
-    // in flight per lane.
-    const int T = np[0] + np[1];
-    for (int p = wave; p < T; p += 2 * kMvWaves) {
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int pp = p + u * kMvWaves;
-            if (pp >= T) break;
-            const int s = pp < np[0] ? 0 : 1;
-            const int c = lo[s] + (s == 0 ? pp : pp - np[0]) * PC;
-            const int j = c + CPL * lane;
-            const bool ok = j < hi[s];
-            const int jj = ok ? j : lo[s];
-            if (s == 0) stream_pass<PART, PAIR>(M, B, v, r0[0], r1[0], jj, ok, acc[0]);
-            else stream_pass<PART, PAIR>(M, B, v, r0[1], r1[1], jj, ok, acc[1]);
-        }
-    }
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
+        for (int q = 0; q < kRows; ++q) acc[q] = 0.0;
+        stream_group<PART, PAIR>(M, B, v, r0[s], r1[s], lo, hi, np, wave, lane, acc);
 #pragma unroll
         for (int q = 0; q < kRows; ++q) {
-            double a = acc[s][q];
+            double t = acc[q];
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
-            acc[s][q] = a;
+            for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+            if (lane == 0) red[wave][s * kRows + q] = t;
         }
-    if (lane == 0) {
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
-#pragma unroll
-            for (int q = 0; q < kRows; ++q) red[wave][s * kRows + q] = acc[s][q];
     }
     __syncthreads();
     if (threadIdx.x < 2 * kRows) {
         const int s = threadIdx.x / kRows, q = threadIdx.x % kRows;
         const int row = r0[s] + q;
         if ((s == 0 || gb != ga) && row <= r1[s]) {
-            const double sum = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
+            double sum = 0.0;
+#pragma unroll
+            for (int w = 0; w < kMvWaves; ++w) sum += red[w][threadIdx.x];
             out[row] = (base ? base[row] : 0.0) + sgn * sum;
         }
     }
@@ -206,8 +234,8 @@ static void slab_mv(const CoarseLU *c, const double *M, const double *v, const d
                     double *out, hipStream_t s) {
     const int G = (c->B + kRows - 1) / kRows;
     const dim3 grid((G + 1) / 2);
-    if (c->B % 2 == 0) k_slab_mv<PART, true><<<grid, 256, 0, s>>>(M, c->B, c->nc, G, v, base, sgn, out);
-    else k_slab_mv<PART, false><<<grid, 256, 0, s>>>(M, c->B, c->nc, G, v, base, sgn, out);
+    if (c->B % 2 == 0) k_slab_mv<PART, true><<<grid, 64 * kMvWaves, 0, s>>>(M, c->B, c->nc, G, v, base, sgn, out);
+    else k_slab_mv<PART, false><<<grid, 64 * kMvWaves, 0, s>>>(M, c->B, c->nc, G, v, base, sgn, out);
 }
 
 fts_status coarse_solve(CoarseLU *c, const double *b, double *x, hipStream_t s) {

@@ -43,20 +43,35 @@ __device__ __forceinline__ void cell_coords(int64_t cell, const int *m, int *c) 
 // ---------------------------------------------------------------------------
 // SIPG operator (Sec. 3.2, eq. KDseparable / bulkcart / 1Dsipg): on a
 // rectilinear mesh the operator restricted to the rows of cell K is
-//   (A x)_K = sum_t (prod_{s != t} h_s) (Mhat x..x W_t x..x Mhat)
+//   (A x)_K = sum_t (prod_{s != t} h_s Mhat_s) W_t
 //   W_t = A_t^K x_K + B_t(K, K+e_t) x_{K+e_t} + B_t(K-e_t, K)^T x_{K-e_t}
-// with the 1-D cell operator A_t^K (both faces' Nitsche terms) and the
-// interface blocks B_t.  One cell per workgroup (operator_block below): the
-// cell and its face neighbours are staged in LDS, every thread applies the
-// 1-D operators along one line of the cell for each axis, then the transverse
-// mass matrices are applied line by line in LDS.
+// with the 1-D cell operator A_t^K = Lhat / h + (Nitsche terms of both faces)
+// and the interface blocks B_t.  With the nodal Gauss-Lobatto basis the value
+// at an end of the cell is the end coefficient, so every face term is rank one
+// or two in the end values and the end derivatives d0, d1 (eq. 1Dnitsche,
+// eq. 1Dsipginterface): the kernels need only the reference tables Lhat,
+// Mhat, d0, d1 (the same for every cell) and a few widths per cell.  That
+// frees the mapping of cells to lanes: a workgroup takes CPW cells so that
+// its lanes are nearly all busy.
 template <int D, int N1>
 struct OpCfg {
     static constexpr int NC = ipow(N1, D);
     static constexpr int LINES = ipow(N1, D - 1);
-    // one cell per workgroup: every 1-D table address is uniform (scalar loads)
-    static constexpr int THREADS = LINES <= 64 ? 64 : rup64(LINES);
-    static constexpr int PPB = 1;
+    // workgroup size (64..256) wasting the fewest lanes on whole cells
+    static constexpr int pick_threads() {
+        int best = 64, best_used = 0;
+        for (int th = 64; th <= 256; th += 64) {
+            const int used = (th / LINES) * LINES;
+            if (used * best > best_used * th) best = th, best_used = used;
+        }
+        return best;
+    }
+    static constexpr int THREADS = pick_threads();
+    static constexpr int CPW = THREADS / LINES;  // cells per workgroup
+    // LDS pitch of a line along x: odd, so that lanes reading consecutive
+    // x-lines hit different banks
+    static constexpr int P = N1 | 1;
+    static constexpr int SLOT = D == 3 ? P * N1 * N1 : P * N1;
 };
 
 template <int D, int N1, typename P>
@@ -142,6 +157,19 @@ __device__ __forceinline__ void contract_line(T *Tq, int a, int l, P Mat) {
     for (int i = 0; i < N; ++i) Tq[base + i * st] = out[i];
 }
 
+// 1/d from the hardware reciprocal refined by Newton steps, each of which
+// squares the relative error: within a few units in the last place of the
+// correctly rounded quotient, at a third of the instructions of IEEE division.
+__device__ __forceinline__ double recip(double d) {
+    double y = __builtin_amdgcn_rcp(d);
+    y = fma(y, fma(-d, y, 1.0), y);
+    return fma(y, fma(-d, y, 1.0), y);
+}
+__device__ __forceinline__ float recip(float d) {
+    const float y = __builtin_amdgcn_rcpf(d);
+    return fmaf(y, fmaf(-d, y, 1.0f), y);
+}
+
 // Last axis: forward transform, eigenvalue scaling and backward transform of
 // the same line, kept in registers.  lam_rest = lambda of the other axes at
 // this line's fixed mode indices.
@@ -154,7 +182,7 @@ __device__ __forceinline__ void last_axis_solve(T *Tq, int l, P ST, P S, Q lam_l
     for (int i = 0; i < N; ++i) in[i] = Tq[base + i * st];
     matvec_regs<N>(in, mid, ST);
 #pragma unroll
-    for (int m = 0; m < N; ++m) mid[m] = mid[m] * (omega / (lam_rest + (T)lam_last[m]));
+    for (int m = 0; m < N; ++m) mid[m] = mid[m] * (omega * recip(lam_rest + (T)lam_last[m]));
     matvec_regs<N>(mid, in, S);
 #pragma unroll
     for (int i = 0; i < N; ++i) Tq[base + i * st] = in[i];
@@ -181,156 +209,251 @@ inline fts_status check_launch(const char *what) {
 }
 
 
-// Body of the operator for the PPB cells cell0.. of the mesh described by g
-// (x, b, y: that mesh's vectors).  Shared by the single-mesh and the batched
-// kernels.  The block's cells and their 2d face neighbours are first copied
-// into LDS with coalesced whole-cell loads (slot 0 = the cell, slots 1..2d =
-// neighbours -x, +x, -y, +y, -z, +z; absent neighbours are skipped); each
-// thread then applies the 1-D operators along its line of each axis
-// (cell block + the two interface blocks), keeps the d results in registers,
-// and after a barrier the transverse mass matrices are applied in LDS reusing
-// the neighbour slots.
-template <int D, int N1, bool RES>
-__device__ __forceinline__ void operator_block(const LevelView &g, int64_t cell0, const double *__restrict__ x,
+// One 1-D operator along axis t on a line of cell K (eq. 1Dsipg with the
+// interface blocks of eq. 1Dsipginterface): in = the line of K, nl / nr = the
+// same line in the neighbours K - e_t / K + e_t (used when present), h, hl,
+// hr = widths, gk = gamma_hat k (k+1).  PEN: only the penalty terms, i.e.
+// dA/dgamma_hat with gk = k (k+1).
+template <int N1, bool PEN, typename P>
+__device__ __forceinline__ void sipg_line(const double *in, const double *nl, const double *nr, bool hasl, bool hasr,
+                                          double h, double hl, double hr, double gk, P Lh, P d0, P d1, double *out) {
+    const double ih = 1.0 / h;
+    const double eta0 = hasl ? 0.5 : 1.0, eta1 = hasr ? 0.5 : 1.0;
+    const double g0 = hasl ? gk * (ih + 1.0 / hl) : 2.0 * gk * ih;
+    const double g1 = hasr ? gk * (ih + 1.0 / hr) : 2.0 * gk * ih;
+    const double x0 = in[0], xn = in[N1 - 1];
+    if constexpr (PEN) {
+#pragma unroll
+        for (int o = 0; o < N1; ++o) out[o] = 0.0;
+        out[0] = eta0 * g0 * x0;
+        out[N1 - 1] += eta1 * g1 * xn;
+        if (hasl) out[0] -= 0.5 * g0 * nl[N1 - 1];
+        if (hasr) out[N1 - 1] -= 0.5 * g1 * nr[0];
+    } else {
+#pragma unroll
+        for (int o = 0; o < N1; ++o) {
+            double s = 0.0;
+#pragma unroll
+            for (int j = 0; j < N1; ++j) s = fma((double)Lh[o * N1 + j], in[j], s);
+            out[o] = s * ih;
+        }
+        double dx0 = 0.0, dxn = 0.0;
+#pragma unroll
+        for (int j = 0; j < N1; ++j) {
+            dx0 = fma((double)d0[j], in[j], dx0);
+            dxn = fma((double)d1[j], in[j], dxn);
+        }
+        double e0 = eta0 * (g0 * x0 + ih * dx0);   // added to out[0]
+        double en = eta1 * (g1 * xn - ih * dxn);   // added to out[N1-1]
+        double c0 = eta0 * ih * x0, c1 = -eta1 * ih * xn;  // coefficients of d0, d1
+        if (hasl) {
+            double dl = 0.0;
+#pragma unroll
+            for (int j = 0; j < N1; ++j) dl = fma((double)d1[j], nl[j], dl);
+            const double xl = nl[N1 - 1];
+            e0 += dl / (2.0 * hl) - 0.5 * g0 * xl;
+            c0 -= 0.5 * ih * xl;
+        }
+        if (hasr) {
+            double dr = 0.0;
+#pragma unroll
+            for (int j = 0; j < N1; ++j) dr = fma((double)d0[j], nr[j], dr);
+            const double xr = nr[0];
+            en -= dr / (2.0 * hr) + 0.5 * g1 * xr;
+            c1 += 0.5 * ih * xr;
+        }
+        out[0] += e0;
+        out[N1 - 1] += en;
+#pragma unroll
+        for (int o = 0; o < N1; ++o) out[o] = fma((double)d0[o], c0, fma((double)d1[o], c1, out[o]));
+    }
+}
+
+// out = scale * Mhat in on one line.
+template <int N1, typename P>
+__device__ __forceinline__ void mass_regs(const double *in, double *out, double scale, P Mh) {
+#pragma unroll
+    for (int o = 0; o < N1; ++o) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < N1; ++j) s = fma((double)Mh[o * N1 + j], in[j], s);
+        out[o] = s * scale;
+    }
+}
+
+// y = A x (RES: y = b - A x) on the CPW cells cell0, cell0+1, ... of the mesh
+// described by g (x, b, y: that mesh's vectors).  Shared by the single-mesh
+// and the batched kernels.  Thread (q, l) works on cell cell0 + q and is in
+// turn the owner of line l along x, along y and along z.  LDS per cell: the
+// cell's coefficients X and two work slots U, V, lines along x padded to an
+// odd pitch.  Neighbour lines are read from global memory by the thread that
+// needs them.  Sequence (3-D):
+//   x-lines: W_x -> U                       y-lines: U <- h_y h_z Mhat U, W_y -> V
+//   x-lines: U += h_x h_z Mhat V            z-lines: U <- Mhat U,          W_z -> V
+//   y-lines: V <- h_x h_y Mhat V            x-lines: y = U + Mhat V (or b - ...)
+template <int D, int N1, bool RES, bool PEN = false>
+__device__ __forceinline__ void operator_cells(const LevelView &g, int64_t cell0, const double *__restrict__ x,
                                                const double *__restrict__ b, double *__restrict__ y) {
     using C = OpCfg<D, N1>;
-    constexpr int NC = C::NC, LINES = C::LINES, PPB = C::PPB, TH = C::THREADS;
-    constexpr int NS = 2 * D + 1;  // LDS slots per cell
-    __shared__ double S[PPB][NS][NC];
-    __shared__ int64_t src_cell[PPB][NS];  // -1: absent
+    constexpr int NC = C::NC, LINES = C::LINES, CPW = C::CPW, TH = C::THREADS, P = C::P, SL = C::SLOT;
+    __shared__ double S[CPW][3][SL];
     const int t = threadIdx.x;
     const int q = t / LINES, l = t % LINES;
-    const int64_t cs[3] = {1, g.m[0], (int64_t)g.m[0] * g.m[1]};
-    for (int e = t; e < PPB * NS; e += TH) {
-        const int qq = e / NS, slot = e % NS;
-        const int64_t cc = cell0 + qq;
-        int64_t src = cc < g.ncells ? cc : -1;
-        if (src >= 0 && slot > 0) {
-            int c3[3];
-            cell_coords(cc, g.m, c3);
-            const int a = (slot - 1) >> 1, dir = (slot - 1) & 1;  // dir 0: -e_a, 1: +e_a
-            const int nb = c3[a] + (dir ? 1 : -1);
-            src = (nb < 0 || nb >= g.m[a]) ? -1 : cc + (dir ? cs[a] : -cs[a]);
-        }
-        src_cell[qq][slot] = src;
-    }
-    __syncthreads();
-    // stage cells and neighbours (whole cells, coalesced); loads are issued in
-    // chunks of independent registers before the LDS stores
-    constexpr int TOT = PPB * NS * NC, ITER = (TOT + TH - 1) / TH, CH = 8;
-#pragma unroll
-    for (int k0 = 0; k0 < ITER; k0 += CH) {
-        double v[CH];
-#pragma unroll
-        for (int k = 0; k < CH; ++k) {
-            const int p = t + (k0 + k) * TH;
-            v[k] = 0.0;
-            if (k0 + k < ITER && p < TOT) {
-                const int qs = p / NC, i = p % NC;
-                const int64_t src = src_cell[qs / NS][qs % NS];
-                if (src >= 0) v[k] = x[src * NC + i];
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < CH; ++k) {
-            const int p = t + (k0 + k) * TH;
-            if (k0 + k < ITER && p < TOT) {
-                const int qs = p / NC, i = p % NC;
-                S[qs / NS][qs % NS][i] = v[k];
-            }
-        }
-    }
-    __syncthreads();
     const int64_t cell = cell0 + q;
-    const bool act = (q < PPB) && (cell < g.ncells);
-    // PPB == 1: the cell, its coordinates and all table addresses are uniform
+    const bool act = q < CPW && cell < g.ncells;
+    const cptr<double> Lh = uniform_table(g.Lhat), Mh = uniform_table(g.Mhat);
+    const cptr<double> d0 = uniform_table(g.d0), d1 = uniform_table(g.d1);
+    const double gk = PEN ? g.pk : g.gk;
+    // padded LDS index of cell-local coefficient (i0, i1, i2)
+    auto li = [](int i0, int i1, int i2) { return i0 + P * (i1 + N1 * i2); };
+
+    // own cells, coalesced
+    {
+        const int64_t ncopy = min((int64_t)CPW, g.ncells - cell0) * NC;
+        const double *src = x + cell0 * NC;
+        for (int e = t; e < ncopy; e += TH) {
+            const int qq = e / NC, i = e % NC;
+            const int i0 = i % N1, rest = i / N1;
+            S[qq][0][i0 + P * rest] = src[e];
+        }
+    }
     int c[3] = {0, 0, 0};
-    cell_coords(cell0 < g.ncells ? cell0 : 0, g.m, c);
-    for (int a = 0; a < 3; ++a) c[a] = __builtin_amdgcn_readfirstlane(c[a]);
-    const double hx = uniform_table(g.h[0])[c[0]], hy = uniform_table(g.h[1])[c[1]];
-    const double hz = D == 3 ? (double)uniform_table(g.h[2])[c[2]] : 1.0;
-    double w[D][N1];
+    double h[3] = {1.0, 1.0, 1.0};
+    const int64_t cs[3] = {1, g.m[0], (int64_t)g.m[0] * g.m[1]};
     if (act) {
+        const int cc = (int)cell, r0 = cc / g.m[0];
+        c[0] = cc - r0 * g.m[0];
+        c[1] = D == 3 ? r0 % g.m[1] : r0;
+        c[2] = D == 3 ? r0 / g.m[1] : 0;
 #pragma unroll
-        for (int a = 0; a < D; ++a) {
-            const int base = line_base<D, N1>(a, l), st = line_stride<N1>(a);
-            double in[N1];
-#pragma unroll
-            for (int i = 0; i < N1; ++i) in[i] = S[q][0][base + i * st];
-            cptr<double> A = uniform_table(g.cellop[a] + (size_t)c[a] * N1 * N1);
-#pragma unroll
-            for (int o = 0; o < N1; ++o) {
-                double s = 0.0;
-#pragma unroll
-                for (int i = 0; i < N1; ++i) s = fma((double)A[o * N1 + i], in[i], s);
-                w[a][o] = s;
-            }
-            if (c[a] + 1 < g.m[a]) {
-#pragma unroll
-                for (int i = 0; i < N1; ++i) in[i] = S[q][2 + 2 * a][base + i * st];
-                cptr<double> B = uniform_table(g.iface[a] + (size_t)c[a] * N1 * N1);
-#pragma unroll
-                for (int o = 0; o < N1; ++o)
-#pragma unroll
-                    for (int i = 0; i < N1; ++i) w[a][o] = fma((double)B[o * N1 + i], in[i], w[a][o]);
-            }
-            if (c[a] > 0) {
-#pragma unroll
-                for (int i = 0; i < N1; ++i) in[i] = S[q][1 + 2 * a][base + i * st];
-                cptr<double> B = uniform_table(g.iface[a] + (size_t)(c[a] - 1) * N1 * N1);
-#pragma unroll
-                for (int o = 0; o < N1; ++o)
-#pragma unroll
-                    for (int i = 0; i < N1; ++i) w[a][o] = fma((double)B[i * N1 + o], in[i], w[a][o]);
-            }
-        }
+        for (int a = 0; a < D; ++a) h[a] = g.h[a][c[a]];
     }
-    __syncthreads();  // neighbour slots are free from here on
-    double *W0 = S[q][1], *W1 = S[q][2], *U = D == 3 ? S[q][4] : S[q][3];
-    if (act) {
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            const int base = line_base<D, N1>(a, l), st = line_stride<N1>(a);
-            double *Wa = S[q][1 + a];
-#pragma unroll
-            for (int o = 0; o < N1; ++o) Wa[base + o * st] = w[a][o];
+    // line l along axis a: its fixed cell-local indices
+    auto line_idx = [&](int a, int j) {  // global offset (within a cell) of element j of line l along a
+        if constexpr (D == 3) {
+            const int u = l % N1, v = l / N1;
+            return a == 0 ? j + N1 * (u + N1 * v) : (a == 1 ? u + N1 * (j + N1 * v) : u + N1 * (v + N1 * j));
+        } else {
+            return a == 0 ? j + N1 * l : l + N1 * j;
         }
-    }
+    };
+    auto lds_idx = [&](int a, int j) {
+        if constexpr (D == 3) {
+            const int u = l % N1, v = l / N1;
+            return a == 0 ? li(j, u, v) : (a == 1 ? li(u, j, v) : li(u, v, j));
+        } else {
+            return a == 0 ? li(j, l, 0) : li(l, j, 0);
+        }
+    };
+    // W_a on this thread's line along axis a
+    auto w_line = [&](int a, double *w) {
+        double in[N1], nl[N1], nr[N1];
+#pragma unroll
+        for (int j = 0; j < N1; ++j) in[j] = S[q][0][lds_idx(a, j)];
+        const bool hasl = c[a] > 0, hasr = c[a] + 1 < g.m[a];
+        double hl = 1.0, hr = 1.0;
+        if (hasl) {
+            const double *src = x + (cell - cs[a]) * NC;
+#pragma unroll
+            for (int j = 0; j < N1; ++j) nl[j] = src[line_idx(a, j)];
+            hl = g.h[a][c[a] - 1];
+        }
+        if (hasr) {
+            const double *src = x + (cell + cs[a]) * NC;
+#pragma unroll
+            for (int j = 0; j < N1; ++j) nr[j] = src[line_idx(a, j)];
+            hr = g.h[a][c[a] + 1];
+        }
+        sipg_line<N1, PEN>(in, nl, nr, hasl, hasr, h[a], hl, hr, gk, Lh, d0, d1, w);
+    };
+    auto ld = [&](int slot, int a, double *v) {
+#pragma unroll
+        for (int j = 0; j < N1; ++j) v[j] = S[q][slot][lds_idx(a, j)];
+    };
+    auto st = [&](int slot, int a, const double *v) {
+#pragma unroll
+        for (int j = 0; j < N1; ++j) S[q][slot][lds_idx(a, j)] = v[j];
+    };
     __syncthreads();
-    cptr<double> Mh = uniform_table(g.Mhat);
-    double *Y;
-    if constexpr (D == 2) {
-        if (act) mass_line<D, N1>(W0, U, 1, l, hy, Mh, false);
-        __syncthreads();
-        if (act) mass_line<D, N1>(W1, U, 0, l, hx, Mh, true);
-        __syncthreads();
-        Y = U;
-    } else {
-        double *W2 = S[q][3], *X2 = S[q][5];
-        // U = hy hz (Mhat_y W_x) + hx hz (Mhat_x W_y);  X2 = Mhat_y W_z
-        if (act) mass_line<D, N1>(W0, U, 1, l, hy * hz, Mh, false);
+    double w[N1], v[N1], m[N1];
+    if constexpr (D == 3) {
+        if (act) {
+            w_line(0, w);
+            st(1, 0, w);
+        }
         __syncthreads();
         if (act) {
-            mass_line<D, N1>(W1, U, 0, l, hx * hz, Mh, true);
-            mass_line<D, N1>(W2, X2, 1, l, 1.0, Mh, false);
+            ld(1, 1, v);
+            mass_regs<N1>(v, m, h[1] * h[2], Mh);
+            st(1, 1, m);
+            w_line(1, w);
+            st(2, 1, w);
         }
         __syncthreads();
-        // W0 = Mhat_z U;  W0 += hx hy Mhat_x X2
-        if (act) mass_line<D, N1>(U, W0, 2, l, 1.0, Mh, false);
+        if (act) {
+            ld(2, 0, v);
+            mass_regs<N1>(v, m, h[0] * h[2], Mh);
+            ld(1, 0, v);
+#pragma unroll
+            for (int j = 0; j < N1; ++j) v[j] += m[j];
+            st(1, 0, v);
+        }
         __syncthreads();
-        if (act) mass_line<D, N1>(X2, W0, 0, l, hx * hy, Mh, true);
+        if (act) {
+            ld(1, 2, v);
+            mass_regs<N1>(v, m, 1.0, Mh);
+            st(1, 2, m);
+            w_line(2, w);
+            st(2, 2, w);
+        }
         __syncthreads();
-        Y = W0;
-    }
-    (void)Y;
-    for (int p = t; p < PPB * NC; p += TH) {
-        const int qq = p / NC, i = p % NC;
-        const int64_t cc = cell0 + qq;
-        if (cc < g.ncells) {
-            const int64_t gi = cc * NC + i;
-            const double v = S[qq][1][i];  // W0 of cell qq holds the result (U for 2-D)
-            const double yv = D == 3 ? v : S[qq][3][i];
-            y[gi] = RES ? b[gi] - yv : yv;
+        if (act) {
+            ld(2, 1, v);
+            mass_regs<N1>(v, m, h[0] * h[1], Mh);
+            st(2, 1, m);
+        }
+        __syncthreads();
+        if (act) {
+            ld(2, 0, v);
+            mass_regs<N1>(v, m, 1.0, Mh);
+            ld(1, 0, v);
+            double *dst = y + cell * NC + line_idx(0, 0);
+            if constexpr (RES) {
+                const double *bb = b + cell * NC + line_idx(0, 0);
+#pragma unroll
+                for (int j = 0; j < N1; ++j) dst[j] = bb[j] - (v[j] + m[j]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < N1; ++j) dst[j] = v[j] + m[j];
+            }
+        }
+    } else {
+        if (act) {
+            w_line(0, w);
+            st(1, 0, w);
+        }
+        __syncthreads();
+        if (act) {
+            ld(1, 1, v);
+            mass_regs<N1>(v, m, h[1], Mh);
+            st(1, 1, m);
+            w_line(1, w);
+            st(2, 1, w);
+        }
+        __syncthreads();
+        if (act) {
+            ld(2, 0, v);
+            mass_regs<N1>(v, m, h[0], Mh);
+            ld(1, 0, v);
+            double *dst = y + cell * NC + line_idx(0, 0);
+            if constexpr (RES) {
+                const double *bb = b + cell * NC + line_idx(0, 0);
+#pragma unroll
+                for (int j = 0; j < N1; ++j) dst[j] = bb[j] - (v[j] + m[j]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < N1; ++j) dst[j] = v[j] + m[j];
+            }
         }
     }
 }

@@ -64,6 +64,9 @@ struct LevelView {
     const double *h[3];       // per axis widths
     const double *Mhat;       // n1 x n1
     const double *E;          // 2 x n1 x n1 embedding matrices
+    const double *Lhat;       // n1 x n1 reference stiffness
+    const double *d0, *d1;    // derivatives of the basis at 0 and at 1
+    double gk, pk;            // gamma_hat k (k+1) and k (k+1)
 };
 
 // The coarse matrix stored by slabs of cells (all cells sharing their
@@ -107,7 +110,6 @@ struct fts_level {
     std::vector<double> host_cellop[3], host_iface[3];
     double *d_tab = nullptr;  // single device allocation holding every table
     fts::LevelView view{};
-    fts::LevelView view_pen{};  // same mesh, 1-D tables of dA/dgamma_hat (penalty terms)
 };
 
 struct fts_eigs {
@@ -155,6 +157,8 @@ fts_status launch_cg_update(double *x, double *r, const double *p, const double 
                             hipStream_t stream);
 fts_status launch_xpby(double *p, const double *z, double beta, int64_t n, hipStream_t stream);
 int red_partials();
+// cells per workgroup of the operator kernels (the batched residual's blocks)
+int operator_cells_per_block(int dim, int n1);
 
 // Direct solver of the coarsest level (coarse.hip).
 struct CoarseLU;

@@ -12,10 +12,10 @@
 
 namespace fts {
 
-template <int D, int N1, bool RES>
+template <int D, int N1, bool RES, bool PEN>
 __global__ void __launch_bounds__((OpCfg<D, N1>::THREADS))
 k_operator(LevelView g, const double *__restrict__ x, const double *__restrict__ b, double *__restrict__ y) {
-    operator_block<D, N1, RES>(g, (int64_t)blockIdx.x * OpCfg<D, N1>::PPB, x, b, y);
+    operator_cells<D, N1, RES, PEN>(g, (int64_t)blockIdx.x * OpCfg<D, N1>::CPW, x, b, y);
 }
 
 // ---------------------------------------------------------------------------
@@ -29,13 +29,12 @@ k_operator(LevelView g, const double *__restrict__ x, const double *__restrict__
 // correction of subdomain s is written to W[s][cell of the subdomain][DoF]
 // and k_patch_gather adds the contributions to x in a fixed order.
 template <int D, int N1, int KIND, typename T, bool STAGE>
-__global__ void __launch_bounds__((SwCfg<D, N1, KIND>::THREADS))
-k_schwarz(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r, double *__restrict__ x,
-          double *__restrict__ W, double omega) {
+__device__ __forceinline__ void schwarz_generic(const LevelView &g, const EigView &e, const SubGrid &sg,
+                                                const double *__restrict__ r, double *__restrict__ x,
+                                                double *__restrict__ W, double omega, T *Ts) {
     using C = SwCfg<D, N1, KIND>;
     constexpr int N = C::N, NT = C::NT, NC1 = C::NC1, NSC = C::NSC, LINES = C::LINES, PPB = C::PPB,
                   TH = C::THREADS;
-    __shared__ T Ts[PPB * NT];
     const int t = threadIdx.x;
     const int q = t / LINES, l = t % LINES;
     const int64_t s0 = (int64_t)blockIdx.x * PPB;
@@ -143,6 +142,90 @@ k_schwarz(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r, doub
             x[gi] = x[gi] + (double)Ts[qq * NT + lds];
         }
     }
+}
+
+// 3-D, one subdomain per workgroup: thread l < N^2 owns the line along the
+// first axis with the other two local indices (a1, a2) = (l % N, l / N).  It
+// reads its line of the residual straight from global memory (2 runs of k+1
+// contiguous values for a patch, one for a cell), applies the first forward
+// contraction in registers and only then goes through LDS for the other
+// axes; the last backward contraction also ends in registers and is written
+// to the staging buffer (or added to x) directly.  Index arithmetic happens
+// once per thread, not once per element.
+template <int N1, int KIND, typename T, bool STAGE>
+__device__ __forceinline__ void schwarz_lines3(const LevelView &g, const EigView &e, const SubGrid &sg,
+                                               const double *__restrict__ r, double *__restrict__ x,
+                                               double *__restrict__ W, double omega, T *Ts) {
+    using C = SwCfg<3, N1, KIND>;
+    constexpr int N = C::N, NC1 = C::NC1, NSC = C::NSC, LINES = C::LINES, NO = KIND ? 2 : 1;
+    const int l = threadIdx.x;
+    const int s = blockIdx.x;
+    int pos[3];
+    {
+        const int j0 = s % sg.cnt[0], rr = s / sg.cnt[0];
+        pos[0] = __builtin_amdgcn_readfirstlane(sg.first[0] + sg.step * j0);
+        pos[1] = __builtin_amdgcn_readfirstlane(sg.first[1] + sg.step * (rr % sg.cnt[1]));
+        pos[2] = __builtin_amdgcn_readfirstlane(sg.first[2] + sg.step * (rr / sg.cnt[1]));
+    }
+    const bool act = l < LINES;
+    const int a1 = l % N, a2 = l / N;
+    const int o1 = a1 / N1, i1 = a1 % N1, o2 = a2 / N1, i2 = a2 % N1;
+    const int64_t cs1 = g.m[0], cs2 = (int64_t)g.m[0] * g.m[1];
+    const int64_t cell0 = pos[0] + (pos[1] + o1) * cs1 + (pos[2] + o2) * cs2;
+    const int iofs = i1 * N1 + i2 * N1 * N1;
+    constexpr int nn = N * N;
+    T v[N], w[N];
+    if (act) {
+        const double *src = r + cell0 * NC1 + iofs;
+#pragma unroll
+        for (int o0 = 0; o0 < NO; ++o0)
+#pragma unroll
+            for (int i0 = 0; i0 < N1; ++i0) v[o0 * N1 + i0] = (T)src[o0 * NC1 + i0];
+        matvec_regs<N>(v, w, uniform_table(EigTab<T>::ST(e, 0) + (size_t)pos[0] * nn));
+#pragma unroll
+        for (int a = 0; a < N; ++a) Ts[N * l + a] = w[a];
+    }
+    __syncthreads();
+    if (act) contract_line<3, N, T>(Ts, 1, l, uniform_table(EigTab<T>::ST(e, 1) + (size_t)pos[1] * nn));
+    __syncthreads();
+    if (act) {
+        const T lr = (T)uniform_table(EigTab<T>::L(e, 0) + (size_t)pos[0] * N)[a1] +
+                     (T)uniform_table(EigTab<T>::L(e, 1) + (size_t)pos[1] * N)[a2];
+        last_axis_solve<3, N, T>(Ts, l, uniform_table(EigTab<T>::ST(e, 2) + (size_t)pos[2] * nn),
+                                 uniform_table(EigTab<T>::S(e, 2) + (size_t)pos[2] * nn),
+                                 uniform_table(EigTab<T>::L(e, 2) + (size_t)pos[2] * N), lr, (T)omega);
+    }
+    __syncthreads();
+    if (act) contract_line<3, N, T>(Ts, 1, l, uniform_table(EigTab<T>::S(e, 1) + (size_t)pos[1] * nn));
+    __syncthreads();
+    if (act) {
+#pragma unroll
+        for (int a = 0; a < N; ++a) v[a] = Ts[N * l + a];
+        matvec_regs<N>(v, w, uniform_table(EigTab<T>::S(e, 0) + (size_t)pos[0] * nn));
+        if constexpr (STAGE) {
+            double *dst = W + (int64_t)s * (NSC * NC1) + (2 * o1 + 4 * o2) * NC1 + iofs;
+#pragma unroll
+            for (int o0 = 0; o0 < NO; ++o0)
+#pragma unroll
+                for (int i0 = 0; i0 < N1; ++i0) dst[o0 * NC1 + i0] = (double)w[o0 * N1 + i0];
+        } else {
+            double *dst = x + cell0 * NC1 + iofs;
+#pragma unroll
+            for (int o0 = 0; o0 < NO; ++o0)
+#pragma unroll
+                for (int i0 = 0; i0 < N1; ++i0) dst[o0 * NC1 + i0] += (double)w[o0 * N1 + i0];
+        }
+    }
+}
+
+template <int D, int N1, int KIND, typename T, bool STAGE>
+__global__ void __launch_bounds__((SwCfg<D, N1, KIND>::THREADS))
+k_schwarz(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r, double *__restrict__ x,
+          double *__restrict__ W, double omega) {
+    using C = SwCfg<D, N1, KIND>;
+    __shared__ T Ts[C::PPB * C::NT];
+    if constexpr (D == 3 && C::PPB == 1) schwarz_lines3<N1, KIND, T, STAGE>(g, e, sg, r, x, W, omega, Ts);
+    else schwarz_generic<D, N1, KIND, T, STAGE>(g, e, sg, r, x, W, omega, Ts);
 }
 
 // x += sum over the 2^d vertex patches containing each cell of that patch's
@@ -528,12 +611,13 @@ struct RunOperator {
     static fts_status run(const fts_level *lv, const double *x, const double *b, double *y, bool res,
                           hipStream_t st) {
         using C = OpCfg<D, N1>;
-        const int64_t blocks = (lv->ncells + C::PPB - 1) / C::PPB;
+        if (lv->ncells > INT_MAX) return fail(FTS_E_SIZE, "too many cells for one launch");
+        const int64_t blocks = (lv->ncells + C::CPW - 1) / C::CPW;
         if (blocks == 0) return FTS_OK;
         if (res)
-            k_operator<D, N1, true><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(lv->view, x, b, y);
+            k_operator<D, N1, true, false><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(lv->view, x, b, y);
         else
-            k_operator<D, N1, false><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(lv->view, x, b, y);
+            k_operator<D, N1, false, false><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(lv->view, x, b, y);
         return check_launch("k_operator");
     }
 };
@@ -568,6 +652,7 @@ struct RunSchwarz {
             }
             if (sg.nsub == 0) continue;
             const int64_t blocks = (sg.nsub + C::PPB - 1) / C::PPB;
+            if (blocks > INT_MAX) return fail(FTS_E_SIZE, "too many subdomains for one launch");
             if (staged)
                 k_schwarz<D, N1, KIND, T, true><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(
                     lv->view, eg->view, sg, r, x, eg->d_stage, omega);
@@ -912,15 +997,25 @@ template <int D, int N1>
 struct RunOperatorPen {
     static fts_status run(const fts_level *lv, const double *x, double *y, hipStream_t st) {
         using C = OpCfg<D, N1>;
-        const int64_t blocks = (lv->ncells + C::PPB - 1) / C::PPB;
+        if (lv->ncells > INT_MAX) return fail(FTS_E_SIZE, "too many cells for one launch");
+        const int64_t blocks = (lv->ncells + C::CPW - 1) / C::CPW;
         if (blocks == 0) return FTS_OK;
-        k_operator<D, N1, false><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(lv->view_pen, x, nullptr, y);
+        k_operator<D, N1, false, true><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(lv->view, x, nullptr, y);
         return check_launch("k_operator (penalty)");
     }
 };
 
 fts_status launch_operator_penalty(const fts_level *lv, const double *x, double *y, hipStream_t stream) {
     return dispatch<RunOperatorPen>(lv->dim, lv->n1, lv, x, y, stream);
+}
+
+template <int D, int N1>
+struct OpCells {
+    static int run() { return OpCfg<D, N1>::CPW; }
+};
+int operator_cells_per_block(int dim, int n1) {
+    const int r = dispatch<OpCells>(dim, n1);
+    return r > 0 ? r : 1;
 }
 
 __global__ void __launch_bounds__(256) k_dot2_final_acc(const double *__restrict__ part, int nb, double scale,

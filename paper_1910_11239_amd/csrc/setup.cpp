@@ -357,27 +357,21 @@ fts_status fts_level_create(const fts_mesh_desc *mesh, fts_level **out) {
     const int n1 = lv->n1, nn = n1 * n1;
     // host tables
     size_t total = 0;
-    std::vector<double> pen_cell[3], pen_face[3];
     for (int a = 0; a < 3; ++a) {
         const int m = lv->m[a];
         lv->host_cellop[a].assign((size_t)m * nn, 0.0);
         lv->host_iface[a].assign((size_t)std::max(m - 1, 0) * nn, 0.0);
-        pen_cell[a].assign((size_t)m * nn, 0.0);
-        pen_face[a].assign((size_t)std::max(m - 1, 0) * nn, 0.0);
         for (int c = 0; c < m; ++c) {
             const double hl = c > 0 ? lv->h[a][c - 1] : -1.0;
             const double hr = c + 1 < m ? lv->h[a][c + 1] : -1.0;
             lv->ref.cell_operator(lv->h[a][c], hl, hr, lv->gamma_hat, &lv->host_cellop[a][(size_t)c * nn]);
-            lv->ref.cell_penalty(lv->h[a][c], hl, hr, &pen_cell[a][(size_t)c * nn]);
-            if (c + 1 < m) {
+            if (c + 1 < m)
                 lv->ref.interface_block(lv->h[a][c], lv->h[a][c + 1], lv->gamma_hat,
                                         &lv->host_iface[a][(size_t)c * nn]);
-                lv->ref.interface_penalty(lv->h[a][c], lv->h[a][c + 1], &pen_face[a][(size_t)c * nn]);
-            }
         }
-        total += 2 * (lv->host_cellop[a].size() + lv->host_iface[a].size()) + lv->h[a].size();
+        total += lv->host_cellop[a].size() + lv->host_iface[a].size() + lv->h[a].size();
     }
-    total += nn + 2 * nn;
+    total += nn + 2 * nn + nn + 2 * lv->n1;
     if (hipMalloc(&lv->d_tab, total * sizeof(double)) != hipSuccess) {
         delete lv;
         return fail(FTS_E_HIP, "hipMalloc of level tables failed");
@@ -395,22 +389,18 @@ fts_status fts_level_create(const fts_mesh_desc *mesh, fts_level **out) {
         lv->view.iface[a] = put(lv->host_iface[a]);
         lv->view.h[a] = put(lv->h[a]);
         lv->view.m[a] = lv->m[a];
-        lv->view_pen.cellop[a] = put(pen_cell[a]);
-        lv->view_pen.iface[a] = put(pen_face[a]);
     }
     lv->view.Mhat = put(lv->ref.Mhat);
     std::vector<double> E(2 * nn);
     std::copy(lv->ref.E[0].begin(), lv->ref.E[0].end(), E.begin());
     std::copy(lv->ref.E[1].begin(), lv->ref.E[1].end(), E.begin() + nn);
     lv->view.E = put(E);
+    lv->view.Lhat = put(lv->ref.Lhat);
+    lv->view.d0 = put(lv->ref.d0);
+    lv->view.d1 = put(lv->ref.d1);
+    lv->view.gk = lv->gamma_hat * lv->k * (lv->k + 1.0);
+    lv->view.pk = lv->k * (lv->k + 1.0);
     lv->view.ncells = lv->ncells;
-    for (int a = 0; a < 3; ++a) {
-        lv->view_pen.h[a] = lv->view.h[a];
-        lv->view_pen.m[a] = lv->m[a];
-    }
-    lv->view_pen.Mhat = lv->view.Mhat;
-    lv->view_pen.E = lv->view.E;
-    lv->view_pen.ncells = lv->ncells;
     if (hipMemcpy(lv->d_tab, host.data(), total * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
         hipFree(lv->d_tab);
         delete lv;
