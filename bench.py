@@ -44,6 +44,23 @@ def _events_time(fn, reps):
     return e0.elapsed_time(e1) / reps  # ms
 
 
+def measured_traffic(kernel):
+    """HBM bytes per call of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by the copy calibration), or
+    None when the kernel's source has changed since the counters were taken."""
+    import hashlib
+    tpath = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(tpath):
+        return None
+    rec = json.load(open(tpath)).get(kernel)
+    if not rec:
+        return None
+    src = os.path.join(ROOT, rec["source"])
+    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["sha256"]:
+        return None
+    return rec["bytes_per_call"]
+
+
 def cpu_baseline(cfg):
     """The oracle's V-cycle on the same workload reduced to 8^3 fine cells
     (3 levels 8^3/4^3/2^3, Q4, omega 0.5, 2/2 sweeps); setup excluded."""
@@ -250,10 +267,7 @@ def main():
         v["ms_per_step"] = v["ms_per_call"] * v["calls_per_step"]
     dom_name = max(kernels, key=lambda n: kernels[n]["ms_per_step"])
     dom = kernels[dom_name]
-    traffic = None
-    tpath = os.path.join(ROOT, "profiles", "traffic.json")
-    if os.path.exists(tpath):
-        traffic = json.load(open(tpath)).get(dom_name)
+    traffic = measured_traffic(dom_name)
     roofline = {"bound": dom["bound"], "achieved": round(dom["achieved"], 3), "peak": dom["peak"],
                 "unit": dom["unit"], "frac": round(dom["frac"], 4), "traffic": traffic, "kernel": dom_name}
 

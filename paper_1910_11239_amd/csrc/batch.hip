@@ -43,7 +43,7 @@ constexpr int kBatchMaxN = 20;  // vertex patch of degree 9
 
 template <int N1, int TH, typename T>
 __device__ __forceinline__ void batch_patch(const BatchMesh &M, int64_t p, const double *__restrict__ r,
-                                            double *__restrict__ W, T om, T *Ts) {
+                                            T *__restrict__ W, T om, T *Ts) {
     constexpr int D = 3, N = 2 * N1, NC1 = N1 * N1 * N1, NSC = 8, LINES = N * N, NN = N * N;
     const int t = threadIdx.x;
     int pos[3];
@@ -85,12 +85,12 @@ __device__ __forceinline__ void batch_patch(const BatchMesh &M, int64_t p, const
     for (int l = t; l < LINES; l += TH)
         contract_line<D, N, T>(Ts, 0, l, uniform_table(EigTab<T>::S(e, 0) + (size_t)pos[0] * NN));
     __syncthreads();
-    double *Wm = W + M.stage_off + p * (NSC * NC1);
+    T *Wm = W + M.stage_off + p * (NSC * NC1);
     for (int q = t; q < NSC * NC1; q += TH) {
         const int sc = q / NC1, i = q % NC1;
         const int o0 = sc & 1, o1 = (sc >> 1) & 1, o2 = (sc >> 2) & 1;
         const int i0 = i % N1, i1 = (i / N1) % N1, i2 = i / (N1 * N1);
-        Wm[q] = (double)Ts[(o0 * N1 + i0) + (o1 * N1 + i1) * N + (o2 * N1 + i2) * NN];
+        Wm[q] = Ts[(o0 * N1 + i0) + (o1 * N1 + i1) * N + (o2 * N1 + i2) * NN];
     }
     __syncthreads();  // Ts is reused by the next patch
 }
@@ -99,7 +99,7 @@ template <int TH, typename T>
 __global__ void __launch_bounds__(TH)
 k_batch_smooth(const BatchMesh *__restrict__ meshes, const int64_t *__restrict__ prefix,
                const int *__restrict__ order, int nslot, int64_t total, int chunk,
-               unsigned long long *__restrict__ counter, const double *__restrict__ r, double *__restrict__ W,
+               unsigned long long *__restrict__ counter, const double *__restrict__ r, T *__restrict__ W,
                double omega) {
     __shared__ T Ts[kBatchMaxN * kBatchMaxN * kBatchMaxN];
     __shared__ unsigned long long start_s;
@@ -141,9 +141,12 @@ k_batch_smooth(const BatchMesh *__restrict__ meshes, const int64_t *__restrict__
 
 __global__ void k_batch_reset(unsigned long long *counter) { *counter = 0ull; }
 
+// x += the staged corrections (FP64 or FP32, the contraction type) of the
+// 8 patches around each cell, in FP64 and in a fixed order.
+template <typename WT>
 __global__ void __launch_bounds__(256)
 k_batch_gather(const BatchMesh *__restrict__ meshes, const BatchBlock *__restrict__ blocks,
-               const double *__restrict__ W, double *__restrict__ x) {
+               const WT *__restrict__ W, double *__restrict__ x) {
     const BatchBlock B = blocks[blockIdx.x];
     const BatchMesh &M = meshes[B.mesh];
     const int n1 = M.n1, NC1 = n1 * n1 * n1;
@@ -159,7 +162,7 @@ k_batch_gather(const BatchMesh *__restrict__ meshes, const BatchBlock *__restric
         const int a0 = c[0] - (o & 1), a1 = c[1] - ((o >> 1) & 1), a2 = c[2] - ((o >> 2) & 1);
         if (a0 >= 0 && a0 < M.cnt[0] && a1 >= 0 && a1 < M.cnt[1] && a2 >= 0 && a2 < M.cnt[2]) {
             const int64_t sidx = a0 + (int64_t)M.cnt[0] * (a1 + (int64_t)M.cnt[1] * a2);
-            acc += W[M.stage_off + sidx * (8 * NC1) + o * NC1 + i];
+            acc += (double)W[M.stage_off + sidx * (8 * NC1) + o * NC1 + i];
         }
     }
     x[M.dof_off + gid] += acc;
@@ -224,8 +227,8 @@ static fts_status batch_launch_smooth(fts_batch *bt, int threads, int grid, int 
 #define FTS_BATCH_LAUNCH(TH)                                                                                  \
     if (f32)                                                                                                 \
         k_batch_smooth<TH, float><<<grid, TH, 0, s>>>(bt->d_meshes, bt->d_prefix, bt->d_order, bt->nslot,   \
-                                                      bt->patches_total, chunk, bt->d_counter, r, bt->d_stage, \
-                                                      omega);                                                \
+                                                      bt->patches_total, chunk, bt->d_counter, r,           \
+                                                      reinterpret_cast<float *>(bt->d_stage), omega);        \
     else                                                                                                     \
         k_batch_smooth<TH, double><<<grid, TH, 0, s>>>(bt->d_meshes, bt->d_prefix, bt->d_order, bt->nslot,  \
                                                        bt->patches_total, chunk, bt->d_counter, r,           \
@@ -384,7 +387,12 @@ fts_status fts_batch_apply(fts_batch *bt, double omega, fts_prec prec, const dou
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     fts_status st = batch_launch_smooth(bt, bt->threads, bt->grid, bt->chunk, prec, r, omega, s);
     if (st != FTS_OK) return st;
-    k_batch_gather<<<dim3((unsigned)bt->ngather), dim3(256), 0, s>>>(bt->d_meshes, bt->d_gather, bt->d_stage, x);
+    if (prec == FTS_PREC_F32)
+        k_batch_gather<float><<<dim3((unsigned)bt->ngather), dim3(256), 0, s>>>(
+            bt->d_meshes, bt->d_gather, reinterpret_cast<const float *>(bt->d_stage), x);
+    else
+        k_batch_gather<double><<<dim3((unsigned)bt->ngather), dim3(256), 0, s>>>(bt->d_meshes, bt->d_gather,
+                                                                                 bt->d_stage, x);
     return check_launch("k_batch_gather");
 }
 

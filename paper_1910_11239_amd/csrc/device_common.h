@@ -211,16 +211,16 @@ inline fts_status check_launch(const char *what) {
 
 // One 1-D operator along axis t on a line of cell K (eq. 1Dsipg with the
 // interface blocks of eq. 1Dsipginterface): in = the line of K, nl / nr = the
-// same line in the neighbours K - e_t / K + e_t (used when present), h, hl,
-// hr = widths, gk = gamma_hat k (k+1).  PEN: only the penalty terms, i.e.
-// dA/dgamma_hat with gk = k (k+1).
+// same line in the neighbours K - e_t / K + e_t (used when present), ih, ihl,
+// ihr = inverse widths, gk = gamma_hat k (k+1).  PEN: only the penalty terms,
+// i.e. dA/dgamma_hat with gk = k (k+1).
 template <int N1, bool PEN, typename P>
 __device__ __forceinline__ void sipg_line(const double *in, const double *nl, const double *nr, bool hasl, bool hasr,
-                                          double h, double hl, double hr, double gk, P Lh, P d0, P d1, double *out) {
-    const double ih = 1.0 / h;
+                                          double ih, double ihl, double ihr, double gk, P Lh, P d0, P d1,
+                                          double *out) {
     const double eta0 = hasl ? 0.5 : 1.0, eta1 = hasr ? 0.5 : 1.0;
-    const double g0 = hasl ? gk * (ih + 1.0 / hl) : 2.0 * gk * ih;
-    const double g1 = hasr ? gk * (ih + 1.0 / hr) : 2.0 * gk * ih;
+    const double g0 = hasl ? gk * (ih + ihl) : 2.0 * gk * ih;
+    const double g1 = hasr ? gk * (ih + ihr) : 2.0 * gk * ih;
     const double x0 = in[0], xn = in[N1 - 1];
     if constexpr (PEN) {
 #pragma unroll
@@ -251,7 +251,7 @@ __device__ __forceinline__ void sipg_line(const double *in, const double *nl, co
 #pragma unroll
             for (int j = 0; j < N1; ++j) dl = fma((double)d1[j], nl[j], dl);
             const double xl = nl[N1 - 1];
-            e0 += dl / (2.0 * hl) - 0.5 * g0 * xl;
+            e0 += 0.5 * (dl * ihl - g0 * xl);
             c0 -= 0.5 * ih * xl;
         }
         if (hasr) {
@@ -259,7 +259,7 @@ __device__ __forceinline__ void sipg_line(const double *in, const double *nl, co
 #pragma unroll
             for (int j = 0; j < N1; ++j) dr = fma((double)d0[j], nr[j], dr);
             const double xr = nr[0];
-            en -= dr / (2.0 * hr) + 0.5 * g1 * xr;
+            en -= 0.5 * (dr * ihr + g1 * xr);
             c1 += 0.5 * ih * xr;
         }
         out[0] += e0;
@@ -351,20 +351,20 @@ __device__ __forceinline__ void operator_cells(const LevelView &g, int64_t cell0
 #pragma unroll
         for (int j = 0; j < N1; ++j) in[j] = S[q][0][lds_idx(a, j)];
         const bool hasl = c[a] > 0, hasr = c[a] + 1 < g.m[a];
-        double hl = 1.0, hr = 1.0;
+        double ihl = 1.0, ihr = 1.0;
         if (hasl) {
             const double *src = x + (cell - cs[a]) * NC;
 #pragma unroll
             for (int j = 0; j < N1; ++j) nl[j] = src[line_idx(a, j)];
-            hl = g.h[a][c[a] - 1];
+            ihl = g.ih[a][c[a] - 1];
         }
         if (hasr) {
             const double *src = x + (cell + cs[a]) * NC;
 #pragma unroll
             for (int j = 0; j < N1; ++j) nr[j] = src[line_idx(a, j)];
-            hr = g.h[a][c[a] + 1];
+            ihr = g.ih[a][c[a] + 1];
         }
-        sipg_line<N1, PEN>(in, nl, nr, hasl, hasr, h[a], hl, hr, gk, Lh, d0, d1, w);
+        sipg_line<N1, PEN>(in, nl, nr, hasl, hasr, g.ih[a][c[a]], ihl, ihr, gk, Lh, d0, d1, w);
     };
     auto ld = [&](int slot, int a, double *v) {
 #pragma unroll

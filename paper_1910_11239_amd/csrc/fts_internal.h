@@ -62,6 +62,7 @@ struct LevelView {
     const double *cellop[3];  // per axis: m[a] blocks of n1 x n1 (A_cell, eq. 1Dsipg)
     const double *iface[3];   // per axis: m[a]-1 blocks, coupling cell c (test) to c+1 (trial)
     const double *h[3];       // per axis widths
+    const double *ih[3];      // per axis 1 / widths
     const double *Mhat;       // n1 x n1
     const double *E;          // 2 x n1 x n1 embedding matrices
     const double *Lhat;       // n1 x n1 reference stiffness
@@ -119,7 +120,9 @@ struct fts_eigs {
     std::vector<double> A[3], M[3], S[3], lam[3], DG[3];
     double *d_tab = nullptr;
     float *d_tab32 = nullptr;
-    double *d_stage = nullptr;  // staged corrections of all vertex patches (one per cell of each)
+    double *d_stage = nullptr;  // staged corrections of all vertex patches (one per cell of each;
+                                // FP64 or FP32 values, sized for FP64)
+    double *d_stage_scale = nullptr;  // one FP64 factor per patch for the 16-bit path
     void *d_mfma = nullptr;     // 16-bit MFMA tables (n <= 16 only)
     int schedule = FTS_SCHEDULE_STAGED;
     fts::EigView view{};

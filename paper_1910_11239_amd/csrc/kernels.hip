@@ -26,12 +26,13 @@ k_operator(LevelView g, const double *__restrict__ x, const double *__restrict__
 // local index a_t = (cell offset)_t (k+1) + i_t.  T is the contraction type.
 // STAGE = false: x += correction (the subdomains of one launch must not share
 // cells: cells, or one parquet color of vertex patches).  STAGE = true: the
-// correction of subdomain s is written to W[s][cell of the subdomain][DoF]
-// and k_patch_gather adds the contributions to x in a fixed order.
+// correction of subdomain s is written to W[s][cell of the subdomain][DoF] in
+// the contraction type T and k_patch_gather adds the contributions to x in
+// FP64 in a fixed order.
 template <int D, int N1, int KIND, typename T, bool STAGE>
 __device__ __forceinline__ void schwarz_generic(const LevelView &g, const EigView &e, const SubGrid &sg,
                                                 const double *__restrict__ r, double *__restrict__ x,
-                                                double *__restrict__ W, double omega, T *Ts) {
+                                                T *__restrict__ W, double omega, T *Ts) {
     using C = SwCfg<D, N1, KIND>;
     constexpr int N = C::N, NT = C::NT, NC1 = C::NC1, NSC = C::NSC, LINES = C::LINES, PPB = C::PPB,
                   TH = C::THREADS;
@@ -136,7 +137,7 @@ __device__ __forceinline__ void schwarz_generic(const LevelView &g, const EigVie
         const int i0 = i % N1, i1 = (i / N1) % N1, i2 = D == 3 ? i / (N1 * N1) : 0;
         const int lds = (o0 * N1 + i0) + (o1 * N1 + i1) * N + (D == 3 ? (o2 * N1 + i2) * N * N : 0);
         if constexpr (STAGE) {
-            W[ss * (NSC * NC1) + rem] = (double)Ts[qq * NT + lds];
+            W[ss * (NSC * NC1) + rem] = Ts[qq * NT + lds];
         } else {
             const int64_t gi = cell * NC1 + i;
             x[gi] = x[gi] + (double)Ts[qq * NT + lds];
@@ -155,7 +156,7 @@ __device__ __forceinline__ void schwarz_generic(const LevelView &g, const EigVie
 template <int N1, int KIND, typename T, bool STAGE>
 __device__ __forceinline__ void schwarz_lines3(const LevelView &g, const EigView &e, const SubGrid &sg,
                                                const double *__restrict__ r, double *__restrict__ x,
-                                               double *__restrict__ W, double omega, T *Ts) {
+                                               T *__restrict__ W, double omega, T *Ts) {
     using C = SwCfg<3, N1, KIND>;
     constexpr int N = C::N, NC1 = C::NC1, NSC = C::NSC, LINES = C::LINES, NO = KIND ? 2 : 1;
     const int l = threadIdx.x;
@@ -203,11 +204,11 @@ __device__ __forceinline__ void schwarz_lines3(const LevelView &g, const EigView
         for (int a = 0; a < N; ++a) v[a] = Ts[N * l + a];
         matvec_regs<N>(v, w, uniform_table(EigTab<T>::S(e, 0) + (size_t)pos[0] * nn));
         if constexpr (STAGE) {
-            double *dst = W + (int64_t)s * (NSC * NC1) + (2 * o1 + 4 * o2) * NC1 + iofs;
+            T *dst = W + (int64_t)s * (NSC * NC1) + (2 * o1 + 4 * o2) * NC1 + iofs;
 #pragma unroll
             for (int o0 = 0; o0 < NO; ++o0)
 #pragma unroll
-                for (int i0 = 0; i0 < N1; ++i0) dst[o0 * NC1 + i0] = (double)w[o0 * N1 + i0];
+                for (int i0 = 0; i0 < N1; ++i0) dst[o0 * NC1 + i0] = w[o0 * N1 + i0];
         } else {
             double *dst = x + cell0 * NC1 + iofs;
 #pragma unroll
@@ -221,7 +222,7 @@ __device__ __forceinline__ void schwarz_lines3(const LevelView &g, const EigView
 template <int D, int N1, int KIND, typename T, bool STAGE>
 __global__ void __launch_bounds__((SwCfg<D, N1, KIND>::THREADS))
 k_schwarz(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r, double *__restrict__ x,
-          double *__restrict__ W, double omega) {
+          T *__restrict__ W, double omega) {
     using C = SwCfg<D, N1, KIND>;
     __shared__ T Ts[C::PPB * C::NT];
     if constexpr (D == 3 && C::PPB == 1) schwarz_lines3<N1, KIND, T, STAGE>(g, e, sg, r, x, W, omega, Ts);
@@ -230,9 +231,12 @@ k_schwarz(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r, doub
 
 // x += sum over the 2^d vertex patches containing each cell of that patch's
 // staged correction (Sec. 2.3, eq. additiveschwarz), in the fixed order of the
-// cell's position inside the patch: deterministic, no write conflicts.
-template <int D, int N1>
-__global__ void __launch_bounds__(256) k_patch_gather(LevelView g, const double *__restrict__ W, double *__restrict__ x) {
+// cell's position inside the patch: deterministic, no write conflicts.  The
+// staged values are FP64 or FP32 (the contraction type); SCALED: each patch's
+// FP32 values carry one FP64 factor, multiplied in here.
+template <int D, int N1, typename WT, bool SCALED>
+__global__ void __launch_bounds__(256) k_patch_gather(LevelView g, const WT *__restrict__ W,
+                                                      const double *__restrict__ Wsc, double *__restrict__ x) {
     constexpr int NC1 = ipow(N1, D), NSC = 1 << D;
     const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (gid >= g.ncells * NC1) return;
@@ -248,7 +252,8 @@ __global__ void __launch_bounds__(256) k_patch_gather(LevelView g, const double 
         const bool in = a0 >= 0 && a0 < cnt0 && a1 >= 0 && a1 < cnt1 && (D == 2 || (a2 >= 0 && a2 < g.m[2] - 1));
         if (in) {
             const int64_t sidx = a0 + (int64_t)cnt0 * (a1 + (int64_t)cnt1 * a2);
-            acc += W[sidx * (NSC * NC1) + o * NC1 + i];
+            const double w = (double)W[sidx * (NSC * NC1) + o * NC1 + i];
+            acc += SCALED ? Wsc[sidx] * w : w;
         }
     }
     x[gid] += acc;
@@ -336,7 +341,7 @@ struct Mfma16<1> {
 template <int N1, int KIND, int BF, bool STAGE>
 __global__ void __launch_bounds__(256)
 k_schwarz_mfma(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r, double *__restrict__ x,
-               double *__restrict__ W, double omega) {
+               float *__restrict__ W, double *__restrict__ Wsc, double omega) {
     using M = Mfma16<BF>;
     constexpr int D = 3;
     constexpr int N = KIND ? 2 * N1 : N1;
@@ -442,14 +447,16 @@ k_schwarz_mfma(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r,
     const double sx = e.mscale[0][pos[0]], sy = e.mscale[1][pos[1]], sz = e.mscale[2][pos[2]];
     const double lmin = (double)e.lmin[0][pos[0]] + e.lmin[1][pos[1]] + e.lmin[2][pos[2]];
     const double F = (double)rmax * omega * (sx * sy * sz) * (sx * sy * sz) / lmin;
+    if (STAGE && t == 0) Wsc[s] = F;
     for (int p = t; p < NSC * NC1; p += 256) {
         const int sc = p / NC1, i = p % NC1;
         const int o0 = sc & 1, o1 = (sc >> 1) & 1, o2 = (sc >> 2) & 1;
         const int i0 = i % N1, i1 = (i / N1) % N1, i2 = i / (N1 * N1);
-        const double v = F * (double)Ts[(o0 * N1 + i0) + (o1 * N1 + i1) * kPy + (o2 * N1 + i2) * kPz];
+        const float c = Ts[(o0 * N1 + i0) + (o1 * N1 + i1) * kPy + (o2 * N1 + i2) * kPz];
         if constexpr (STAGE) {
-            W[s * (NSC * NC1) + p] = v;
+            W[s * (NSC * NC1) + p] = c;  // F applied by the gather
         } else {
+            const double v = F * (double)c;
             const int64_t cell = (pos[0] + o0) + (pos[1] + o1) * cs1 + (pos[2] + o2) * cs2;
             const int64_t gi = cell * NC1 + i;
             x[gi] = x[gi] + v;
@@ -655,7 +662,7 @@ struct RunSchwarz {
             if (blocks > INT_MAX) return fail(FTS_E_SIZE, "too many subdomains for one launch");
             if (staged)
                 k_schwarz<D, N1, KIND, T, true><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(
-                    lv->view, eg->view, sg, r, x, eg->d_stage, omega);
+                    lv->view, eg->view, sg, r, x, reinterpret_cast<T *>(eg->d_stage), omega);
             else
                 k_schwarz<D, N1, KIND, T, false><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(
                     lv->view, eg->view, sg, r, x, nullptr, omega);
@@ -664,7 +671,8 @@ struct RunSchwarz {
         }
         if (staged) {
             const int64_t n = lv->ndofs;
-            k_patch_gather<D, N1><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(lv->view, eg->d_stage, x);
+            k_patch_gather<D, N1, T, false><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(
+                lv->view, reinterpret_cast<const T *>(eg->d_stage), nullptr, x);
             return check_launch("k_patch_gather");
         }
         return FTS_OK;
@@ -690,16 +698,18 @@ struct RunSchwarz {
                 if (sg.nsub == 0) continue;
                 if (staged)
                     k_schwarz_mfma<N1, KIND, BF, true><<<dim3((unsigned)sg.nsub), dim3(256), 0, st>>>(
-                        lv->view, eg->view, sg, r, x, eg->d_stage, omega);
+                        lv->view, eg->view, sg, r, x, reinterpret_cast<float *>(eg->d_stage), eg->d_stage_scale,
+                        omega);
                 else
                     k_schwarz_mfma<N1, KIND, BF, false><<<dim3((unsigned)sg.nsub), dim3(256), 0, st>>>(
-                        lv->view, eg->view, sg, r, x, nullptr, omega);
+                        lv->view, eg->view, sg, r, x, nullptr, nullptr, omega);
                 fts_status s = check_launch("k_schwarz_mfma");
                 if (s != FTS_OK) return s;
             }
             if (staged) {
                 const int64_t n = lv->ndofs;
-                k_patch_gather<D, N1><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(lv->view, eg->d_stage, x);
+                k_patch_gather<D, N1, float, true><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(
+                    lv->view, reinterpret_cast<const float *>(eg->d_stage), eg->d_stage_scale, x);
                 return check_launch("k_patch_gather");
             }
             return FTS_OK;

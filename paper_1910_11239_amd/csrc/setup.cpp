@@ -369,7 +369,7 @@ fts_status fts_level_create(const fts_mesh_desc *mesh, fts_level **out) {
                 lv->ref.interface_block(lv->h[a][c], lv->h[a][c + 1], lv->gamma_hat,
                                         &lv->host_iface[a][(size_t)c * nn]);
         }
-        total += lv->host_cellop[a].size() + lv->host_iface[a].size() + lv->h[a].size();
+        total += lv->host_cellop[a].size() + lv->host_iface[a].size() + 2 * lv->h[a].size();
     }
     total += nn + 2 * nn + nn + 2 * lv->n1;
     if (hipMalloc(&lv->d_tab, total * sizeof(double)) != hipSuccess) {
@@ -388,6 +388,9 @@ fts_status fts_level_create(const fts_mesh_desc *mesh, fts_level **out) {
         lv->view.cellop[a] = put(lv->host_cellop[a]);
         lv->view.iface[a] = put(lv->host_iface[a]);
         lv->view.h[a] = put(lv->h[a]);
+        std::vector<double> ih(lv->h[a].size());
+        for (size_t c = 0; c < ih.size(); ++c) ih[c] = 1.0 / lv->h[a][c];
+        lv->view.ih[a] = put(ih);
         lv->view.m[a] = lv->m[a];
     }
     lv->view.Mhat = put(lv->ref.Mhat);
@@ -621,7 +624,9 @@ fts_status setup_eigs_internal(const fts_level *lv, fts_patch_kind kind, bool st
         int64_t nsub = 1;
         for (int a = 0; a < lv->dim; ++a) nsub *= eg->count[a];
         const size_t bytes = (size_t)nsub * (1u << lv->dim) * (lv->ndofs / lv->ncells) * sizeof(double);
-        if (hipMalloc(&eg->d_stage, std::max<size_t>(bytes, 8)) != hipSuccess) {
+        if (hipMalloc(&eg->d_stage, std::max<size_t>(bytes, 8)) != hipSuccess ||
+            hipMalloc(&eg->d_stage_scale, (size_t)std::max<int64_t>(nsub, 1) * sizeof(double)) != hipSuccess) {
+            if (eg->d_stage) hipFree(eg->d_stage);
             hipFree(eg->d_tab);
             hipFree(eg->d_tab32);
             if (eg->d_mfma) hipFree(eg->d_mfma);
@@ -656,6 +661,7 @@ fts_status fts_eigs_destroy(fts_eigs *eigs) {
     if (eigs->d_tab) hipFree(eigs->d_tab);
     if (eigs->d_tab32) hipFree(eigs->d_tab32);
     if (eigs->d_stage) hipFree(eigs->d_stage);
+    if (eigs->d_stage_scale) hipFree(eigs->d_stage_scale);
     if (eigs->d_mfma) hipFree(eigs->d_mfma);
     delete eigs;
     return FTS_OK;
