@@ -176,6 +176,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-mesh batched sweep")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + steps of the V-cycle only (for rocprofv3)")
+    ap.add_argument("--profile-mixed", choices=["f64", "f32", "f16", "bf16"],
+                    help="run warmup + steps V-cycles of the 48^3 Q7 CG preconditioner at this contraction "
+                         "precision only (for rocprofv3)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB FP64 buffer on the device --steps times (reference kernel of known "
                          "traffic for the rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -196,6 +199,25 @@ def main():
         print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "copies": args.steps}))
         return
     import paper_1910_11239_amd as fts
+
+    if args.profile_mixed:
+        c3 = CONFIGS["mixed_3d_q7"]
+        nl3 = c3["nlevels"]
+        h3 = fts.Hierarchy(3, c3["k"], uniform_widths(3, c3["m"]), nl3, "vertex", [0.0] + [c3["omega"]] * (nl3 - 1),
+                           c3["gamma_hat"], c3["m_pre"], c3["m_post"])
+        b3 = torch.as_tensor(random_vector(h3.ndofs, c3["seed_b"])).cuda()
+        x3 = torch.zeros_like(b3)
+        for _ in range(args.warmup):
+            x3.zero_()
+            h3.vcycle(b3, x3, prec=args.profile_mixed)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        for _ in range(args.steps):
+            x3.zero_()
+            h3.vcycle(b3, x3, prec=args.profile_mixed)
+        torch.cuda.synchronize()
+        print(json.dumps({"prec": args.profile_mixed, "ms_per_vcycle": (time.perf_counter() - t3) / args.steps * 1e3}))
+        return
 
     cfg = CONFIGS["avs_3d_q4"]
     dim, k, m, nl = cfg["dim"], cfg["k"], cfg["m"], cfg["nlevels"]

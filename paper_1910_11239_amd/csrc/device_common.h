@@ -146,15 +146,20 @@ __device__ __forceinline__ void matvec_regs(const T *in, T *out, P Mat) {
     }
 }
 
-template <int D, int N, typename T, typename P>
-__device__ __forceinline__ void contract_line(T *Tq, int a, int l, P Mat) {
-    const int base = line_base<D, N>(a, l), st = line_stride<N>(a);
+// Line of N values at Tq[base + i st] <- Mat * line.
+template <int N, typename T, typename P>
+__device__ __forceinline__ void contract_at(T *Tq, int base, int st, P Mat) {
     T in[N], out[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) in[i] = Tq[base + i * st];
     matvec_regs<N>(in, out, Mat);
 #pragma unroll
     for (int i = 0; i < N; ++i) Tq[base + i * st] = out[i];
+}
+
+template <int D, int N, typename T, typename P>
+__device__ __forceinline__ void contract_line(T *Tq, int a, int l, P Mat) {
+    contract_at<N>(Tq, line_base<D, N>(a, l), line_stride<N>(a), Mat);
 }
 
 // 1/d from the hardware reciprocal refined by Newton steps, each of which
@@ -173,10 +178,9 @@ __device__ __forceinline__ float recip(float d) {
 // Last axis: forward transform, eigenvalue scaling and backward transform of
 // the same line, kept in registers.  lam_rest = lambda of the other axes at
 // this line's fixed mode indices.
-template <int D, int N, typename T, typename P, typename Q>
-__device__ __forceinline__ void last_axis_solve(T *Tq, int l, P ST, P S, Q lam_last, T lam_rest, T omega) {
-    constexpr int a = D - 1;
-    const int base = line_base<D, N>(a, l), st = line_stride<N>(a);
+template <int N, typename T, typename P, typename Q>
+__device__ __forceinline__ void last_axis_solve_at(T *Tq, int base, int st, P ST, P S, Q lam_last, T lam_rest,
+                                                   T omega) {
     T in[N], mid[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) in[i] = Tq[base + i * st];
@@ -186,6 +190,12 @@ __device__ __forceinline__ void last_axis_solve(T *Tq, int l, P ST, P S, Q lam_l
     matvec_regs<N>(mid, in, S);
 #pragma unroll
     for (int i = 0; i < N; ++i) Tq[base + i * st] = in[i];
+}
+
+template <int D, int N, typename T, typename P, typename Q>
+__device__ __forceinline__ void last_axis_solve(T *Tq, int l, P ST, P S, Q lam_last, T lam_rest, T omega) {
+    constexpr int a = D - 1;
+    last_axis_solve_at<N>(Tq, line_base<D, N>(a, l), line_stride<N>(a), ST, S, lam_last, lam_rest, omega);
 }
 
 // ---------------------------------------------------------------------------

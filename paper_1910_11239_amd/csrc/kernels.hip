@@ -190,6 +190,7 @@ __device__ __forceinline__ void schwarz_lines3(const LevelView &g, const EigView
     if (act) contract_line<3, N, T>(Ts, 1, l, uniform_table(EigTab<T>::ST(e, 1) + (size_t)pos[1] * nn));
     __syncthreads();
     if (act) {
+        // the z-line l has mode indices (l % N, l / N) along x and y
         const T lr = (T)uniform_table(EigTab<T>::L(e, 0) + (size_t)pos[0] * N)[a1] +
                      (T)uniform_table(EigTab<T>::L(e, 1) + (size_t)pos[1] * N)[a2];
         last_axis_solve<3, N, T>(Ts, l, uniform_table(EigTab<T>::ST(e, 2) + (size_t)pos[2] * nn),
@@ -224,8 +225,9 @@ __global__ void __launch_bounds__((SwCfg<D, N1, KIND>::THREADS))
 k_schwarz(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r, double *__restrict__ x,
           T *__restrict__ W, double omega) {
     using C = SwCfg<D, N1, KIND>;
+    constexpr bool LINES3 = D == 3 && C::PPB == 1;
     __shared__ T Ts[C::PPB * C::NT];
-    if constexpr (D == 3 && C::PPB == 1) schwarz_lines3<N1, KIND, T, STAGE>(g, e, sg, r, x, W, omega, Ts);
+    if constexpr (LINES3) schwarz_lines3<N1, KIND, T, STAGE>(g, e, sg, r, x, W, omega, Ts);
     else schwarz_generic<D, N1, KIND, T, STAGE>(g, e, sg, r, x, W, omega, Ts);
 }
 
@@ -234,29 +236,69 @@ k_schwarz(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r, doub
 // cell's position inside the patch: deterministic, no write conflicts.  The
 // staged values are FP64 or FP32 (the contraction type); SCALED: each patch's
 // FP32 values carry one FP64 factor, multiplied in here.
-template <int D, int N1, typename WT, bool SCALED>
+template <typename WT, int V>
+struct VecOf;
+template <> struct VecOf<double, 1> { typedef double type; };
+template <> struct VecOf<double, 2> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct VecOf<double, 4> { typedef double type __attribute__((ext_vector_type(4))); };
+template <> struct VecOf<float, 1> { typedef float type; };
+template <> struct VecOf<float, 2> { typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct VecOf<float, 4> { typedef float type __attribute__((ext_vector_type(4))); };
+
+template <int D, int N1>
+struct GatherCfg {
+    static constexpr int NC1 = ipow(N1, D);
+    // consecutive DoFs of one cell per thread (vector loads stay aligned)
+    static constexpr int V = NC1 % 4 == 0 ? 4 : (NC1 % 2 == 0 ? 2 : 1);
+};
+
+template <int D, int N1, typename WT, bool SCALED, int V>
 __global__ void __launch_bounds__(256) k_patch_gather(LevelView g, const WT *__restrict__ W,
                                                       const double *__restrict__ Wsc, double *__restrict__ x) {
     constexpr int NC1 = ipow(N1, D), NSC = 1 << D;
-    const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    static_assert(NC1 % V == 0, "a thread's DoFs must lie in one cell");
+    using WV = typename VecOf<WT, V>::type;
+    using XV = typename VecOf<double, V>::type;
+    const int64_t gid = ((int64_t)blockIdx.x * 256 + threadIdx.x) * V;  // first DoF of this thread
     if (gid >= g.ncells * NC1) return;
-    const int64_t cell = gid / NC1;
-    const int i = (int)(gid % NC1);
-    int c[3];
-    cell_coords(cell, g.m, c);
+    const int cell = (int)(gid / NC1);
+    const int i = (int)(gid - (int64_t)cell * NC1);
+    const int r0 = cell / g.m[0];
+    const int c0 = cell - r0 * g.m[0], c1 = D == 3 ? r0 % g.m[1] : r0, c2 = D == 3 ? r0 / g.m[1] : 0;
     const int cnt0 = g.m[0] - 1, cnt1 = g.m[1] - 1;
-    double acc = 0.0;
+    XV acc = (XV)0.0;
 #pragma unroll
     for (int o = 0; o < NSC; ++o) {
-        const int a0 = c[0] - (o & 1), a1 = c[1] - ((o >> 1) & 1), a2 = D == 3 ? c[2] - ((o >> 2) & 1) : 0;
+        const int a0 = c0 - (o & 1), a1 = c1 - ((o >> 1) & 1), a2 = D == 3 ? c2 - ((o >> 2) & 1) : 0;
         const bool in = a0 >= 0 && a0 < cnt0 && a1 >= 0 && a1 < cnt1 && (D == 2 || (a2 >= 0 && a2 < g.m[2] - 1));
         if (in) {
             const int64_t sidx = a0 + (int64_t)cnt0 * (a1 + (int64_t)cnt1 * a2);
-            const double w = (double)W[sidx * (NSC * NC1) + o * NC1 + i];
-            acc += SCALED ? Wsc[sidx] * w : w;
+            const WV w = *(const WV *)(W + sidx * (NSC * NC1) + o * NC1 + i);
+            XV wd;
+            if constexpr (V == 1) wd = (double)w;
+            else wd = __builtin_convertvector(w, XV);
+            if constexpr (SCALED) acc += Wsc[sidx] * wd;
+            else acc += wd;
         }
     }
-    x[gid] += acc;
+    XV *xp = (XV *)(x + gid);
+    *xp += acc;
+}
+
+// Vector width V when x is aligned for it (a caller may pass a view of a
+// larger vector), else one DoF per thread.
+template <int D, int N1, typename WT, bool SCALED>
+static void launch_gather(const fts_level *lv, const WT *W, const double *Wsc, double *x, hipStream_t st) {
+    constexpr int V = GatherCfg<D, N1>::V;
+    const int64_t n = lv->ndofs;
+    if (reinterpret_cast<uintptr_t>(x) % (V * sizeof(double)) == 0) {
+        const int64_t nt = n / V;
+        k_patch_gather<D, N1, WT, SCALED, V><<<dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st>>>(lv->view, W,
+                                                                                                       Wsc, x);
+    } else {
+        k_patch_gather<D, N1, WT, SCALED, 1><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(lv->view, W,
+                                                                                                      Wsc, x);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -365,15 +407,29 @@ k_schwarz_mfma(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r,
     if (N < 16)
         for (int p = t; p < 16 * kPz; p += 256) Ts[p] = 0.f;
     __syncthreads();
+    // thread t < N^2 owns the patch line along x with (a1, a2) = (t % N, t / N):
+    // NO runs of k+1 contiguous residual values, all loads issued together
+    constexpr int NO = KIND ? 2 : 1;
+    const bool own = t < N * N;
+    const int a1 = t % N, a2 = t / N;
+    const int o1 = a1 / N1, i1 = a1 % N1, o2 = a2 / N1, i2 = a2 % N1;
+    const int64_t cell0 = pos[0] + (pos[1] + o1) * cs1 + (pos[2] + o2) * cs2;
+    const int iofs = i1 * N1 + i2 * N1 * N1;
+    const int lbase = a1 * kPy + a2 * kPz;
     float amax = 0.f;
-    for (int p = t; p < NSC * NC1; p += 256) {
-        const int sc = p / NC1, i = p % NC1;
-        const int o0 = sc & 1, o1 = (sc >> 1) & 1, o2 = (sc >> 2) & 1;
-        const int64_t cell = (pos[0] + o0) + (pos[1] + o1) * cs1 + (pos[2] + o2) * cs2;
-        const int i0 = i % N1, i1 = (i / N1) % N1, i2 = i / (N1 * N1);
-        const float v = (float)r[cell * NC1 + i];
-        Ts[(o0 * N1 + i0) + (o1 * N1 + i1) * kPy + (o2 * N1 + i2) * kPz] = v;
-        amax = fmaxf(amax, fabsf(v));
+    if (own) {
+        const double *src = r + cell0 * NC1 + iofs;
+        double rv[N];
+#pragma unroll
+        for (int o0 = 0; o0 < NO; ++o0)
+#pragma unroll
+            for (int i0 = 0; i0 < N1; ++i0) rv[o0 * N1 + i0] = src[o0 * NC1 + i0];
+#pragma unroll
+        for (int a0 = 0; a0 < N; ++a0) {
+            const float v = (float)rv[a0];
+            Ts[lbase + a0] = v;
+            amax = fmaxf(amax, fabsf(v));
+        }
     }
     for (int off = 32; off > 0; off >>= 1) amax = fmaxf(amax, __shfl_xor(amax, off, 64));
     if (lane == 0) wmax[wv] = amax;
@@ -448,18 +504,22 @@ k_schwarz_mfma(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r,
     const double lmin = (double)e.lmin[0][pos[0]] + e.lmin[1][pos[1]] + e.lmin[2][pos[2]];
     const double F = (double)rmax * omega * (sx * sy * sz) * (sx * sy * sz) / lmin;
     if (STAGE && t == 0) Wsc[s] = F;
-    for (int p = t; p < NSC * NC1; p += 256) {
-        const int sc = p / NC1, i = p % NC1;
-        const int o0 = sc & 1, o1 = (sc >> 1) & 1, o2 = (sc >> 2) & 1;
-        const int i0 = i % N1, i1 = (i / N1) % N1, i2 = i / (N1 * N1);
-        const float c = Ts[(o0 * N1 + i0) + (o1 * N1 + i1) * kPy + (o2 * N1 + i2) * kPz];
+    if (own) {
+        float c[N];
+#pragma unroll
+        for (int a0 = 0; a0 < N; ++a0) c[a0] = Ts[lbase + a0];
         if constexpr (STAGE) {
-            W[s * (NSC * NC1) + p] = c;  // F applied by the gather
+            float *dst = W + s * (NSC * NC1) + (2 * o1 + 4 * o2) * NC1 + iofs;  // F applied by the gather
+#pragma unroll
+            for (int o0 = 0; o0 < NO; ++o0)
+#pragma unroll
+                for (int i0 = 0; i0 < N1; ++i0) dst[o0 * NC1 + i0] = c[o0 * N1 + i0];
         } else {
-            const double v = F * (double)c;
-            const int64_t cell = (pos[0] + o0) + (pos[1] + o1) * cs1 + (pos[2] + o2) * cs2;
-            const int64_t gi = cell * NC1 + i;
-            x[gi] = x[gi] + v;
+            double *dst = x + cell0 * NC1 + iofs;
+#pragma unroll
+            for (int o0 = 0; o0 < NO; ++o0)
+#pragma unroll
+                for (int i0 = 0; i0 < N1; ++i0) dst[o0 * NC1 + i0] += F * (double)c[o0 * N1 + i0];
         }
     }
 }
@@ -670,9 +730,7 @@ struct RunSchwarz {
             if (s != FTS_OK) return s;
         }
         if (staged) {
-            const int64_t n = lv->ndofs;
-            k_patch_gather<D, N1, T, false><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(
-                lv->view, reinterpret_cast<const T *>(eg->d_stage), nullptr, x);
+            launch_gather<D, N1, T, false>(lv, reinterpret_cast<const T *>(eg->d_stage), nullptr, x, st);
             return check_launch("k_patch_gather");
         }
         return FTS_OK;
@@ -707,9 +765,8 @@ struct RunSchwarz {
                 if (s != FTS_OK) return s;
             }
             if (staged) {
-                const int64_t n = lv->ndofs;
-                k_patch_gather<D, N1, float, true><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(
-                    lv->view, reinterpret_cast<const float *>(eg->d_stage), eg->d_stage_scale, x);
+                launch_gather<D, N1, float, true>(lv, reinterpret_cast<const float *>(eg->d_stage),
+                                                  eg->d_stage_scale, x, st);
                 return check_launch("k_patch_gather");
             }
             return FTS_OK;
