@@ -66,6 +66,18 @@ def cell_red_black(mesh):
     return [sum(c) % 2 for c in mesh.cells()]
 
 
+def vertex_patch_mult_colors(mesh):
+    """2^(d+1) colors of the multiplicative vertex-patch smoother (Sec. 2.3:
+    parqueting combined with red-black).  Reading: the parquet color of
+    eq. (vertex_patch_colors) in the low d bits, and in bit d the red-black
+    parity of the patch inside its parquet sub-lattice,
+    sum_t floor((v_t - 1) / 2) mod 2.  Two patches of one color then share no
+    cell and no face, so their local problems do not couple through A."""
+    d = mesh.dim
+    return [sum(((v[t] - 1) % 2) << t for t in range(d)) + ((sum((v[t] - 1) // 2 for t in range(d)) % 2) << d)
+            for v in interior_vertices(mesh)]
+
+
 class ExactLocalSolvers:
     """Dense LU of every A_j = R_j A R_j^T.  Factors are shared between
     subdomains whose local matrices are bit-identical (switch off with cache=False)."""

@@ -5,7 +5,7 @@ import scipy.linalg as sla
 
 from oracle.mesh import Mesh, uniform_mesh
 from oracle import sipg, onedim, schwarz
-from synthetic import loguniform_widths
+from synthetic import loguniform_widths, random_vector
 
 
 def _mesh(d, k, ms, seed, gamma_hat=1.0):
@@ -165,3 +165,46 @@ def test_multiplicative_one_color_per_cell_is_sequential_gauss_seidel():
         R[np.arange(len(idx)), idx] = 1
         E = (np.eye(mesh.ndofs) - R.T @ np.linalg.solve(R @ Ad @ R.T, R @ Ad)) @ E
     assert np.abs((out - xs) - E @ (x - xs)).max() < 1e-11
+
+
+@pytest.mark.parametrize("d,k,ms", [(2, 2, (5, 4)), (3, 1, (4, 5, 3))])
+def test_mult_vertex_colors_decouple(d, k, ms):
+    """2^(d+1) colors: two patches of one color share no DoF and A couples none
+    of their DoFs (brute force on the assembled matrix)."""
+    rng = np.random.default_rng(5)
+    m = Mesh(d, k, loguniform_widths(rng, d, ms, 0.25, 4.0))
+    A = sipg.assemble(m).tocsr()
+    subs = schwarz.vertex_patch_subdomains(m)
+    cols = schwarz.vertex_patch_mult_colors(m)
+    assert set(cols) == set(range(2 ** (d + 1)))
+    for c in range(2 ** (d + 1)):
+        js = [j for j, cc in enumerate(cols) if cc == c]
+        for a in js:
+            for b in js:
+                if a < b:
+                    assert not set(subs[a]) & set(subs[b])
+                    assert abs(A[subs[a]][:, subs[b]]).max() == 0.0
+
+
+@pytest.mark.parametrize("kind,d,k,ms", [("cell", 2, 3, (4, 3)), ("vertex", 2, 2, (4, 5)), ("vertex", 3, 1, (3, 4, 3))])
+def test_colored_multiplicative_equals_sequential(kind, d, k, ms):
+    """Within a color the local problems do not couple (eq. coloredschwarz), so
+    Alg. multsmoother with one residual per color equals the fully sequential
+    product over single subdomains in the same order."""
+    rng = np.random.default_rng(6)
+    m = Mesh(d, k, loguniform_widths(rng, d, ms, 0.25, 4.0))
+    A = sipg.assemble(m).tocsr()
+    if kind == "cell":
+        subs, cols = schwarz.cell_subdomains(m), schwarz.cell_red_black(m)
+    else:
+        subs, cols = schwarz.vertex_patch_subdomains(m), schwarz.vertex_patch_mult_colors(m)
+    sol = schwarz.ExactLocalSolvers(A, subs)
+    b = random_vector(m.ndofs, 0)
+    x0 = random_vector(m.ndofs, 1)
+    omega = 0.8
+    xm = schwarz.multiplicative_smooth(A, sol, x0, b, omega, cols)
+    xs = x0.copy()
+    for j in schwarz.colored_order(cols):
+        r = b - A @ xs
+        xs[subs[j]] += omega * sol.local_solve(j, r[subs[j]])
+    assert np.linalg.norm(xm - xs) <= 1e-12 * np.linalg.norm(xs)
