@@ -161,6 +161,20 @@ fts_status fts_schwarz_smooth(const fts_level *level, const fts_eigs *eigs, doub
 fts_status fts_schwarz_apply(const fts_level *level, const fts_eigs *eigs, double omega,
                              fts_prec prec, const double *r, double *x, void *stream);
 
+/* Multiplicative Schwarz smoother (Alg. multsmoother, eq. coloredschwarz):
+ * nsweeps times, for each color c = 0..C-1 in turn: r = b - A x, then
+ * x += omega sum_{j in color c} R_j^T A_j^-1 R_j r.  Colors (Sec. 2.3): cells
+ * red-black (C = 2); vertex patches the parquet coloring combined with
+ * red-black, C = 2^(d+1): color bits t < d are (v_t - 1) mod 2 of the
+ * patch's interior vertex v, bit d is sum_t floor((v_t - 1) / 2) mod 2.  Two
+ * subdomains of one color share no DoF and their local problems do not
+ * couple through A, so each color is one parallel launch updating x in
+ * place.  ws: fts_smooth_ws_bytes(level) bytes.  prec as for
+ * fts_schwarz_smooth. */
+fts_status fts_schwarz_smooth_mult(const fts_level *level, const fts_eigs *eigs, double omega, fts_prec prec,
+                                   const double *b, double *x, int32_t nsweeps, void *ws, size_t ws_bytes,
+                                   void *stream);
+
 /* ---- a10: transfers and V-cycle ------------------------------------------ */
 
 /* Transfers between a level and its parent (each parent cell = 2^d children,
@@ -217,6 +231,32 @@ size_t fts_pcg_ws_bytes(const fts_hierarchy *hier);
 fts_status fts_pcg(fts_hierarchy *hier, fts_prec prec, const double *b, double *x, double rtol,
                    int32_t maxit, void *ws, size_t ws_bytes, int32_t *iters, double *relres,
                    double *history, void *stream);
+
+/* Smoother of the V-cycle on every level > 0: FTS_SMOOTHER_ADDITIVE (default,
+ * Alg. addsmoother) or FTS_SMOOTHER_MULTIPLICATIVE (Alg. multsmoother with the
+ * colors of fts_schwarz_smooth_mult; pre- and post-smoothing run the colors
+ * in the same order, so the V-cycle is not symmetric: use fts_gmres). */
+#define FTS_SMOOTHER_ADDITIVE 0
+#define FTS_SMOOTHER_MULTIPLICATIVE 1
+fts_status fts_hierarchy_set_smoother(fts_hierarchy *hier, int32_t smoother);
+
+/* Workspace bytes of fts_gmres: 2 restart + 2 finest-level vectors plus
+ * reduction partials. */
+size_t fts_gmres_ws_bytes(const fts_hierarchy *hier, int32_t restart);
+
+/* Restarted GMRES on the finest level, right-preconditioned by one V-cycle
+ * z = MG_L(0, v) (Sec. 2.4 uses GMRES with the multiplicative smoothers), in
+ * the flexible form that keeps the preconditioned directions z_j (so
+ * reduced-precision contractions are tolerated): Arnoldi with modified
+ * Gram-Schmidt, Givens rotations on the host, x += Z y at the end of each
+ * cycle of `restart` steps.  FP64 vectors and deterministic reductions; every
+ * inner product is read back (the only synchronisations).  x: initial guess
+ * on entry, iterate on exit; stops when the relative residual (least-squares
+ * estimate inside a cycle, true residual at its end) is <= rtol or after
+ * maxit inner steps.  history: NULL or maxit+1 doubles. */
+fts_status fts_gmres(fts_hierarchy *hier, fts_prec prec, const double *b, double *x, double rtol, int32_t restart,
+                     int32_t maxit, void *ws, size_t ws_bytes, int32_t *iters, double *relres, double *history,
+                     void *stream);
 
 /* Replaces the per-level damping (host array of nlevels, index 0 unused). */
 fts_status fts_hierarchy_set_omega(fts_hierarchy *hier, const double *omega_per_level);

@@ -24,7 +24,8 @@ import scipy.sparse as sp
 from .basis import gll_nodes, lagrange_values
 from .mesh import coarsen
 from .sipg import assemble, tensor
-from .schwarz import ExactLocalSolvers, cell_subdomains, vertex_patch_subdomains, additive_smooth
+from .schwarz import (ExactLocalSolvers, cell_subdomains, vertex_patch_subdomains, additive_smooth,
+                      multiplicative_smooth, cell_red_black, vertex_patch_mult_colors)
 
 
 def prolongation(mesh_c, mesh_f):
@@ -53,10 +54,12 @@ class Hierarchy:
     """Levels 0..L built by coarsening ``fine`` nlevels-1 times.
 
     omegas[l] and gamma_hats[l] (l = 0..L) are per-level relaxation and
-    penalty factors (omegas[0] unused)."""
+    penalty factors (omegas[0] unused).  smoother: "additive" (Alg. addsmoother)
+    or "multiplicative" (Alg. multsmoother with red-black cells or the 2^(d+1)
+    vertex-patch colors, pre- and post-smoothing in the same color order)."""
 
     def __init__(self, fine, nlevels, kind="vertex", omegas=0.5, m_pre=1, m_post=1,
-                 gamma_hats=None, cache=True):
+                 gamma_hats=None, cache=True, smoother="additive"):
         meshes = [fine]
         for _ in range(nlevels - 1):
             meshes.insert(0, coarsen(meshes[0]))
@@ -74,8 +77,13 @@ class Hierarchy:
         self.solvers = [None] + [ExactLocalSolvers(self.A[l], subs(meshes[l]), cache)
                                  for l in range(1, L + 1)]
         self.coarse_lu = sla.lu_factor(self.A[0].toarray())
+        self.smoother = smoother
+        col = cell_red_black if kind == "cell" else vertex_patch_mult_colors
+        self.colors = [None] + [col(meshes[l]) for l in range(1, L + 1)]
 
     def smooth(self, l, x, b):
+        if self.smoother == "multiplicative":
+            return multiplicative_smooth(self.A[l], self.solvers[l], x, b, self.omegas[l], self.colors[l])
         return additive_smooth(self.A[l], self.solvers[l], x, b, self.omegas[l])
 
     def vcycle(self, x, b, l=None):

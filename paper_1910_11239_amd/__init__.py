@@ -46,6 +46,7 @@ _SIGS = {
     "fts_residual": (_I32, [_VP, _VP, _VP, _VP, _VP]),
     "fts_smooth_ws_bytes": (_SZ, [_VP]),
     "fts_schwarz_smooth": (_I32, [_VP, _VP, _D, _I32, _VP, _VP, _I32, _VP, _SZ, _VP]),
+    "fts_schwarz_smooth_mult": (_I32, [_VP, _VP, _D, _I32, _VP, _VP, _I32, _VP, _SZ, _VP]),
     "fts_schwarz_apply": (_I32, [_VP, _VP, _D, _I32, _VP, _VP, _VP]),
     "fts_restrict": (_I32, [_VP, _VP, _VP, _VP, _VP]),
     "fts_prolongate_add": (_I32, [_VP, _VP, _VP, _VP, _VP]),
@@ -57,6 +58,9 @@ _SIGS = {
     "fts_coarse_solve": (_I32, [_VP, _VP, _VP, _VP]),
     "fts_pcg_ws_bytes": (_SZ, [_VP]),
     "fts_hierarchy_set_omega": (_I32, [_VP, _VP]),
+    "fts_hierarchy_set_smoother": (_I32, [_VP, _I32]),
+    "fts_gmres_ws_bytes": (_SZ, [_VP, _I32]),
+    "fts_gmres": (_I32, [_VP, _I32, _VP, _VP, _D, _I32, _I32, _VP, _SZ, _VP, _VP, _VP, _VP]),
     "fts_hierarchy_enable_adjoint": (_I32, [_VP]),
     "fts_vcycle_adjoint": (_I32, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "fts_batch_create": (_I32, [_VP, _I32, _VP]),
@@ -208,6 +212,17 @@ def schwarz_smooth(level, eigs, omega, b, x, nsweeps=1, prec="f64", ws=None):
     return x
 
 
+def schwarz_smooth_mult(level, eigs, omega, b, x, nsweeps=1, prec="f64", ws=None):
+    """Multiplicative smoother (Alg. multsmoother): a residual before each color."""
+    import torch
+    if ws is None:
+        ws = torch.empty(level.ndofs, dtype=torch.float64, device=x.device)
+    _check(lib().fts_schwarz_smooth_mult(level._h, eigs._h, float(omega), PREC[prec], _ptr(b, level.ndofs, "b"),
+                                         _ptr(x, level.ndofs, "x"), int(nsweeps), _ptr(ws, None, "ws"),
+                                         ws.numel() * 8, _stream()), "fts_schwarz_smooth_mult")
+    return x
+
+
 def schwarz_apply(level, eigs, omega, r, x, prec="f64"):
     _check(lib().fts_schwarz_apply(level._h, eigs._h, float(omega), PREC[prec], _ptr(r, level.ndofs, "r"),
                                    _ptr(x, level.ndofs, "x"), _stream()), "fts_schwarz_apply")
@@ -270,6 +285,27 @@ class Hierarchy:
         _check(lib().fts_pcg(self._h, PREC[prec], _ptr(b, self.ndofs, "b"), _ptr(x, self.ndofs, "x"),
                              float(rtol), int(maxit), _ptr(ws, None, "ws"), ws.numel() * 8, ctypes.byref(it),
                              ctypes.byref(rel), hist.ctypes.data, _stream()), "fts_pcg")
+        return it.value, rel.value, hist[:it.value + 1]
+
+    def set_smoother(self, smoother):
+        """'additive' (default) or 'multiplicative' on every smoothed level."""
+        _check(lib().fts_hierarchy_set_smoother(self._h, {"additive": 0, "multiplicative": 1}[smoother]),
+               "fts_hierarchy_set_smoother")
+
+    def gmres(self, b, x, rtol=1e-10, restart=30, maxit=200, prec="f64", ws=None):
+        """Flexible restarted GMRES with one V-cycle as right preconditioner; x:
+        initial guess, updated.  Returns (iterations, final relative residual,
+        history of relative residuals)."""
+        import torch
+        nbytes = int(lib().fts_gmres_ws_bytes(self._h, int(restart)))
+        if ws is None:
+            ws = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=x.device)
+        hist = np.zeros(maxit + 1)
+        it = ctypes.c_int32()
+        rel = ctypes.c_double()
+        _check(lib().fts_gmres(self._h, PREC[prec], _ptr(b, self.ndofs, "b"), _ptr(x, self.ndofs, "x"),
+                               float(rtol), int(restart), int(maxit), _ptr(ws, None, "ws"), ws.numel() * 8,
+                               ctypes.byref(it), ctypes.byref(rel), hist.ctypes.data, _stream()), "fts_gmres")
         return it.value, rel.value, hist[:it.value + 1]
 
     def set_omega(self, omegas):

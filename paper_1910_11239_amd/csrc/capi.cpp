@@ -15,6 +15,7 @@ struct fts_hierarchy {
     std::vector<fts_eigs *> eigs;     // eigs[0] = nullptr
     std::vector<double *> vb, vx, vr;  // per-level vectors (b, x for l < L; r for every l)
     CoarseLU *coarse = nullptr;  // direct solver of A_0 (coarse.hip)
+    int smoother = FTS_SMOOTHER_ADDITIVE;
     int64_t N0 = 0;
     double *host_scalars = nullptr;       // pinned readback buffer of the CG reductions
     // adjoint workspaces (fts_hierarchy_enable_adjoint)
@@ -62,6 +63,25 @@ fts_status fts_schwarz_smooth(const fts_level *level, const fts_eigs *eigs, doub
         st = launch_schwarz(level, eigs, omega, prec, r, x, S(stream));
         if (st != FTS_OK) return st;
     }
+    return FTS_OK;
+}
+
+fts_status fts_schwarz_smooth_mult(const fts_level *level, const fts_eigs *eigs, double omega, fts_prec prec,
+                                   const double *b, double *x, int32_t nsweeps, void *ws, size_t ws_bytes,
+                                   void *stream) {
+    if (!level || !eigs || !b || !x || !ws) return fail(FTS_E_INVAL, "fts_schwarz_smooth_mult: NULL argument");
+    if (eigs->level != level) return fail(FTS_E_INVAL, "fts_schwarz_smooth_mult: eigs belong to another level");
+    if (ws_bytes < fts_smooth_ws_bytes(level))
+        return fail(FTS_E_SIZE, "fts_schwarz_smooth_mult: workspace too small");
+    double *r = static_cast<double *>(ws);
+    const int nc = schwarz_mult_colors(eigs);
+    for (int it = 0; it < nsweeps; ++it)
+        for (int c = 0; c < nc; ++c) {
+            fts_status st = launch_operator(level, x, b, r, true, S(stream));
+            if (st != FTS_OK) return st;
+            st = launch_schwarz_color(level, eigs, omega, prec, r, x, c, S(stream));
+            if (st != FTS_OK) return st;
+        }
     return FTS_OK;
 }
 
@@ -210,25 +230,38 @@ fts_status fts_coarse_solve(fts_hierarchy *h, const double *b0, double *x0, void
     return coarse_solve(h->coarse, b0, x0, S(stream));
 }
 
-static fts_status vcycle_level(fts_hierarchy *h, int l, fts_prec prec, const double *b, double *x, hipStream_t s) {
-    if (l == 0) return coarse_solve(h->coarse, b, x, s);
+// One smoothing step on level l: Alg. addsmoother (one residual, all local
+// solves) or Alg. multsmoother (a residual before each color).
+static fts_status smooth_step(fts_hierarchy *h, int l, fts_prec prec, const double *b, double *x, hipStream_t s) {
     const fts_level *lv = h->levels[l];
     const fts_eigs *eg = h->eigs[l];
     double *r = h->vr[l];
     fts_status st = FTS_OK;
-    for (int i = 0; i < h->m_pre && st == FTS_OK; ++i) {
-        st = launch_operator(lv, x, b, r, true, s);
-        if (st == FTS_OK) st = launch_schwarz(lv, eg, h->omega[l], prec, r, x, s);
+    if (h->smoother == FTS_SMOOTHER_MULTIPLICATIVE) {
+        const int nc = schwarz_mult_colors(eg);
+        for (int c = 0; c < nc && st == FTS_OK; ++c) {
+            st = launch_operator(lv, x, b, r, true, s);
+            if (st == FTS_OK) st = launch_schwarz_color(lv, eg, h->omega[l], prec, r, x, c, s);
+        }
+        return st;
     }
+    st = launch_operator(lv, x, b, r, true, s);
+    if (st == FTS_OK) st = launch_schwarz(lv, eg, h->omega[l], prec, r, x, s);
+    return st;
+}
+
+static fts_status vcycle_level(fts_hierarchy *h, int l, fts_prec prec, const double *b, double *x, hipStream_t s) {
+    if (l == 0) return coarse_solve(h->coarse, b, x, s);
+    const fts_level *lv = h->levels[l];
+    double *r = h->vr[l];
+    fts_status st = FTS_OK;
+    for (int i = 0; i < h->m_pre && st == FTS_OK; ++i) st = smooth_step(h, l, prec, b, x, s);
     if (st == FTS_OK) st = launch_operator(lv, x, b, r, true, s);
     if (st == FTS_OK) st = launch_restrict(h->levels[l - 1], lv, r, h->vb[l - 1], s);
     if (st == FTS_OK && l - 1 > 0) st = launch_fill(h->vx[l - 1], h->levels[l - 1]->ndofs, 0.0, s);
     if (st == FTS_OK) st = vcycle_level(h, l - 1, prec, h->vb[l - 1], h->vx[l - 1], s);
     if (st == FTS_OK) st = launch_prolongate(h->levels[l - 1], lv, h->vx[l - 1], x, s);
-    for (int i = 0; i < h->m_post && st == FTS_OK; ++i) {
-        st = launch_operator(lv, x, b, r, true, s);
-        if (st == FTS_OK) st = launch_schwarz(lv, eg, h->omega[l], prec, r, x, s);
-    }
+    for (int i = 0; i < h->m_post && st == FTS_OK; ++i) st = smooth_step(h, l, prec, b, x, s);
     return st;
 }
 
@@ -302,8 +335,121 @@ fts_status fts_pcg(fts_hierarchy *h, fts_prec prec, const double *b, double *x, 
         }
     }
 #undef FTS_TRY
+
     if (iters) *iters = it;
     if (relres) *relres = rel;
+    return FTS_OK;
+}
+
+size_t fts_gmres_ws_bytes(const fts_hierarchy *h, int32_t restart) {
+    if (!h || restart < 1) return 0;
+    return (size_t)((2 * (int64_t)restart + 2) * h->levels.back()->ndofs + 2 * red_partials() + 2) * sizeof(double);
+}
+
+fts_status fts_gmres(fts_hierarchy *h, fts_prec prec, const double *b, double *x, double rtol, int32_t restart,
+                     int32_t maxit, void *ws, size_t ws_bytes, int32_t *iters, double *relres, double *history,
+                     void *stream) {
+    if (!h || !b || !x || !ws) return fail(FTS_E_INVAL, "fts_gmres: NULL argument");
+    if (restart < 1 || maxit < 0) return fail(FTS_E_INVAL, "fts_gmres: restart >= 1 and maxit >= 0 required");
+    if (ws_bytes < fts_gmres_ws_bytes(h, restart)) return fail(FTS_E_SIZE, "fts_gmres: workspace too small");
+    hipStream_t s = S(stream);
+    const int L = h->nlevels - 1;
+    const fts_level *lv = h->levels[L];
+    const int64_t N = lv->ndofs;
+    const int m = restart;
+    double *V = static_cast<double *>(ws);  // m + 1 vectors
+    double *Z = V + (int64_t)(m + 1) * N;   // m vectors
+    double *w = Z + (int64_t)m * N;
+    double *part = w + N, *dout = part + 2 * red_partials();
+    double v2[2];
+    fts_status st;
+#define GM_TRY(expr)                   \
+    do {                               \
+        st = (expr);                   \
+        if (st != FTS_OK) return st;   \
+    } while (0)
+    auto dot = [&](const double *a, const double *c, double *out) -> fts_status {
+        fts_status e = launch_dot2(a, c, nullptr, N, part, dout, s);
+        if (e != FTS_OK) return e;
+        e = readback(h, dout, s, v2);
+        *out = v2[0];
+        return e;
+    };
+    double bb, rr;
+    GM_TRY(dot(b, b, &bb));
+    const double nb = std::sqrt(bb) > 0.0 ? std::sqrt(bb) : 1.0;
+    GM_TRY(launch_operator(lv, x, b, V, true, s));  // r = b - A x in V_0
+    GM_TRY(dot(V, V, &rr));
+    double beta = std::sqrt(rr);
+    double rel = beta / nb;
+    if (history) history[0] = rel;
+    int it = 0;
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    auto Hij = [&](int i, int j) -> double & { return H[(size_t)i * m + j]; };
+    while (rel > rtol && it < maxit && beta > 0.0) {
+        GM_TRY(launch_scale(V, 1.0 / beta, N, s));  // v_1 = r / |r|
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int k = 0;
+        for (int j = 0; j < m; ++j) {
+            double *Vj = V + (int64_t)j * N, *Zj = Z + (int64_t)j * N;
+            GM_TRY(launch_fill(Zj, N, 0.0, s));
+            GM_TRY(vcycle_level(h, L, prec, Vj, Zj, s));  // z_j = MG(0, v_j)
+            GM_TRY(launch_operator(lv, Zj, nullptr, w, false, s));
+            for (int i = 0; i <= j; ++i) {  // modified Gram-Schmidt
+                double hij;
+                GM_TRY(dot(w, V + (int64_t)i * N, &hij));
+                Hij(i, j) = hij;
+                GM_TRY(launch_axpy(-hij, V + (int64_t)i * N, w, N, s));
+            }
+            double ww;
+            GM_TRY(dot(w, w, &ww));
+            const double hn = std::sqrt(ww);
+            // Givens rotations: triangularise column j, residual = |g[j+1]|
+            for (int i = 0; i < j; ++i) {
+                const double t0 = Hij(i, j), t1 = Hij(i + 1, j);
+                Hij(i, j) = cs[i] * t0 + sn[i] * t1;
+                Hij(i + 1, j) = -sn[i] * t0 + cs[i] * t1;
+            }
+            const double a = Hij(j, j), r2 = std::hypot(a, hn);
+            cs[j] = r2 > 0.0 ? a / r2 : 1.0;
+            sn[j] = r2 > 0.0 ? hn / r2 : 0.0;
+            Hij(j, j) = r2;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            k = j + 1;
+            ++it;
+            rel = std::fabs(g[j + 1]) / nb;
+            if (history) history[it] = rel;
+            if (rel <= rtol || it >= maxit || hn == 0.0) break;
+            double *Vn = V + (int64_t)(j + 1) * N;
+            GM_TRY(launch_fill(Vn, N, 0.0, s));
+            GM_TRY(launch_axpy(1.0 / hn, w, Vn, N, s));
+        }
+        for (int i = k - 1; i >= 0; --i) {  // R y = g
+            double t = g[i];
+            for (int c = i + 1; c < k; ++c) t -= Hij(i, c) * y[c];
+            y[i] = t / Hij(i, i);
+        }
+        for (int i = 0; i < k; ++i) GM_TRY(launch_axpy(y[i], Z + (int64_t)i * N, x, N, s));
+        GM_TRY(launch_operator(lv, x, b, V, true, s));
+        GM_TRY(dot(V, V, &rr));
+        beta = std::sqrt(rr);
+        rel = beta / nb;
+        if (history) history[it] = rel;
+    }
+#undef GM_TRY
+    if (iters) *iters = it;
+    if (relres) *relres = rel;
+    return FTS_OK;
+}
+
+fts_status fts_hierarchy_set_smoother(fts_hierarchy *h, int32_t smoother) {
+    if (!h) return fail(FTS_E_INVAL, "fts_hierarchy_set_smoother: NULL handle");
+    if (smoother != FTS_SMOOTHER_ADDITIVE && smoother != FTS_SMOOTHER_MULTIPLICATIVE)
+        return fail(FTS_E_INVAL, "fts_hierarchy_set_smoother: unknown smoother");
+    h->smoother = smoother;
     return FTS_OK;
 }
 
@@ -445,6 +591,8 @@ fts_status fts_vcycle_adjoint(fts_hierarchy *h, const double *b, const double *x
                               double *lambda_b, double *lambda_x, double *d_omega, double *d_penalty, void *stream) {
     if (!h || !b || !x_in || !lambda_out) return fail(FTS_E_INVAL, "fts_vcycle_adjoint: NULL argument");
     if (!h->adj) return fail(FTS_E_INVAL, "fts_vcycle_adjoint: call fts_hierarchy_enable_adjoint first");
+    if (h->smoother != FTS_SMOOTHER_ADDITIVE)
+        return fail(FTS_E_UNSUPPORTED, "fts_vcycle_adjoint: the adjoint is built for the additive smoother");
     if (h->kind != FTS_VERTEX_PATCH && h->kind != FTS_CELL) return fail(FTS_E_INVAL, "bad hierarchy");
     hipStream_t s = S(stream);
     const int L = h->nlevels - 1;

@@ -106,8 +106,19 @@ struct SubGrid {
     int cnt[3];    // subdomains per axis in this launch
     int first[3];  // position of the first subdomain per axis
     int step;      // 1 (cells) or 2 (one parquet color of vertex patches)
+    int parity;    // -1: every subdomain; 0 / 1: only those with j0 + j1 + j2 of this parity
+                   // (j = index inside this launch's grid; red-black colors)
     int64_t nsub;
 };
+
+// Is subdomain s (index within the launch) part of it under sg.parity?
+__device__ __forceinline__ bool sub_in_color(const SubGrid &sg, int64_t s) {
+    if (sg.parity < 0) return true;
+    const int j0 = (int)(s % sg.cnt[0]);
+    const int64_t rr = s / sg.cnt[0];
+    const int j1 = (int)(rr % sg.cnt[1]), j2 = (int)(rr / sg.cnt[1]);
+    return ((j0 + j1 + j2) & 1) == sg.parity;
+}
 
 template <typename T>
 struct EigTab;

@@ -147,6 +147,11 @@ fts_status launch_sum_acc(const double *x, int64_t n, double scale, double *part
 fts_status launch_axpy(double a, const double *x, double *y, int64_t n, hipStream_t stream);
 fts_status launch_schwarz(const fts_level *lv, const fts_eigs *eg, double omega, fts_prec prec,
                           const double *r, double *x, hipStream_t stream);
+// Colors of the multiplicative smoother: 2 (red-black cells) or 2^(d+1)
+// (vertex patches); one color's local solves added to x in place.
+int schwarz_mult_colors(const fts_eigs *eg);
+fts_status launch_schwarz_color(const fts_level *lv, const fts_eigs *eg, double omega, fts_prec prec,
+                                const double *r, double *x, int color, hipStream_t stream);
 fts_status launch_restrict(const fts_level *coarse, const fts_level *fine, const double *rf,
                            double *bc, hipStream_t stream);
 fts_status launch_prolongate(const fts_level *coarse, const fts_level *fine, const double *ec,
@@ -159,6 +164,8 @@ fts_status launch_dot2(const double *x, const double *y, const double *z, int64_
 fts_status launch_cg_update(double *x, double *r, const double *p, const double *q, double alpha, int64_t n,
                             hipStream_t stream);
 fts_status launch_xpby(double *p, const double *z, double beta, int64_t n, hipStream_t stream);
+// p *= a
+fts_status launch_scale(double *p, double a, int64_t n, hipStream_t stream);
 int red_partials();
 // cells per workgroup of the operator kernels (the batched residual's blocks)
 int operator_cells_per_block(int dim, int n1);

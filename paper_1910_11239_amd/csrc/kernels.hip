@@ -55,7 +55,7 @@ __device__ __forceinline__ void schwarz_generic(const LevelView &g, const EigVie
     for (int p = t; p < PPB * NSC * NC1; p += TH) {
         const int qq = p / (NSC * NC1), rem = p % (NSC * NC1), sc = rem / NC1, i = rem % NC1;
         const int64_t s = s0 + qq;
-        if (s >= sg.nsub) continue;
+        if (s >= sg.nsub || !sub_in_color(sg, s)) continue;
         int pos[3];
         position(s, pos);
         const int o0 = sc & 1, o1 = (sc >> 1) & 1, o2 = (sc >> 2) & 1;
@@ -66,7 +66,7 @@ __device__ __forceinline__ void schwarz_generic(const LevelView &g, const EigVie
     }
     __syncthreads();
     const int64_t s = s0 + q;
-    const bool act = (q < PPB) && (s < sg.nsub);
+    const bool act = (q < PPB) && (s < sg.nsub) && sub_in_color(sg, s);
     T *Tq = Ts + q * NT;
     const T om = (T)omega;
     // mode indices of this thread's line along the last axis (fixed coordinates of the other axes)
@@ -129,7 +129,7 @@ __device__ __forceinline__ void schwarz_generic(const LevelView &g, const EigVie
     for (int p = t; p < PPB * NSC * NC1; p += TH) {
         const int qq = p / (NSC * NC1), rem = p % (NSC * NC1), sc = rem / NC1, i = rem % NC1;
         const int64_t ss = s0 + qq;
-        if (ss >= sg.nsub) continue;
+        if (ss >= sg.nsub || !sub_in_color(sg, ss)) continue;
         int ps[3];
         position(ss, ps);
         const int o0 = sc & 1, o1 = (sc >> 1) & 1, o2 = (sc >> 2) & 1;
@@ -161,6 +161,7 @@ __device__ __forceinline__ void schwarz_lines3(const LevelView &g, const EigView
     constexpr int N = C::N, NC1 = C::NC1, NSC = C::NSC, LINES = C::LINES, NO = KIND ? 2 : 1;
     const int l = threadIdx.x;
     const int s = blockIdx.x;
+    if (!sub_in_color(sg, s)) return;  // uniform: the whole workgroup leaves before any barrier
     int pos[3];
     {
         const int j0 = s % sg.cnt[0], rr = s / sg.cnt[0];
@@ -393,6 +394,7 @@ k_schwarz_mfma(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r,
     __shared__ float wmax[4];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int64_t s = blockIdx.x;
+    if (!sub_in_color(sg, s)) return;  // uniform: the whole workgroup leaves before any barrier
     int pos[3];
     {
         const int j0 = (int)(s % sg.cnt[0]);
@@ -704,6 +706,7 @@ struct RunSchwarz {
         const int ncolor = (KIND && !staged) ? (1 << D) : 1;
         for (int color = 0; color < ncolor; ++color) {
             SubGrid sg{};
+            sg.parity = -1;
             sg.step = (KIND && !staged) ? 2 : 1;
             sg.nsub = 1;
             for (int a = 0; a < 3; ++a) {
@@ -745,6 +748,7 @@ struct RunSchwarz {
             const int ncolor = (KIND && !staged) ? 8 : 1;
             for (int color = 0; color < ncolor; ++color) {
                 SubGrid sg{};
+                sg.parity = -1;
                 sg.step = (KIND && !staged) ? 2 : 1;
                 sg.nsub = 1;
                 for (int a = 0; a < 3; ++a) {
@@ -772,6 +776,75 @@ struct RunSchwarz {
             return FTS_OK;
         }
     }
+    // One color of the multiplicative smoother (Alg. multsmoother, Sec. 2.3):
+    // red-black cells (color 0 / 1), or the 2^(d+1) vertex-patch colors with
+    // the parquet color in the low d bits and the red-black parity inside the
+    // parquet sub-lattice in bit d.  Subdomains of one color share no DoF (and
+    // their local problems do not couple), so x is updated in place.
+    template <int KIND>
+    static SubGrid color_grid(const fts_eigs *eg, int color) {
+        SubGrid sg{};
+        sg.step = KIND ? 2 : 1;
+        sg.nsub = 1;
+        for (int a = 0; a < 3; ++a) {
+            if (a >= D) {
+                sg.cnt[a] = 1;
+                sg.first[a] = 0;
+                continue;
+            }
+            sg.first[a] = KIND ? ((color >> a) & 1) : 0;
+            const int npos = eg->count[a];
+            sg.cnt[a] = npos > sg.first[a] ? (npos - sg.first[a] + sg.step - 1) / sg.step : 0;
+            sg.nsub *= sg.cnt[a];
+        }
+        sg.parity = KIND ? ((color >> D) & 1) : (color & 1);
+        return sg;
+    }
+    template <int KIND, typename T>
+    static fts_status go_color(const fts_level *lv, const fts_eigs *eg, double omega, const double *r, double *x,
+                               int color, hipStream_t st) {
+        using C = SwCfg<D, N1, KIND>;
+        const SubGrid sg = color_grid<KIND>(eg, color);
+        if (sg.nsub == 0) return FTS_OK;
+        const int64_t blocks = (sg.nsub + C::PPB - 1) / C::PPB;
+        if (blocks > INT_MAX) return fail(FTS_E_SIZE, "too many subdomains for one launch");
+        k_schwarz<D, N1, KIND, T, false><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(
+            lv->view, eg->view, sg, r, x, nullptr, omega);
+        return check_launch("k_schwarz (color)");
+    }
+    template <int KIND, int BF>
+    static fts_status go_color_mfma(const fts_level *lv, const fts_eigs *eg, double omega, const double *r,
+                                    double *x, int color, hipStream_t st) {
+        if constexpr (D != 3 || (KIND ? 2 * N1 : N1) > 16) {
+            return fail(FTS_E_UNSUPPORTED, "16-bit MFMA contractions need d = 3 and n <= 16");
+        } else {
+            const SubGrid sg = color_grid<KIND>(eg, color);
+            if (sg.nsub == 0) return FTS_OK;
+            if (sg.nsub > INT_MAX) return fail(FTS_E_SIZE, "too many subdomains for one launch");
+            k_schwarz_mfma<N1, KIND, BF, false><<<dim3((unsigned)sg.nsub), dim3(256), 0, st>>>(
+                lv->view, eg->view, sg, r, x, nullptr, nullptr, omega);
+            return check_launch("k_schwarz_mfma (color)");
+        }
+    }
+    static fts_status run_color(const fts_level *lv, const fts_eigs *eg, double omega, fts_prec prec,
+                                const double *r, double *x, int color, hipStream_t st) {
+        const bool cell = eg->kind == FTS_CELL;
+        if (prec == FTS_PREC_F16 || prec == FTS_PREC_BF16) {
+            if (!eg->d_mfma) return fail(FTS_E_UNSUPPORTED, "16-bit MFMA contractions need n <= 16");
+            if (prec == FTS_PREC_BF16)
+                return cell ? go_color_mfma<0, 1>(lv, eg, omega, r, x, color, st)
+                            : go_color_mfma<1, 1>(lv, eg, omega, r, x, color, st);
+            return cell ? go_color_mfma<0, 0>(lv, eg, omega, r, x, color, st)
+                        : go_color_mfma<1, 0>(lv, eg, omega, r, x, color, st);
+        }
+        if (prec == FTS_PREC_F64)
+            return cell ? go_color<0, double>(lv, eg, omega, r, x, color, st)
+                        : go_color<1, double>(lv, eg, omega, r, x, color, st);
+        if (prec == FTS_PREC_F32)
+            return cell ? go_color<0, float>(lv, eg, omega, r, x, color, st)
+                        : go_color<1, float>(lv, eg, omega, r, x, color, st);
+        return fail(FTS_E_UNSUPPORTED, "precision not built");
+    }
     static fts_status run(const fts_level *lv, const fts_eigs *eg, double omega, fts_prec prec, const double *r,
                           double *x, hipStream_t st) {
         if (prec == FTS_PREC_F16 || prec == FTS_PREC_BF16) {
@@ -792,6 +865,24 @@ struct RunSchwarz {
 fts_status launch_schwarz(const fts_level *lv, const fts_eigs *eg, double omega, fts_prec prec, const double *r,
                           double *x, hipStream_t stream) {
     return dispatch<RunSchwarz>(lv->dim, lv->n1, lv, eg, omega, prec, r, x, stream);
+}
+
+template <int D, int N1>
+struct RunSchwarzColor {
+    static fts_status run(const fts_level *lv, const fts_eigs *eg, double omega, fts_prec prec, const double *r,
+                          double *x, int color, hipStream_t st) {
+        return RunSchwarz<D, N1>::run_color(lv, eg, omega, prec, r, x, color, st);
+    }
+};
+
+int schwarz_mult_colors(const fts_eigs *eg) {
+    return eg->kind == FTS_CELL ? 2 : 2 << eg->level->dim;
+}
+
+fts_status launch_schwarz_color(const fts_level *lv, const fts_eigs *eg, double omega, fts_prec prec,
+                                const double *r, double *x, int color, hipStream_t stream) {
+    if (color < 0 || color >= schwarz_mult_colors(eg)) return fail(FTS_E_INVAL, "Schwarz color out of range");
+    return dispatch<RunSchwarzColor>(lv->dim, lv->n1, lv, eg, omega, prec, r, x, color, stream);
 }
 
 template <int D, int N1>
@@ -926,6 +1017,15 @@ fts_status launch_cg_update(double *x, double *r, const double *p, const double 
     return check_launch("k_cg_update");
 }
 
+__global__ void __launch_bounds__(256) k_scale(double *__restrict__ p, double a, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] *= a;
+}
+
+fts_status launch_scale(double *p, double a, int64_t n, hipStream_t st) {
+    k_scale<<<vec_grid(n), 256, 0, st>>>(p, a, n);
+    return check_launch("k_scale");
+}
+
 fts_status launch_xpby(double *p, const double *z, double beta, int64_t n, hipStream_t st) {
     k_xpby<<<vec_grid(n), 256, 0, st>>>(p, z, beta, n);
     return check_launch("k_xpby");
@@ -1035,6 +1135,7 @@ struct RunDgamma {
                          int64_t *npart, hipStream_t st) {
         using C = SwCfg<D, N1, KIND>;
         SubGrid sg{};
+        sg.parity = -1;
         sg.step = 1;
         sg.nsub = 1;
         for (int a = 0; a < 3; ++a) {

@@ -5,7 +5,7 @@ import scipy.linalg as sla
 
 from oracle.mesh import Mesh, uniform_mesh, coarsen, refine
 from oracle import sipg, onedim, multigrid, krylov
-from synthetic import loguniform_widths
+from synthetic import loguniform_widths, random_vector
 
 
 @pytest.mark.parametrize("d,k", [(1, 3), (2, 2), (3, 2), (2, 4)])
@@ -81,3 +81,17 @@ def test_pcg_with_vcycle_converges():
     assert it < 40 and hist[-1] <= 1e-10
     xs = onedim.global_fastdiag_solve(fine, b)
     assert np.linalg.norm(x - xs) < 1e-8 * np.linalg.norm(xs)
+
+
+@pytest.mark.parametrize("kind,d,k,ms", [("vertex", 2, 2, (4, 4)), ("cell", 2, 3, (4, 4))])
+def test_gmres_with_multiplicative_vcycle_converges(kind, d, k, ms):
+    """GMRES with the multiplicative V-cycle (Alg. multsmoother on every level)
+    reaches the exact discrete solution (global fast diagonalisation)."""
+    from oracle import krylov, onedim
+    fine = refine(uniform_mesh(d, k, ms))
+    oh = multigrid.Hierarchy(fine, 2, kind, [0.0, 1.0], m_pre=1, m_post=1, smoother="multiplicative")
+    b = random_vector(fine.ndofs, 0)
+    x, it, hist = krylov.gmres(oh.A[-1], b, lambda v: oh.vcycle(np.zeros_like(v), v), restart=20, rtol=1e-10)
+    assert hist[-1] <= 1e-10 and it < 40
+    xs = onedim.global_fastdiag_solve(fine, b)
+    assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
