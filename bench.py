@@ -166,6 +166,55 @@ def batched_workload():
             "residual_ms": t_res, "launch": report.strip().splitlines()[-1]}
 
 
+def multiplicative_workload():
+    """Multiplicative smoothers on the 3-D Q4 32^3 mesh (4,096,000 DoFs):
+    one sweep of the vertex-patch smoother with 2^(d+1) = 16 colors and of the
+    red-black cell smoother (a residual before every color, Alg. multsmoother),
+    and time-to-solution at a relative residual of 1e-8 (the paper's
+    criterion) of GMRES preconditioned by the V-cycle with the multiplicative
+    vertex-patch smoother (omega 1, 1+1 sweeps, 3 levels) next to PCG with the
+    additive one (omega 2^-3, 1+1 sweeps).  Setup excluded."""
+    import torch
+    import paper_1910_11239_amd as fts
+    cfg = CONFIGS["avs_3d_q4"]
+    dim, k, m, nl = cfg["dim"], cfg["k"], cfg["m"], cfg["nlevels"]
+    widths = uniform_widths(dim, m)
+    out = {"workload": "3-D SIPG Q4, 32^3 uniform cells (4,096,000 DoFs), FP64"}
+    lv = fts.Level(dim, k, widths, cfg["gamma_hat"])
+    N = lv.ndofs
+    b = torch.as_tensor(random_vector(N, cfg["seed_b"])).cuda()
+    x = torch.zeros(N, dtype=torch.float64, device="cuda")
+    ws = torch.empty(N, dtype=torch.float64, device="cuda")
+    for kind, ncol in (("vertex", 16), ("cell", 2)):
+        eg = fts.Eigs(lv, kind)
+        fn = lambda: fts.schwarz_smooth_mult(lv, eg, 1.0, b, x, nsweeps=1, ws=ws)
+        fn()
+        t = _events_time(fn, 5)
+        out[f"{kind}_sweep"] = {"colors": ncol, "ms": t, "dofs_per_s": N / (t * 1e-3)}
+        del eg
+    del lv
+    torch.cuda.empty_cache()
+    solve = {}
+    for name, smoother, omega, method in (("gmres_multiplicative_vertex", "multiplicative", 1.0, "gmres"),
+                                          ("pcg_additive_vertex", "additive", 0.125, "pcg")):
+        h = fts.Hierarchy(dim, k, widths, nl, "vertex", [0.0] + [omega] * (nl - 1), cfg["gamma_hat"], 1, 1)
+        h.set_smoother(smoother)
+        xs = torch.zeros(N, dtype=torch.float64, device="cuda")
+        run = (lambda: h.gmres(b, xs, rtol=1e-8, restart=30, maxit=300)) if method == "gmres" else \
+              (lambda: h.pcg(b, xs, rtol=1e-8, maxit=300))
+        run()  # warm-up
+        xs.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it, relres, _ = run()
+        torch.cuda.synchronize()
+        solve[name] = {"iterations": it, "final_relres": relres, "seconds": time.perf_counter() - t0}
+        del h
+        torch.cuda.empty_cache()
+    out["time_to_1e-8"] = solve
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +223,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the 48^3 Q7 mixed-precision CG comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-mesh batched sweep")
+    ap.add_argument("--no-mult", action="store_true", help="skip the multiplicative-smoother measurements")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + steps of the V-cycle only (for rocprofv3)")
     ap.add_argument("--profile-mixed", choices=["f64", "f32", "f16", "bf16"],
@@ -322,6 +372,8 @@ def main():
         out["mixed_vs_fp64"] = mixed_vs_fp64()
     if not args.no_batched:
         out["batched"] = batched_workload()
+    if not args.no_mult:
+        out["multiplicative"] = multiplicative_workload()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out))
