@@ -527,6 +527,133 @@ k_schwarz_mfma(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r,
 }
 
 // ---------------------------------------------------------------------------
+// FP64 local solves on MFMA (v_mfma_f64_16x16x4f64) for 3-D vertex patches of
+// extent N = 16 (k = 7), the shape where each 1-D contraction of 16 lines is
+// a dense 16 x 16 x 16 product.  Same algorithm and arithmetic type as
+// k_schwarz (only the summation order differs).  Operand layout of the
+// instruction: lane l holds A[l % 16][l / 16] and B[l / 16][l % 16] and
+// receives D[4 v + l / 16][l % 16] in slot v.  A contraction Out^T = Mat In^T
+// of 16 lines runs as 4 instructions; in step c lane group q = l / 16
+// supplies k = 4 c + q, so the result (mode 4 v + q in slot v) is already the
+// B operand of a following contraction along the same lines: the last axis
+// runs forward transform, eigenvalue scaling and backward transform in
+// registers.  The tensor lives in LDS with the pitches of the 16-bit path.
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <int N1, bool STAGE>
+__global__ void __launch_bounds__(256)
+k_schwarz_mfma64(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r, double *__restrict__ x,
+                 double *__restrict__ W, double omega) {
+    constexpr int N = 2 * N1, NC1 = N1 * N1 * N1, NSC = 8;
+    static_assert(N == 16, "one 16 x 16 tile per contraction");
+    __shared__ double Ts[16 * kPz];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int64_t s = blockIdx.x;
+    if (!sub_in_color(sg, s)) return;  // uniform: the whole workgroup leaves before any barrier
+    int pos[3];
+    {
+        const int j0 = (int)(s % sg.cnt[0]);
+        const int64_t rr = s / sg.cnt[0];
+        pos[0] = __builtin_amdgcn_readfirstlane(sg.first[0] + sg.step * j0);
+        pos[1] = __builtin_amdgcn_readfirstlane(sg.first[1] + sg.step * (int)(rr % sg.cnt[1]));
+        pos[2] = __builtin_amdgcn_readfirstlane(sg.first[2] + sg.step * (int)(rr / sg.cnt[1]));
+    }
+    const int64_t cs1 = g.m[0], cs2 = (int64_t)g.m[0] * g.m[1];
+    // thread t owns the patch line along x with (a1, a2) = (t % 16, t / 16)
+    const int a1 = t % N, a2 = t / N;
+    const int o1 = a1 / N1, i1 = a1 % N1, o2 = a2 / N1, i2 = a2 % N1;
+    const int64_t cell0 = pos[0] + (pos[1] + o1) * cs1 + (pos[2] + o2) * cs2;
+    const int iofs = i1 * N1 + i2 * N1 * N1;
+    const int lbase = a1 * kPy + a2 * kPz;
+    {
+        const double *src = r + cell0 * NC1 + iofs;
+        double rv[N];
+#pragma unroll
+        for (int o0 = 0; o0 < 2; ++o0)
+#pragma unroll
+            for (int i0 = 0; i0 < N1; ++i0) rv[o0 * N1 + i0] = src[o0 * NC1 + i0];
+#pragma unroll
+        for (int a0 = 0; a0 < N; ++a0) Ts[lbase + a0] = rv[a0];
+    }
+    __syncthreads();
+    const int q = lane >> 4, j = lane & 15;
+    constexpr int nn = N * N;
+    // A operand of step c: Mat[j][4 c + q]
+    auto amat = [&](const double *M, double *A) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) A[c] = M[j * N + 4 * c + q];
+    };
+    auto tiles = [&](int a, const double *A) {
+        const int st = mline_stride(a);
+        for (int tt = wv; tt < 16; tt += 4) {
+            const int base = mline_base(a, 16 * tt + j);
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[c], Ts[base + st * (4 * c + q)], acc, 0, 0, 0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Ts[base + st * (4 * v + q)] = acc[v];
+        }
+    };
+    double A[4];
+    // forward transforms along x and y: Mat = S^T
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        amat(e.ST[a] + (size_t)pos[a] * nn, A);
+        tiles(a, A);
+        __syncthreads();
+    }
+    {
+        double Af[4], Ab[4];
+        amat(e.ST[2] + (size_t)pos[2] * nn, Af);
+        amat(e.S[2] + (size_t)pos[2] * nn, Ab);
+        const double *lx = e.lam[0] + (size_t)pos[0] * N, *ly = e.lam[1] + (size_t)pos[1] * N;
+        const double *lz = e.lam[2] + (size_t)pos[2] * N;
+        for (int tt = wv; tt < 16; tt += 4) {
+            const int base = mline_base(2, 16 * tt + j);
+            d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Af[c], Ts[base + kPz * (4 * c + q)], acc, 0, 0, 0);
+            // this z-line has modes (j, tt) along x and y; slot v holds mode 4 v + q along z
+            const double lxy = lx[j] + ly[tt];
+            d4 acc2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double sc = acc[c] * (omega * recip(lxy + lz[4 * c + q]));
+                acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(Ab[c], sc, acc2, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Ts[base + kPz * (4 * v + q)] = acc2[v];
+        }
+        __syncthreads();
+    }
+    // backward transforms along y and x: Mat = S
+#pragma unroll
+    for (int a = 1; a >= 0; --a) {
+        amat(e.S[a] + (size_t)pos[a] * nn, A);
+        tiles(a, A);
+        __syncthreads();
+    }
+    double cv[N];
+#pragma unroll
+    for (int a0 = 0; a0 < N; ++a0) cv[a0] = Ts[lbase + a0];
+    if constexpr (STAGE) {
+        double *dst = W + s * (NSC * NC1) + (2 * o1 + 4 * o2) * NC1 + iofs;
+#pragma unroll
+        for (int o0 = 0; o0 < 2; ++o0)
+#pragma unroll
+            for (int i0 = 0; i0 < N1; ++i0) dst[o0 * NC1 + i0] = cv[o0 * N1 + i0];
+    } else {
+        double *dst = x + cell0 * NC1 + iofs;
+#pragma unroll
+        for (int o0 = 0; o0 < 2; ++o0)
+#pragma unroll
+            for (int i0 = 0; i0 < N1; ++i0) dst[o0 * NC1 + i0] += cv[o0 * N1 + i0];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Transfers (Sec. 2.2).  Child c of a coarse cell sits at offset o in
 // {0,1}^d; its coefficients are (E_{o_d} x..x E_{o_1}) applied to the coarse
 // coefficients, E_o[i][j] = phi_j((xi_i + o)/2).  Restriction applies the
@@ -837,13 +964,60 @@ struct RunSchwarz {
             return cell ? go_color_mfma<0, 0>(lv, eg, omega, r, x, color, st)
                         : go_color_mfma<1, 0>(lv, eg, omega, r, x, color, st);
         }
-        if (prec == FTS_PREC_F64)
+        if (prec == FTS_PREC_F64) {
+            if constexpr (D == 3 && N1 == 8)
+                if (!cell) {
+                    const SubGrid sg = color_grid<1>(eg, color);
+                    if (sg.nsub == 0) return FTS_OK;
+                    if (sg.nsub > INT_MAX) return fail(FTS_E_SIZE, "too many subdomains for one launch");
+                    k_schwarz_mfma64<N1, false><<<dim3((unsigned)sg.nsub), dim3(256), 0, st>>>(
+                        lv->view, eg->view, sg, r, x, nullptr, omega);
+                    return check_launch("k_schwarz_mfma64 (color)");
+                }
             return cell ? go_color<0, double>(lv, eg, omega, r, x, color, st)
                         : go_color<1, double>(lv, eg, omega, r, x, color, st);
+        }
         if (prec == FTS_PREC_F32)
             return cell ? go_color<0, float>(lv, eg, omega, r, x, color, st)
                         : go_color<1, float>(lv, eg, omega, r, x, color, st);
         return fail(FTS_E_UNSUPPORTED, "precision not built");
+    }
+    // FP64 vertex patches of extent 16 (3-D, k = 7): the MFMA kernel
+    static fts_status go_mfma64(const fts_level *lv, const fts_eigs *eg, double omega, const double *r, double *x,
+                                hipStream_t st) {
+        if constexpr (D != 3 || N1 != 8) {
+            return fail(FTS_E_UNSUPPORTED, "FP64 MFMA local solves need d = 3 and k = 7");
+        } else {
+            const bool staged = eg->schedule == FTS_SCHEDULE_STAGED;
+            const int ncolor = staged ? 1 : 8;
+            for (int color = 0; color < ncolor; ++color) {
+                SubGrid sg{};
+                sg.parity = -1;
+                sg.step = staged ? 1 : 2;
+                sg.nsub = 1;
+                for (int a = 0; a < 3; ++a) {
+                    sg.first[a] = staged ? 0 : ((color >> a) & 1);
+                    const int npos = eg->count[a];
+                    sg.cnt[a] = npos > sg.first[a] ? (npos - sg.first[a] + sg.step - 1) / sg.step : 0;
+                    sg.nsub *= sg.cnt[a];
+                }
+                if (sg.nsub == 0) continue;
+                if (sg.nsub > INT_MAX) return fail(FTS_E_SIZE, "too many subdomains for one launch");
+                if (staged)
+                    k_schwarz_mfma64<N1, true><<<dim3((unsigned)sg.nsub), dim3(256), 0, st>>>(
+                        lv->view, eg->view, sg, r, x, eg->d_stage, omega);
+                else
+                    k_schwarz_mfma64<N1, false><<<dim3((unsigned)sg.nsub), dim3(256), 0, st>>>(
+                        lv->view, eg->view, sg, r, x, nullptr, omega);
+                fts_status s = check_launch("k_schwarz_mfma64");
+                if (s != FTS_OK) return s;
+            }
+            if (staged) {
+                launch_gather<D, N1, double, false>(lv, eg->d_stage, nullptr, x, st);
+                return check_launch("k_patch_gather");
+            }
+            return FTS_OK;
+        }
     }
     static fts_status run(const fts_level *lv, const fts_eigs *eg, double omega, fts_prec prec, const double *r,
                           double *x, hipStream_t st) {
@@ -854,8 +1028,11 @@ struct RunSchwarz {
                 return bf ? go_mfma<0, 1>(lv, eg, omega, r, x, st) : go_mfma<0, 0>(lv, eg, omega, r, x, st);
             return bf ? go_mfma<1, 1>(lv, eg, omega, r, x, st) : go_mfma<1, 0>(lv, eg, omega, r, x, st);
         }
-        if (prec == FTS_PREC_F64)
+        if (prec == FTS_PREC_F64) {
+            if constexpr (D == 3 && N1 == 8)
+                if (eg->kind == FTS_VERTEX_PATCH) return go_mfma64(lv, eg, omega, r, x, st);
             return eg->kind == FTS_CELL ? go<0, double>(lv, eg, omega, r, x, st) : go<1, double>(lv, eg, omega, r, x, st);
+        }
         if (prec == FTS_PREC_F32)
             return eg->kind == FTS_CELL ? go<0, float>(lv, eg, omega, r, x, st) : go<1, float>(lv, eg, omega, r, x, st);
         return fail(FTS_E_UNSUPPORTED, "precision not built");

@@ -76,7 +76,8 @@ def test_setup_1d_eigs(kind, d, k, ms):
 
 SMOOTH_CASES = [("cell", 2, 3, (5, 4)), ("cell", 3, 4, (3, 4, 3)), ("cell", 3, 9, (2, 2, 1)),
                 ("vertex", 2, 3, (5, 4)), ("vertex", 2, 9, (3, 3)), ("vertex", 3, 1, (5, 4, 3)),
-                ("vertex", 3, 2, (4, 3, 5)), ("vertex", 3, 4, (3, 4, 3)), ("vertex", 3, 6, (3, 3, 2))]
+                ("vertex", 3, 2, (4, 3, 5)), ("vertex", 3, 4, (3, 4, 3)), ("vertex", 3, 6, (3, 3, 2)),
+                ("vertex", 3, 7, (3, 4, 3))]  # k = 7: FP64 MFMA local solves
 
 
 @pytest.mark.parametrize("kind,d,k,ms", SMOOTH_CASES)
