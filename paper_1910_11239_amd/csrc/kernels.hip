@@ -540,13 +540,26 @@ k_schwarz_mfma(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r,
 // registers.  The tensor lives in LDS with the pitches of the 16-bit path.
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// LDS pitches of the FP64 tile (in doubles): lanes (j, q) of a contraction
+// touch element (line j, index 4 c + q); with a line pitch of 17 and a plane
+// pitch of 272 = 16 (mod 32) the 64 addresses of each access spread over the
+// 32 double-wide bank pairs for lines along x, y and z alike.
+constexpr int kQy = 17, kQz = 272;
+__device__ __forceinline__ int qline_base(int a, int L) {
+    const int u = L & 15, v = L >> 4;
+    if (a == 0) return u * kQy + v * kQz;
+    if (a == 1) return u + v * kQz;
+    return u + v * kQy;
+}
+__device__ __forceinline__ int qline_stride(int a) { return a == 0 ? 1 : (a == 1 ? kQy : kQz); }
+
 template <int N1, bool STAGE>
 __global__ void __launch_bounds__(256)
 k_schwarz_mfma64(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r, double *__restrict__ x,
                  double *__restrict__ W, double omega) {
     constexpr int N = 2 * N1, NC1 = N1 * N1 * N1, NSC = 8;
     static_assert(N == 16, "one 16 x 16 tile per contraction");
-    __shared__ double Ts[16 * kPz];
+    __shared__ double Ts[16 * kQz];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int64_t s = blockIdx.x;
     if (!sub_in_color(sg, s)) return;  // uniform: the whole workgroup leaves before any barrier
@@ -564,7 +577,7 @@ k_schwarz_mfma64(LevelView g, EigView e, SubGrid sg, const double *__restrict__ 
     const int o1 = a1 / N1, i1 = a1 % N1, o2 = a2 / N1, i2 = a2 % N1;
     const int64_t cell0 = pos[0] + (pos[1] + o1) * cs1 + (pos[2] + o2) * cs2;
     const int iofs = i1 * N1 + i2 * N1 * N1;
-    const int lbase = a1 * kPy + a2 * kPz;
+    const int lbase = a1 * kQy + a2 * kQz;
     {
         const double *src = r + cell0 * NC1 + iofs;
         double rv[N];
@@ -584,9 +597,9 @@ k_schwarz_mfma64(LevelView g, EigView e, SubGrid sg, const double *__restrict__ 
         for (int c = 0; c < 4; ++c) A[c] = M[j * N + 4 * c + q];
     };
     auto tiles = [&](int a, const double *A) {
-        const int st = mline_stride(a);
+        const int st = qline_stride(a);
         for (int tt = wv; tt < 16; tt += 4) {
-            const int base = mline_base(a, 16 * tt + j);
+            const int base = qline_base(a, 16 * tt + j);
             d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int c = 0; c < 4; ++c)
@@ -610,11 +623,11 @@ k_schwarz_mfma64(LevelView g, EigView e, SubGrid sg, const double *__restrict__ 
         const double *lx = e.lam[0] + (size_t)pos[0] * N, *ly = e.lam[1] + (size_t)pos[1] * N;
         const double *lz = e.lam[2] + (size_t)pos[2] * N;
         for (int tt = wv; tt < 16; tt += 4) {
-            const int base = mline_base(2, 16 * tt + j);
+            const int base = qline_base(2, 16 * tt + j);
             d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int c = 0; c < 4; ++c)
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Af[c], Ts[base + kPz * (4 * c + q)], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Af[c], Ts[base + kQz * (4 * c + q)], acc, 0, 0, 0);
             // this z-line has modes (j, tt) along x and y; slot v holds mode 4 v + q along z
             const double lxy = lx[j] + ly[tt];
             d4 acc2 = {0.0, 0.0, 0.0, 0.0};
@@ -624,7 +637,7 @@ k_schwarz_mfma64(LevelView g, EigView e, SubGrid sg, const double *__restrict__ 
                 acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(Ab[c], sc, acc2, 0, 0, 0);
             }
 #pragma unroll
-            for (int v = 0; v < 4; ++v) Ts[base + kPz * (4 * v + q)] = acc2[v];
+            for (int v = 0; v < 4; ++v) Ts[base + kQz * (4 * v + q)] = acc2[v];
         }
         __syncthreads();
     }
