@@ -5,14 +5,21 @@ A step is one V-cycle x = MG_L(0, b) (Alg. gmg) of the 3-D Q4 SIPG problem on
 32^3 uniform cells of the unit cube (4,096,000 DoFs, FP64): on each of the two
 finer levels 2 pre- and 2 post-smoothing sweeps of the additive vertex-patch
 Schwarz smoother (omega = 0.5, fast-diagonalisation local solves, matrix-free
-residual), restriction and prolongation, and the dense-LU solve of the
-64,000-DoF coarse problem (8^3 cells).  Setup (1-D eigenproblems, coarse LU)
-is outside the timed region; b is resident in HBM.
+residual), restriction and prolongation, and the LU solve of the 64,000-DoF
+coarse problem (8^3 cells; factors stored by slabs of cells, the exact zeros
+of the dense factors left out).  Setup (1-D eigenproblems, coarse LU) is
+outside the timed region; b is resident in HBM.
 
 value = fine-level DoFs processed per second = N / (time per V-cycle).
 Per-kernel rooflines are measured live with events on the launch stream.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+                    [--no-mixed] [--no-batched] [--no-mult]
+    python bench.py --profile-only | --profile-mixed PREC | --calibrate-copy   (for rocprofv3)
+
+The JSON line also carries the 48^3 Q7 mixed-precision CG comparison, the
+64-mesh batched sweep, the multiplicative smoothers with GMRES, and the CPU
+oracle baseline.
 """
 import argparse
 import json

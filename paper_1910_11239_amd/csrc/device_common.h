@@ -74,23 +74,6 @@ struct OpCfg {
     static constexpr int SLOT = D == 3 ? P * N1 * N1 : P * N1;
 };
 
-template <int D, int N1, typename P>
-__device__ __forceinline__ void mass_line(const double *src, double *dst, int a, int l, double scale, P Mh,
-                                          bool acc) {
-    const int base = line_base<D, N1>(a, l), st = line_stride<N1>(a);
-    double in[N1];
-#pragma unroll
-    for (int i = 0; i < N1; ++i) in[i] = src[base + i * st];
-#pragma unroll
-    for (int o = 0; o < N1; ++o) {
-        double s = 0.0;
-#pragma unroll
-        for (int i = 0; i < N1; ++i) s = fma((double)Mh[o * N1 + i], in[i], s);
-        s *= scale;
-        dst[base + o * st] = acc ? dst[base + o * st] + s : s;
-    }
-}
-
 template <int D, int N1, int KIND>
 struct SwCfg {
     static constexpr int N = KIND ? 2 * N1 : N1;

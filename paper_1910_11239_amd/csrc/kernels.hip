@@ -1,6 +1,7 @@
 // HIP kernels for gfx950: matrix-free SIPG operator, fast-diagonalisation
-// Schwarz local solves on cells and vertex patches, grid transfers and the
-// dense assembly of the coarse matrix.
+// Schwarz local solves on cells and vertex patches (FP64 / FP32 on the vector
+// units, FP64 and 16-bit variants on MFMA), grid transfers, the slab-blocked
+// assembly of the coarse matrix and the BLAS-1 kernels of CG and GMRES.
 //
 // Data layout: vectors are cell-major (cells lexicographic, x fastest), each
 // cell holding (k+1)^d FP64 coefficients lexicographic with x fastest.  A
