@@ -97,6 +97,10 @@ struct EigView {
     const float *mscale[3], *lmin[3];
     // S^T (dA/dgamma_hat) S per axis position (n x n, FP64), for the adjoint
     const double *DG[3];
+    // per axis and position: the first position with the same tables (the
+    // kernels read their tables there, so that a uniform mesh touches only
+    // a few distinct tables)
+    const int *cls[3];
 };
 
 }  // namespace fts
@@ -118,6 +122,8 @@ struct fts_eigs {
     int kind = 0, n = 0;
     int count[3] = {0, 0, 0};
     std::vector<double> A[3], M[3], S[3], lam[3], DG[3];
+    std::vector<int> cls[3];
+    int *d_cls = nullptr;
     double *d_tab = nullptr;
     float *d_tab32 = nullptr;
     double *d_stage = nullptr;  // staged corrections of all vertex patches (one per cell of each;

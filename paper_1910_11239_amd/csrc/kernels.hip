@@ -77,53 +77,58 @@ __device__ __forceinline__ void schwarz_generic(const LevelView &g, const EigVie
         int pos[3];
         position(s0, pos);
         for (int a = 0; a < 3; ++a) pos[a] = __builtin_amdgcn_readfirstlane(pos[a]);
+        int tp[3] = {0, 0, 0};  // table positions (EigView::cls)
+        for (int a = 0; a < D; ++a) tp[a] = __builtin_amdgcn_readfirstlane(e.cls[a][pos[a]]);
         const int nn = N * N;
-        if (act) contract_line<D, N, T>(Tq, 0, l, uniform_table(EigTab<T>::ST(e, 0) + (size_t)pos[0] * nn));
+        if (act) contract_line<D, N, T>(Tq, 0, l, uniform_table(EigTab<T>::ST(e, 0) + (size_t)tp[0] * nn));
         __syncthreads();
         if constexpr (D == 3) {
-            if (act) contract_line<D, N, T>(Tq, 1, l, uniform_table(EigTab<T>::ST(e, 1) + (size_t)pos[1] * nn));
+            if (act) contract_line<D, N, T>(Tq, 1, l, uniform_table(EigTab<T>::ST(e, 1) + (size_t)tp[1] * nn));
             __syncthreads();
         }
         if (act) {
             constexpr int a = D - 1;
-            cptr<T> L0 = uniform_table(EigTab<T>::L(e, 0) + (size_t)pos[0] * N);
+            cptr<T> L0 = uniform_table(EigTab<T>::L(e, 0) + (size_t)tp[0] * N);
             T lr = (T)L0[ml0];
-            if constexpr (D == 3) lr += (T)uniform_table(EigTab<T>::L(e, 1) + (size_t)pos[1] * N)[ml1];
-            last_axis_solve<D, N, T>(Tq, l, uniform_table(EigTab<T>::ST(e, a) + (size_t)pos[a] * nn),
-                                     uniform_table(EigTab<T>::S(e, a) + (size_t)pos[a] * nn),
-                                     uniform_table(EigTab<T>::L(e, a) + (size_t)pos[a] * N), lr, om);
+            if constexpr (D == 3) lr += (T)uniform_table(EigTab<T>::L(e, 1) + (size_t)tp[1] * N)[ml1];
+            last_axis_solve<D, N, T>(Tq, l, uniform_table(EigTab<T>::ST(e, a) + (size_t)tp[a] * nn),
+                                     uniform_table(EigTab<T>::S(e, a) + (size_t)tp[a] * nn),
+                                     uniform_table(EigTab<T>::L(e, a) + (size_t)tp[a] * N), lr, om);
         }
         __syncthreads();
         if constexpr (D == 3) {
-            if (act) contract_line<D, N, T>(Tq, 1, l, uniform_table(EigTab<T>::S(e, 1) + (size_t)pos[1] * nn));
+            if (act) contract_line<D, N, T>(Tq, 1, l, uniform_table(EigTab<T>::S(e, 1) + (size_t)tp[1] * nn));
             __syncthreads();
         }
-        if (act) contract_line<D, N, T>(Tq, 0, l, uniform_table(EigTab<T>::S(e, 0) + (size_t)pos[0] * nn));
+        if (act) contract_line<D, N, T>(Tq, 0, l, uniform_table(EigTab<T>::S(e, 0) + (size_t)tp[0] * nn));
         __syncthreads();
     } else {
         int pos[3] = {0, 0, 0};
         if (act) position(s, pos);
+        int tp[3] = {0, 0, 0};
+        if (act)
+            for (int a = 0; a < D; ++a) tp[a] = e.cls[a][pos[a]];
         const int nn = N * N;
-        if (act) contract_line<D, N, T>(Tq, 0, l, EigTab<T>::ST(e, 0) + (size_t)pos[0] * nn);
+        if (act) contract_line<D, N, T>(Tq, 0, l, EigTab<T>::ST(e, 0) + (size_t)tp[0] * nn);
         __syncthreads();
         if constexpr (D == 3) {
-            if (act) contract_line<D, N, T>(Tq, 1, l, EigTab<T>::ST(e, 1) + (size_t)pos[1] * nn);
+            if (act) contract_line<D, N, T>(Tq, 1, l, EigTab<T>::ST(e, 1) + (size_t)tp[1] * nn);
             __syncthreads();
         }
         if (act) {
             constexpr int a = D - 1;
-            T lr = EigTab<T>::L(e, 0)[(size_t)pos[0] * N + ml0];
-            if constexpr (D == 3) lr += EigTab<T>::L(e, 1)[(size_t)pos[1] * N + ml1];
-            last_axis_solve<D, N, T>(Tq, l, EigTab<T>::ST(e, a) + (size_t)pos[a] * nn,
-                                     EigTab<T>::S(e, a) + (size_t)pos[a] * nn,
-                                     EigTab<T>::L(e, a) + (size_t)pos[a] * N, lr, om);
+            T lr = EigTab<T>::L(e, 0)[(size_t)tp[0] * N + ml0];
+            if constexpr (D == 3) lr += EigTab<T>::L(e, 1)[(size_t)tp[1] * N + ml1];
+            last_axis_solve<D, N, T>(Tq, l, EigTab<T>::ST(e, a) + (size_t)tp[a] * nn,
+                                     EigTab<T>::S(e, a) + (size_t)tp[a] * nn,
+                                     EigTab<T>::L(e, a) + (size_t)tp[a] * N, lr, om);
         }
         __syncthreads();
         if constexpr (D == 3) {
-            if (act) contract_line<D, N, T>(Tq, 1, l, EigTab<T>::S(e, 1) + (size_t)pos[1] * nn);
+            if (act) contract_line<D, N, T>(Tq, 1, l, EigTab<T>::S(e, 1) + (size_t)tp[1] * nn);
             __syncthreads();
         }
-        if (act) contract_line<D, N, T>(Tq, 0, l, EigTab<T>::S(e, 0) + (size_t)pos[0] * nn);
+        if (act) contract_line<D, N, T>(Tq, 0, l, EigTab<T>::S(e, 0) + (size_t)tp[0] * nn);
         __syncthreads();
     }
     // scatter-add R_j^T
@@ -170,6 +175,8 @@ __device__ __forceinline__ void schwarz_lines3(const LevelView &g, const EigView
         pos[1] = __builtin_amdgcn_readfirstlane(sg.first[1] + sg.step * (rr % sg.cnt[1]));
         pos[2] = __builtin_amdgcn_readfirstlane(sg.first[2] + sg.step * (rr / sg.cnt[1]));
     }
+    int tp[3];  // table positions (EigView::cls)
+    for (int a = 0; a < 3; ++a) tp[a] = __builtin_amdgcn_readfirstlane(e.cls[a][pos[a]]);
     const bool act = l < LINES;
     const int a1 = l % N, a2 = l / N;
     const int o1 = a1 / N1, i1 = a1 % N1, o2 = a2 / N1, i2 = a2 % N1;
@@ -184,28 +191,28 @@ __device__ __forceinline__ void schwarz_lines3(const LevelView &g, const EigView
         for (int o0 = 0; o0 < NO; ++o0)
 #pragma unroll
             for (int i0 = 0; i0 < N1; ++i0) v[o0 * N1 + i0] = (T)src[o0 * NC1 + i0];
-        matvec_regs<N>(v, w, uniform_table(EigTab<T>::ST(e, 0) + (size_t)pos[0] * nn));
+        matvec_regs<N>(v, w, uniform_table(EigTab<T>::ST(e, 0) + (size_t)tp[0] * nn));
 #pragma unroll
         for (int a = 0; a < N; ++a) Ts[N * l + a] = w[a];
     }
     __syncthreads();
-    if (act) contract_line<3, N, T>(Ts, 1, l, uniform_table(EigTab<T>::ST(e, 1) + (size_t)pos[1] * nn));
+    if (act) contract_line<3, N, T>(Ts, 1, l, uniform_table(EigTab<T>::ST(e, 1) + (size_t)tp[1] * nn));
     __syncthreads();
     if (act) {
         // the z-line l has mode indices (l % N, l / N) along x and y
-        const T lr = (T)uniform_table(EigTab<T>::L(e, 0) + (size_t)pos[0] * N)[a1] +
-                     (T)uniform_table(EigTab<T>::L(e, 1) + (size_t)pos[1] * N)[a2];
-        last_axis_solve<3, N, T>(Ts, l, uniform_table(EigTab<T>::ST(e, 2) + (size_t)pos[2] * nn),
-                                 uniform_table(EigTab<T>::S(e, 2) + (size_t)pos[2] * nn),
-                                 uniform_table(EigTab<T>::L(e, 2) + (size_t)pos[2] * N), lr, (T)omega);
+        const T lr = (T)uniform_table(EigTab<T>::L(e, 0) + (size_t)tp[0] * N)[a1] +
+                     (T)uniform_table(EigTab<T>::L(e, 1) + (size_t)tp[1] * N)[a2];
+        last_axis_solve<3, N, T>(Ts, l, uniform_table(EigTab<T>::ST(e, 2) + (size_t)tp[2] * nn),
+                                 uniform_table(EigTab<T>::S(e, 2) + (size_t)tp[2] * nn),
+                                 uniform_table(EigTab<T>::L(e, 2) + (size_t)tp[2] * N), lr, (T)omega);
     }
     __syncthreads();
-    if (act) contract_line<3, N, T>(Ts, 1, l, uniform_table(EigTab<T>::S(e, 1) + (size_t)pos[1] * nn));
+    if (act) contract_line<3, N, T>(Ts, 1, l, uniform_table(EigTab<T>::S(e, 1) + (size_t)tp[1] * nn));
     __syncthreads();
     if (act) {
 #pragma unroll
         for (int a = 0; a < N; ++a) v[a] = Ts[N * l + a];
-        matvec_regs<N>(v, w, uniform_table(EigTab<T>::S(e, 0) + (size_t)pos[0] * nn));
+        matvec_regs<N>(v, w, uniform_table(EigTab<T>::S(e, 0) + (size_t)tp[0] * nn));
         if constexpr (STAGE) {
             T *dst = W + (int64_t)s * (NSC * NC1) + (2 * o1 + 4 * o2) * NC1 + iofs;
 #pragma unroll
@@ -406,6 +413,8 @@ k_schwarz_mfma(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r,
         pos[1] = __builtin_amdgcn_readfirstlane(sg.first[1] + sg.step * j1);
         pos[2] = __builtin_amdgcn_readfirstlane(sg.first[2] + sg.step * j2);
     }
+    int tp[3];  // table positions (EigView::cls)
+    for (int a = 0; a < 3; ++a) tp[a] = __builtin_amdgcn_readfirstlane(e.cls[a][pos[a]]);
     const int64_t cs1 = g.m[0], cs2 = (int64_t)g.m[0] * g.m[1];
     if (N < 16)
         for (int p = t; p < 16 * kPz; p += 256) Ts[p] = 0.f;
@@ -441,7 +450,7 @@ k_schwarz_mfma(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r,
     const float inv = rmax > 0.f ? 1.f / rmax : 0.f;
     const int c4 = 4 * (lane >> 4), j = lane & 15;
     auto mat = [&](const uint16_t *const *tab, int a) {
-        return M::load(tab[a] + (size_t)pos[a] * 256 + j * 16 + c4);
+        return M::load(tab[a] + (size_t)tp[a] * 256 + j * 16 + c4);
     };
     const uint16_t *const *Ftab = BF ? e.Fbf16 : e.Ff16;
     const uint16_t *const *Btab = BF ? e.Bbf16 : e.Bf16;
@@ -464,9 +473,9 @@ k_schwarz_mfma(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r,
     // z: forward, scaling Lambda_min / Lambda(m), backward, in registers
     {
         const typename M::vec Af = mat(Ftab, 2), Ab = mat(Btab, 2);
-        const float *lx = e.lam32[0] + (size_t)pos[0] * N, *ly = e.lam32[1] + (size_t)pos[1] * N;
-        const float *lz = e.lam32[2] + (size_t)pos[2] * N;
-        const float lmin = e.lmin[0][pos[0]] + e.lmin[1][pos[1]] + e.lmin[2][pos[2]];
+        const float *lx = e.lam32[0] + (size_t)tp[0] * N, *ly = e.lam32[1] + (size_t)tp[1] * N;
+        const float *lz = e.lam32[2] + (size_t)tp[2] * N;
+        const float lmin = e.lmin[0][tp[0]] + e.lmin[1][tp[1]] + e.lmin[2][tp[2]];
         for (int tt = wv; tt < 16; tt += 4) {
             const int base = mline_base(2, 16 * tt + j) + c4 * kPz;
             float v[4];
@@ -503,8 +512,8 @@ k_schwarz_mfma(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r,
         }
         __syncthreads();
     }
-    const double sx = e.mscale[0][pos[0]], sy = e.mscale[1][pos[1]], sz = e.mscale[2][pos[2]];
-    const double lmin = (double)e.lmin[0][pos[0]] + e.lmin[1][pos[1]] + e.lmin[2][pos[2]];
+    const double sx = e.mscale[0][tp[0]], sy = e.mscale[1][tp[1]], sz = e.mscale[2][tp[2]];
+    const double lmin = (double)e.lmin[0][tp[0]] + e.lmin[1][tp[1]] + e.lmin[2][tp[2]];
     const double F = (double)rmax * omega * (sx * sy * sz) * (sx * sy * sz) / lmin;
     if (STAGE && t == 0) Wsc[s] = F;
     if (own) {
@@ -572,6 +581,8 @@ k_schwarz_mfma64(LevelView g, EigView e, SubGrid sg, const double *__restrict__ 
         pos[1] = __builtin_amdgcn_readfirstlane(sg.first[1] + sg.step * (int)(rr % sg.cnt[1]));
         pos[2] = __builtin_amdgcn_readfirstlane(sg.first[2] + sg.step * (int)(rr / sg.cnt[1]));
     }
+    int tp[3];  // table positions (EigView::cls)
+    for (int a = 0; a < 3; ++a) tp[a] = __builtin_amdgcn_readfirstlane(e.cls[a][pos[a]]);
     const int64_t cs1 = g.m[0], cs2 = (int64_t)g.m[0] * g.m[1];
     // thread t owns the patch line along x with (a1, a2) = (t % 16, t / 16)
     const int a1 = t % N, a2 = t / N;
@@ -613,16 +624,16 @@ k_schwarz_mfma64(LevelView g, EigView e, SubGrid sg, const double *__restrict__ 
     // forward transforms along x and y: Mat = S^T
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-        amat(e.ST[a] + (size_t)pos[a] * nn, A);
+        amat(e.ST[a] + (size_t)tp[a] * nn, A);
         tiles(a, A);
         __syncthreads();
     }
     {
         double Af[4], Ab[4];
-        amat(e.ST[2] + (size_t)pos[2] * nn, Af);
-        amat(e.S[2] + (size_t)pos[2] * nn, Ab);
-        const double *lx = e.lam[0] + (size_t)pos[0] * N, *ly = e.lam[1] + (size_t)pos[1] * N;
-        const double *lz = e.lam[2] + (size_t)pos[2] * N;
+        amat(e.ST[2] + (size_t)tp[2] * nn, Af);
+        amat(e.S[2] + (size_t)tp[2] * nn, Ab);
+        const double *lx = e.lam[0] + (size_t)tp[0] * N, *ly = e.lam[1] + (size_t)tp[1] * N;
+        const double *lz = e.lam[2] + (size_t)tp[2] * N;
         for (int tt = wv; tt < 16; tt += 4) {
             const int base = qline_base(2, 16 * tt + j);
             d4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -645,7 +656,7 @@ k_schwarz_mfma64(LevelView g, EigView e, SubGrid sg, const double *__restrict__ 
     // backward transforms along y and x: Mat = S
 #pragma unroll
     for (int a = 1; a >= 0; --a) {
-        amat(e.S[a] + (size_t)pos[a] * nn, A);
+        amat(e.S[a] + (size_t)tp[a] * nn, A);
         tiles(a, A);
         __syncthreads();
     }

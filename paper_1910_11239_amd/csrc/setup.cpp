@@ -2,6 +2,8 @@
 // patches, generalised eigenproblems, and the level / eigen tables uploaded to
 // the device.  (Sec. 2.1, Sec. 3.2 of Witte, Arndt, Kanschat.)
 #include <algorithm>
+#include <array>
+#include <map>
 #include <cmath>
 #include <cstring>
 
@@ -449,8 +451,33 @@ fts_status setup_eigs_internal(const fts_level *lv, fts_patch_kind kind, bool st
         eg->M[a].assign((size_t)cnt * nn, 0.0);
         eg->S[a].assign((size_t)cnt * nn, 0.0);
         eg->lam[a].assign((size_t)cnt * n, 0.0);
+        eg->cls[a].assign(cnt, 0);
         const std::vector<double> &h = lv->h[a];
+        // The 1-D problem of a position is a function of the widths of the
+        // cells it covers and of their outer neighbours (-1: boundary).
+        // Positions with the same widths bit for bit share one table.
+        std::map<std::array<double, 4>, int> seen;
         for (int s = 0; s < cnt; ++s) {
+            std::array<double, 4> key;
+            if (kind == FTS_CELL)
+                key = {s > 0 ? h[s - 1] : -1.0, h[s], s + 1 < m ? h[s + 1] : -1.0, 0.0};
+            else
+                key = {s > 0 ? h[s - 1] : -1.0, h[s], h[s + 1], s + 2 < m ? h[s + 2] : -1.0};
+            const auto hit = seen.find(key);
+            if (hit != seen.end()) {
+                const int r = hit->second;
+                eg->cls[a][s] = r;
+                std::copy_n(&eg->A[a][(size_t)r * nn], nn, &eg->A[a][(size_t)s * nn]);
+                std::copy_n(&eg->M[a][(size_t)r * nn], nn, &eg->M[a][(size_t)s * nn]);
+                std::copy_n(&eg->S[a][(size_t)r * nn], nn, &eg->S[a][(size_t)s * nn]);
+                std::copy_n(&eg->lam[a][(size_t)r * n], n, &eg->lam[a][(size_t)s * n]);
+                const std::vector<double> dg(eg->DG[a].begin() + (size_t)r * nn,
+                                             eg->DG[a].begin() + (size_t)(r + 1) * nn);
+                eg->DG[a].insert(eg->DG[a].end(), dg.begin(), dg.end());
+                continue;
+            }
+            seen.emplace(key, s);
+            eg->cls[a][s] = s;
             double *A = &eg->A[a][(size_t)s * nn];
             double *M = &eg->M[a][(size_t)s * nn];
             if (kind == FTS_CELL) {
@@ -552,6 +579,24 @@ fts_status setup_eigs_internal(const fts_level *lv, fts_patch_kind kind, bool st
         delete eg;
         return fail(FTS_E_HIP, "upload of eigen tables failed");
     }
+    {
+        std::vector<int> hc;
+        for (int a = 0; a < 3; ++a) hc.insert(hc.end(), eg->cls[a].begin(), eg->cls[a].end());
+        if (hipMalloc(&eg->d_cls, std::max<size_t>(hc.size(), 1) * sizeof(int)) != hipSuccess ||
+            (!hc.empty() &&
+             hipMemcpy(eg->d_cls, hc.data(), hc.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)) {
+            if (eg->d_cls) hipFree(eg->d_cls);
+            hipFree(eg->d_tab);
+            hipFree(eg->d_tab32);
+            delete eg;
+            return fail(FTS_E_HIP, "upload of the table classes failed");
+        }
+        size_t co = 0;
+        for (int a = 0; a < 3; ++a) {
+            eg->view.cls[a] = eg->d_cls + co;
+            co += eg->cls[a].size();
+        }
+    }
     if (n <= 16) {
         // 16-bit MFMA tables: 4 matrices of 256 entries per (axis, position), plus 2 floats
         size_t cnt_all = 0;
@@ -564,6 +609,7 @@ fts_status setup_eigs_internal(const fts_level *lv, fts_patch_kind kind, bool st
         if (hipMalloc(&eg->d_mfma, host16.size()) != hipSuccess) {
             hipFree(eg->d_tab);
             hipFree(eg->d_tab32);
+            hipFree(eg->d_cls);
             delete eg;
             return fail(FTS_E_HIP, "hipMalloc of the MFMA tables failed");
         }
@@ -616,6 +662,7 @@ fts_status setup_eigs_internal(const fts_level *lv, fts_patch_kind kind, bool st
             hipFree(eg->d_tab);
             hipFree(eg->d_tab32);
             hipFree(eg->d_mfma);
+            hipFree(eg->d_cls);
             delete eg;
             return fail(FTS_E_HIP, "upload of the MFMA tables failed");
         }
@@ -630,6 +677,7 @@ fts_status setup_eigs_internal(const fts_level *lv, fts_patch_kind kind, bool st
             hipFree(eg->d_tab);
             hipFree(eg->d_tab32);
             if (eg->d_mfma) hipFree(eg->d_mfma);
+            hipFree(eg->d_cls);
             delete eg;
             return fail(FTS_E_HIP, "hipMalloc of the patch staging buffer failed");
         }
@@ -663,6 +711,7 @@ fts_status fts_eigs_destroy(fts_eigs *eigs) {
     if (eigs->d_stage) hipFree(eigs->d_stage);
     if (eigs->d_stage_scale) hipFree(eigs->d_stage_scale);
     if (eigs->d_mfma) hipFree(eigs->d_mfma);
+    if (eigs->d_cls) hipFree(eigs->d_cls);
     delete eigs;
     return FTS_OK;
 }
