@@ -218,9 +218,44 @@ inline fts_status check_launch(const char *what) {
 // same line in the neighbours K - e_t / K + e_t (used when present), ih, ihl,
 // ihr = inverse widths, gk = gamma_hat k (k+1).  PEN: only the penalty terms,
 // i.e. dA/dgamma_hat with gk = k (k+1).
+// out = scale * Mat in on one line, Mat centro-symmetric (Mat[i][j] =
+// Mat[n-1-i][n-1-j], true of the reference mass and stiffness because the
+// nodes are symmetric about the cell centre), from its even-odd form: with
+// h = n / 2 and he = (n + 1) / 2, E (he x he) acts on the sums
+// in_j + in_{n-1-j} (and the middle value for odd n), O (h x h) on the
+// differences in_j - in_{n-1-j}, and out_i, out_{n-1-i} are the sum and the
+// difference of the two results.  Half the multiplications of a plain
+// matrix-vector product, and half the table.
+template <int N, typename P>
+__device__ __forceinline__ void eo_matvec(const double *in, double *out, double scale, P E, P O) {
+    constexpr int H = N / 2, HE = (N + 1) / 2;
+    double ue[HE], uo[H > 0 ? H : 1];
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+        ue[j] = in[j] + in[N - 1 - j];
+        uo[j] = in[j] - in[N - 1 - j];
+    }
+    if constexpr (N % 2) ue[H] = in[H];
+#pragma unroll
+    for (int i = 0; i < HE; ++i) {
+        double se = 0.0;
+#pragma unroll
+        for (int j = 0; j < HE; ++j) se = fma((double)E[i * HE + j], ue[j], se);
+        if (i < H) {
+            double so = 0.0;
+#pragma unroll
+            for (int j = 0; j < H; ++j) so = fma((double)O[i * H + j], uo[j], so);
+            out[i] = (se + so) * scale;
+            out[N - 1 - i] = (se - so) * scale;
+        } else {
+            out[i] = se * scale;
+        }
+    }
+}
+
 template <int N1, bool PEN, typename P>
 __device__ __forceinline__ void sipg_line(const double *in, const double *nl, const double *nr, bool hasl, bool hasr,
-                                          double ih, double ihl, double ihr, double gk, P Lh, P d0, P d1,
+                                          double ih, double ihl, double ihr, double gk, P LE, P LO, P d0, P d1,
                                           double *out) {
     const double eta0 = hasl ? 0.5 : 1.0, eta1 = hasr ? 0.5 : 1.0;
     const double g0 = hasl ? gk * (ih + ihl) : 2.0 * gk * ih;
@@ -234,13 +269,7 @@ __device__ __forceinline__ void sipg_line(const double *in, const double *nl, co
         if (hasl) out[0] -= 0.5 * g0 * nl[N1 - 1];
         if (hasr) out[N1 - 1] -= 0.5 * g1 * nr[0];
     } else {
-#pragma unroll
-        for (int o = 0; o < N1; ++o) {
-            double s = 0.0;
-#pragma unroll
-            for (int j = 0; j < N1; ++j) s = fma((double)Lh[o * N1 + j], in[j], s);
-            out[o] = s * ih;
-        }
+        eo_matvec<N1>(in, out, ih, LE, LO);
         double dx0 = 0.0, dxn = 0.0;
 #pragma unroll
         for (int j = 0; j < N1; ++j) {
@@ -273,53 +302,49 @@ __device__ __forceinline__ void sipg_line(const double *in, const double *nl, co
     }
 }
 
-// out = scale * Mhat in on one line.
-template <int N1, typename P>
-__device__ __forceinline__ void mass_regs(const double *in, double *out, double scale, P Mh) {
-#pragma unroll
-    for (int o = 0; o < N1; ++o) {
-        double s = 0.0;
-#pragma unroll
-        for (int j = 0; j < N1; ++j) s = fma((double)Mh[o * N1 + j], in[j], s);
-        out[o] = s * scale;
-    }
-}
-
 // y = A x (RES: y = b - A x) on the CPW cells cell0, cell0+1, ... of the mesh
 // described by g (x, b, y: that mesh's vectors).  Shared by the single-mesh
 // and the batched kernels.  Thread (q, l) works on cell cell0 + q and is in
-// turn the owner of line l along x, along y and along z.  LDS per cell: the
-// cell's coefficients X and two work slots U, V, lines along x padded to an
-// odd pitch.  Neighbour lines are read from global memory by the thread that
-// needs them.  Sequence (3-D):
-//   x-lines: W_x -> U                       y-lines: U <- h_y h_z Mhat U, W_y -> V
-//   x-lines: U += h_x h_z Mhat V            z-lines: U <- Mhat U,          W_z -> V
-//   y-lines: V <- h_x h_y Mhat V            x-lines: y = U + Mhat V (or b - ...)
+// turn the owner of line l along x, along y and along z; it reads the lines
+// of the neighbours (and, for k >= 5, of its own cell) straight from global
+// memory (every such read is a coalesced run along x or a set of them).  LDS
+// per cell: two work slots U, V (and the cell's coefficients X for k <= 4),
+// lines along x padded to an odd pitch.  Sequence (3-D),
+// M = the reference mass (even-odd form) times the widths named:
+//   x-lines: W_x -> U                       y-lines: U <- h_y h_z M U, W_y -> V
+//   x-lines: U += h_x h_z M V               z-lines: U <- M U,         W_z -> V
+//   y-lines: V <- h_x h_y M V               x-lines: y = U + M V (or b - ...)
 template <int D, int N1, bool RES, bool PEN = false>
 __device__ __forceinline__ void operator_cells(const LevelView &g, int64_t cell0, const double *__restrict__ x,
                                                const double *__restrict__ b, double *__restrict__ y) {
     using C = OpCfg<D, N1>;
-    constexpr int NC = C::NC, LINES = C::LINES, CPW = C::CPW, TH = C::THREADS, P = C::P, SL = C::SLOT;
-    __shared__ double S[CPW][3][SL];
+    constexpr int NC = C::NC, LINES = C::LINES, CPW = C::CPW, P = C::P, SL = C::SLOT;
+    constexpr int HE = (N1 + 1) / 2;
+    // XL: the cell's own coefficients are staged in LDS (slot X) instead of
+    // being read from global memory once per axis.  Pays for small cells; from
+    // k = 5 on, the third slot costs more occupancy than the re-reads cost.
+    constexpr bool XL = N1 <= 5;
+    __shared__ double S[CPW][XL ? 3 : 2][SL];
     const int t = threadIdx.x;
     const int q = t / LINES, l = t % LINES;
     const int64_t cell = cell0 + q;
     const bool act = q < CPW && cell < g.ncells;
-    const cptr<double> Lh = uniform_table(g.Lhat), Mh = uniform_table(g.Mhat);
+    const cptr<double> LE = uniform_table(g.Leo), ME = uniform_table(g.Meo);
+    const cptr<double> LO = LE + HE * HE, MO = ME + HE * HE;
     const cptr<double> d0 = uniform_table(g.d0), d1 = uniform_table(g.d1);
     const double gk = PEN ? g.pk : g.gk;
     // padded LDS index of cell-local coefficient (i0, i1, i2)
     auto li = [](int i0, int i1, int i2) { return i0 + P * (i1 + N1 * i2); };
-
-    // own cells, coalesced
-    {
-        const int64_t ncopy = min((int64_t)CPW, g.ncells - cell0) * NC;
+    constexpr int X = 2;
+    if constexpr (XL) {
+        const int ncopy = (int)min((int64_t)CPW, g.ncells - cell0) * NC;
         const double *src = x + cell0 * NC;
-        for (int e = t; e < ncopy; e += TH) {
+        for (int e = t; e < ncopy; e += C::THREADS) {
             const int qq = e / NC, i = e % NC;
             const int i0 = i % N1, rest = i / N1;
-            S[qq][0][i0 + P * rest] = src[e];
+            S[qq][X][i0 + P * rest] = src[e];
         }
+        __syncthreads();
     }
     int c[3] = {0, 0, 0};
     double h[3] = {1.0, 1.0, 1.0};
@@ -352,8 +377,14 @@ __device__ __forceinline__ void operator_cells(const LevelView &g, int64_t cell0
     // W_a on this thread's line along axis a
     auto w_line = [&](int a, double *w) {
         double in[N1], nl[N1], nr[N1];
+        if constexpr (XL) {
 #pragma unroll
-        for (int j = 0; j < N1; ++j) in[j] = S[q][0][lds_idx(a, j)];
+            for (int j = 0; j < N1; ++j) in[j] = S[q][X][lds_idx(a, j)];
+        } else {
+            const double *own = x + cell * NC;
+#pragma unroll
+            for (int j = 0; j < N1; ++j) in[j] = own[line_idx(a, j)];
+        }
         const bool hasl = c[a] > 0, hasr = c[a] + 1 < g.m[a];
         double ihl = 1.0, ihr = 1.0;
         if (hasl) {
@@ -368,7 +399,7 @@ __device__ __forceinline__ void operator_cells(const LevelView &g, int64_t cell0
             for (int j = 0; j < N1; ++j) nr[j] = src[line_idx(a, j)];
             ihr = g.ih[a][c[a] + 1];
         }
-        sipg_line<N1, PEN>(in, nl, nr, hasl, hasr, g.ih[a][c[a]], ihl, ihr, gk, Lh, d0, d1, w);
+        sipg_line<N1, PEN>(in, nl, nr, hasl, hasr, g.ih[a][c[a]], ihl, ihr, gk, LE, LO, d0, d1, w);
     };
     auto ld = [&](int slot, int a, double *v) {
 #pragma unroll
@@ -378,49 +409,50 @@ __device__ __forceinline__ void operator_cells(const LevelView &g, int64_t cell0
 #pragma unroll
         for (int j = 0; j < N1; ++j) S[q][slot][lds_idx(a, j)] = v[j];
     };
-    __syncthreads();
+    auto mass = [&](const double *in, double *out, double scale) { eo_matvec<N1>(in, out, scale, ME, MO); };
+    constexpr int U = 0, V = 1;
     double w[N1], v[N1], m[N1];
     if constexpr (D == 3) {
         if (act) {
             w_line(0, w);
-            st(1, 0, w);
+            st(U, 0, w);
         }
         __syncthreads();
         if (act) {
-            ld(1, 1, v);
-            mass_regs<N1>(v, m, h[1] * h[2], Mh);
-            st(1, 1, m);
+            ld(U, 1, v);
+            mass(v, m, h[1] * h[2]);
+            st(U, 1, m);
             w_line(1, w);
-            st(2, 1, w);
+            st(V, 1, w);
         }
         __syncthreads();
         if (act) {
-            ld(2, 0, v);
-            mass_regs<N1>(v, m, h[0] * h[2], Mh);
-            ld(1, 0, v);
+            ld(V, 0, v);
+            mass(v, m, h[0] * h[2]);
+            ld(U, 0, v);
 #pragma unroll
             for (int j = 0; j < N1; ++j) v[j] += m[j];
-            st(1, 0, v);
+            st(U, 0, v);
         }
         __syncthreads();
         if (act) {
-            ld(1, 2, v);
-            mass_regs<N1>(v, m, 1.0, Mh);
-            st(1, 2, m);
+            ld(U, 2, v);
+            mass(v, m, 1.0);
+            st(U, 2, m);
             w_line(2, w);
-            st(2, 2, w);
+            st(V, 2, w);
         }
         __syncthreads();
         if (act) {
-            ld(2, 1, v);
-            mass_regs<N1>(v, m, h[0] * h[1], Mh);
-            st(2, 1, m);
+            ld(V, 1, v);
+            mass(v, m, h[0] * h[1]);
+            st(V, 1, m);
         }
         __syncthreads();
         if (act) {
-            ld(2, 0, v);
-            mass_regs<N1>(v, m, 1.0, Mh);
-            ld(1, 0, v);
+            ld(V, 0, v);
+            mass(v, m, 1.0);
+            ld(U, 0, v);
             double *dst = y + cell * NC + line_idx(0, 0);
             if constexpr (RES) {
                 const double *bb = b + cell * NC + line_idx(0, 0);
@@ -434,21 +466,21 @@ __device__ __forceinline__ void operator_cells(const LevelView &g, int64_t cell0
     } else {
         if (act) {
             w_line(0, w);
-            st(1, 0, w);
+            st(U, 0, w);
         }
         __syncthreads();
         if (act) {
-            ld(1, 1, v);
-            mass_regs<N1>(v, m, h[1], Mh);
-            st(1, 1, m);
+            ld(U, 1, v);
+            mass(v, m, h[1]);
+            st(U, 1, m);
             w_line(1, w);
-            st(2, 1, w);
+            st(V, 1, w);
         }
         __syncthreads();
         if (act) {
-            ld(2, 0, v);
-            mass_regs<N1>(v, m, h[0], Mh);
-            ld(1, 0, v);
+            ld(V, 0, v);
+            mass(v, m, h[0]);
+            ld(U, 0, v);
             double *dst = y + cell * NC + line_idx(0, 0);
             if constexpr (RES) {
                 const double *bb = b + cell * NC + line_idx(0, 0);

@@ -67,6 +67,7 @@ struct LevelView {
     const double *E;          // 2 x n1 x n1 embedding matrices
     const double *Lhat;       // n1 x n1 reference stiffness
     const double *d0, *d1;    // derivatives of the basis at 0 and at 1
+    const double *Meo, *Leo;  // Mhat, Lhat in even-odd form: E ((n1+1)/2)^2 then O (n1/2)^2, row-major
     double gk, pk;            // gamma_hat k (k+1) and k (k+1)
 };
 

@@ -309,6 +309,29 @@ fts_status sym_gen_eig(int n, const double *A, const double *M, double *S, doubl
 
 using namespace fts;
 
+// Even-odd form of a centro-symmetric n x n matrix M (M[i][j] = M[n-1-i][n-1-j];
+// the reference mass and stiffness are, up to rounding, because the nodes are
+// symmetric about the cell centre; M is symmetrised first).  With h = n / 2 and
+// he = (n + 1) / 2: E (he x he) maps the sums u_j + u_{n-1-j}, j < h, and for odd
+// n the middle value u_h, to the half sums (y_i + y_{n-1-i}) / 2 (i < h) and to
+// y_h; O (h x h) maps the differences u_j - u_{n-1-j} to the half differences.
+// Stored E then O, row-major.
+static std::vector<double> even_odd(const std::vector<double> &M, int n) {
+    const int h = n / 2, he = (n + 1) / 2;
+    auto sym = [&](int i, int j) { return 0.5 * (M[i * n + j] + M[(n - 1 - i) * n + (n - 1 - j)]); };
+    std::vector<double> out((size_t)he * he + (size_t)h * h, 0.0);
+    for (int i = 0; i < he; ++i)
+        for (int j = 0; j < he; ++j) {
+            double e;
+            if (i < h && j < h) e = 0.5 * (sym(i, j) + sym(i, n - 1 - j));
+            else e = sym(i, j);  // middle row or column (odd n)
+            out[(size_t)i * he + j] = e;
+        }
+    for (int i = 0; i < h; ++i)
+        for (int j = 0; j < h; ++j) out[(size_t)he * he + (size_t)i * h + j] = 0.5 * (sym(i, j) - sym(i, n - 1 - j));
+    return out;
+}
+
 extern "C" {
 
 const char *fts_version(void) { return "fts 0.1.0 (gfx950)"; }
@@ -373,7 +396,7 @@ fts_status fts_level_create(const fts_mesh_desc *mesh, fts_level **out) {
         }
         total += lv->host_cellop[a].size() + lv->host_iface[a].size() + 2 * lv->h[a].size();
     }
-    total += nn + 2 * nn + nn + 2 * lv->n1;
+    total += nn + 2 * nn + nn + 2 * lv->n1 + 2 * nn;
     if (hipMalloc(&lv->d_tab, total * sizeof(double)) != hipSuccess) {
         delete lv;
         return fail(FTS_E_HIP, "hipMalloc of level tables failed");
@@ -403,6 +426,8 @@ fts_status fts_level_create(const fts_mesh_desc *mesh, fts_level **out) {
     lv->view.Lhat = put(lv->ref.Lhat);
     lv->view.d0 = put(lv->ref.d0);
     lv->view.d1 = put(lv->ref.d1);
+    lv->view.Meo = put(even_odd(lv->ref.Mhat, lv->n1));
+    lv->view.Leo = put(even_odd(lv->ref.Lhat, lv->n1));
     lv->view.gk = lv->gamma_hat * lv->k * (lv->k + 1.0);
     lv->view.pk = lv->k * (lv->k + 1.0);
     lv->view.ncells = lv->ncells;
