@@ -3,6 +3,8 @@
 // (dimension, degree) dispatch to template instances.
 #pragma once
 
+#include <type_traits>
+
 #include "fts_internal.h"
 
 namespace fts {
@@ -137,6 +139,49 @@ __device__ __forceinline__ void matvec_regs(const T *in, T *out, P Mat) {
 #pragma unroll
         for (int j = 0; j < N; ++j) s = fma((T)Mat[o * N + j], in[j], s);
         out[o] = s;
+    }
+}
+
+// Contractions with a mirror-symmetric eigenbasis (EigView::sym): S (N x N,
+// N even, row-major [i][m]) has its N/2 even columns first (S[N-1-i][m] =
+// S[i][m]) and its N/2 odd ones last (S[N-1-i][m] = -S[i][m]), so only the
+// rows i < N/2 are read and each product costs half the FMAs.
+// out = S^T in:
+template <int N, typename T, typename P>
+__device__ __forceinline__ void eo_fwd(const T *in, T *out, P S) {
+    constexpr int H = N / 2;
+    T ue[H], uo[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+        ue[j] = in[j] + in[N - 1 - j];
+        uo[j] = in[j] - in[N - 1 - j];
+    }
+#pragma unroll
+    for (int m = 0; m < H; ++m) {
+        T se = 0, so = 0;
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            se = fma((T)S[i * N + m], ue[i], se);
+            so = fma((T)S[i * N + H + m], uo[i], so);
+        }
+        out[m] = se;
+        out[H + m] = so;
+    }
+}
+// out = S c:
+template <int N, typename T, typename P>
+__device__ __forceinline__ void eo_bwd(const T *c, T *out, P S) {
+    constexpr int H = N / 2;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        T ve = 0, vo = 0;
+#pragma unroll
+        for (int m = 0; m < H; ++m) {
+            ve = fma((T)S[i * N + m], c[m], ve);
+            vo = fma((T)S[i * N + H + m], c[H + m], vo);
+        }
+        out[i] = ve + vo;
+        out[N - 1 - i] = ve - vo;
     }
 }
 

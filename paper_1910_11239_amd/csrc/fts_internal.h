@@ -102,6 +102,10 @@ struct EigView {
     // kernels read their tables there, so that a uniform mesh touches only
     // a few distinct tables)
     const int *cls[3];
+    // per axis and position: 1 if its modes are ordered even-then-odd about
+    // the centre and S is exactly even / odd in them (contractions may use
+    // the even-odd form with the first n/2 rows of S), else 0
+    const int *sym[3];
 };
 
 }  // namespace fts
@@ -123,7 +127,7 @@ struct fts_eigs {
     int kind = 0, n = 0;
     int count[3] = {0, 0, 0};
     std::vector<double> A[3], M[3], S[3], lam[3], DG[3];
-    std::vector<int> cls[3];
+    std::vector<int> cls[3], sym[3];
     int *d_cls = nullptr;
     double *d_tab = nullptr;
     float *d_tab32 = nullptr;

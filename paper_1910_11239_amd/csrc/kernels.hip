@@ -184,49 +184,97 @@ __device__ __forceinline__ void schwarz_lines3(const LevelView &g, const EigView
     const int64_t cell0 = pos[0] + (pos[1] + o1) * cs1 + (pos[2] + o2) * cs2;
     const int iofs = i1 * N1 + i2 * N1 * N1;
     constexpr int nn = N * N;
-    T v[N], w[N];
-    if (act) {
-        const double *src = r + cell0 * NC1 + iofs;
-#pragma unroll
-        for (int o0 = 0; o0 < NO; ++o0)
-#pragma unroll
-            for (int i0 = 0; i0 < N1; ++i0) v[o0 * N1 + i0] = (T)src[o0 * NC1 + i0];
-        matvec_regs<N>(v, w, uniform_table(EigTab<T>::ST(e, 0) + (size_t)tp[0] * nn));
-#pragma unroll
-        for (int a = 0; a < N; ++a) Ts[N * l + a] = w[a];
-    }
-    __syncthreads();
-    if (act) contract_line<3, N, T>(Ts, 1, l, uniform_table(EigTab<T>::ST(e, 1) + (size_t)tp[1] * nn));
-    __syncthreads();
-    if (act) {
-        // the z-line l has mode indices (l % N, l / N) along x and y
-        const T lr = (T)uniform_table(EigTab<T>::L(e, 0) + (size_t)tp[0] * N)[a1] +
-                     (T)uniform_table(EigTab<T>::L(e, 1) + (size_t)tp[1] * N)[a2];
-        last_axis_solve<3, N, T>(Ts, l, uniform_table(EigTab<T>::ST(e, 2) + (size_t)tp[2] * nn),
-                                 uniform_table(EigTab<T>::S(e, 2) + (size_t)tp[2] * nn),
-                                 uniform_table(EigTab<T>::L(e, 2) + (size_t)tp[2] * N), lr, (T)omega);
-    }
-    __syncthreads();
-    if (act) contract_line<3, N, T>(Ts, 1, l, uniform_table(EigTab<T>::S(e, 1) + (size_t)tp[1] * nn));
-    __syncthreads();
-    if (act) {
-#pragma unroll
-        for (int a = 0; a < N; ++a) v[a] = Ts[N * l + a];
-        matvec_regs<N>(v, w, uniform_table(EigTab<T>::S(e, 0) + (size_t)tp[0] * nn));
-        if constexpr (STAGE) {
-            T *dst = W + (int64_t)s * (NSC * NC1) + (2 * o1 + 4 * o2) * NC1 + iofs;
+    const cptr<T> S0 = uniform_table(EigTab<T>::S(e, 0) + (size_t)tp[0] * nn);
+    const cptr<T> S1 = uniform_table(EigTab<T>::S(e, 1) + (size_t)tp[1] * nn);
+    const cptr<T> S2 = uniform_table(EigTab<T>::S(e, 2) + (size_t)tp[2] * nn);
+    const cptr<T> ST0 = uniform_table(EigTab<T>::ST(e, 0) + (size_t)tp[0] * nn);
+    const cptr<T> ST1 = uniform_table(EigTab<T>::ST(e, 1) + (size_t)tp[1] * nn);
+    const cptr<T> ST2 = uniform_table(EigTab<T>::ST(e, 2) + (size_t)tp[2] * nn);
+    const cptr<T> L2 = uniform_table(EigTab<T>::L(e, 2) + (size_t)tp[2] * N);
+    // the z-line l has mode indices (l % N, l / N) along x and y (idle
+    // threads l >= N^2 read mode 0)
+    const T lr = (T)uniform_table(EigTab<T>::L(e, 0) + (size_t)tp[0] * N)[act ? a1 : 0] +
+                 (T)uniform_table(EigTab<T>::L(e, 1) + (size_t)tp[1] * N)[act ? a2 : 0];
+    const T om = (T)omega;
+    // the same sequence with plain or even-odd contractions (mirror-symmetric
+    // eigenbases along all three axes: most patches of a uniform mesh)
+    auto solve = [&](auto eo) {
+        constexpr bool EO = decltype(eo)::value;
+        auto fwd = [&](const T *in, T *out, cptr<T> S, cptr<T> ST) {
+            if constexpr (EO) eo_fwd<N>(in, out, S);
+            else matvec_regs<N>(in, out, ST);
+        };
+        auto bwd = [&](const T *in, T *out, cptr<T> S) {
+            if constexpr (EO) eo_bwd<N>(in, out, S);
+            else matvec_regs<N>(in, out, S);
+        };
+        T v[N], w[N];
+        if (act) {
+            const double *src = r + cell0 * NC1 + iofs;
 #pragma unroll
             for (int o0 = 0; o0 < NO; ++o0)
 #pragma unroll
-                for (int i0 = 0; i0 < N1; ++i0) dst[o0 * NC1 + i0] = w[o0 * N1 + i0];
-        } else {
-            double *dst = x + cell0 * NC1 + iofs;
+                for (int i0 = 0; i0 < N1; ++i0) v[o0 * N1 + i0] = (T)src[o0 * NC1 + i0];
+            fwd(v, w, S0, ST0);
 #pragma unroll
-            for (int o0 = 0; o0 < NO; ++o0)
+            for (int a = 0; a < N; ++a) Ts[N * l + a] = w[a];
+        }
+        __syncthreads();
+        const int yb = line_base<3, N>(1, l), zb = line_base<3, N>(2, l);
+        if (act) {
 #pragma unroll
-                for (int i0 = 0; i0 < N1; ++i0) dst[o0 * NC1 + i0] += (double)w[o0 * N1 + i0];
+            for (int i = 0; i < N; ++i) v[i] = Ts[yb + i * N];
+            fwd(v, w, S1, ST1);
+#pragma unroll
+            for (int i = 0; i < N; ++i) Ts[yb + i * N] = w[i];
+        }
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) v[i] = Ts[zb + i * nn];
+            fwd(v, w, S2, ST2);
+#pragma unroll
+            for (int m = 0; m < N; ++m) w[m] = w[m] * (om * recip(lr + (T)L2[m]));
+            bwd(w, v, S2);
+#pragma unroll
+            for (int i = 0; i < N; ++i) Ts[zb + i * nn] = v[i];
+        }
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) v[i] = Ts[yb + i * N];
+            bwd(v, w, S1);
+#pragma unroll
+            for (int i = 0; i < N; ++i) Ts[yb + i * N] = w[i];
+        }
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int a = 0; a < N; ++a) v[a] = Ts[N * l + a];
+            bwd(v, w, S0);
+            if constexpr (STAGE) {
+                T *dst = W + (int64_t)s * (NSC * NC1) + (2 * o1 + 4 * o2) * NC1 + iofs;
+#pragma unroll
+                for (int o0 = 0; o0 < NO; ++o0)
+#pragma unroll
+                    for (int i0 = 0; i0 < N1; ++i0) dst[o0 * NC1 + i0] = w[o0 * N1 + i0];
+            } else {
+                double *dst = x + cell0 * NC1 + iofs;
+#pragma unroll
+                for (int o0 = 0; o0 < NO; ++o0)
+#pragma unroll
+                    for (int i0 = 0; i0 < N1; ++i0) dst[o0 * NC1 + i0] += (double)w[o0 * N1 + i0];
+            }
+        }
+    };
+    if constexpr (N % 2 == 0) {
+        const int symm = __builtin_amdgcn_readfirstlane(e.sym[0][tp[0]] & e.sym[1][tp[1]] & e.sym[2][tp[2]]);
+        if (symm) {
+            solve(std::true_type{});
+            return;
         }
     }
+    solve(std::false_type{});
 }
 
 template <int D, int N1, int KIND, typename T, bool STAGE>

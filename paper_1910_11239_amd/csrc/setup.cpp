@@ -571,6 +571,66 @@ fts_status setup_eigs_internal(const fts_level *lv, fts_patch_kind kind, bool st
         }
         total += 3 * eg->S[a].size() + eg->lam[a].size();
     }
+    // Device copies of the tables.  A position whose 1-D problem is mirror
+    // symmetric about its centre (equal widths on both sides, n even) has
+    // eigenvectors that are even or odd about the centre (Sec. 3.2: S is
+    // determined up to the order and sign of its columns).  Its modes are
+    // reordered, the n/2 even ones first, and each vector is made exactly
+    // even or odd, so that the kernels can contract it in even-odd form with
+    // the first n/2 rows of S.  fts_eigs_get returns the eigen-solver's order.
+    std::vector<double> Sd[3], lamd[3], DGd[3];
+    for (int a = 0; a < 3; ++a) {
+        Sd[a] = eg->S[a];
+        lamd[a] = eg->lam[a];
+        DGd[a] = eg->DG[a];
+        eg->sym[a].assign(eg->count[a], 0);
+        if (n % 2) continue;
+        const int m = lv->m[a], h2 = n / 2;
+        const std::vector<double> &h = lv->h[a];
+        for (int p = 0; p < eg->count[a]; ++p) {
+            const int r = eg->cls[a][p];
+            if (r != p) {
+                std::copy_n(&Sd[a][(size_t)r * nn], nn, &Sd[a][(size_t)p * nn]);
+                std::copy_n(&lamd[a][(size_t)r * n], n, &lamd[a][(size_t)p * n]);
+                std::copy_n(&DGd[a][(size_t)r * nn], nn, &DGd[a][(size_t)p * nn]);
+                eg->sym[a][p] = eg->sym[a][r];
+                continue;
+            }
+            const bool mirror = kind == FTS_CELL
+                                    ? (p > 0 ? h[p - 1] : -1.0) == (p + 1 < m ? h[p + 1] : -1.0)
+                                    : h[p] == h[p + 1] && (p > 0 ? h[p - 1] : -1.0) == (p + 2 < m ? h[p + 2] : -1.0);
+            if (!mirror) continue;
+            const double *S0 = &eg->S[a][(size_t)p * nn];
+            std::vector<int> even, odd;
+            for (int c = 0; c < n; ++c) {
+                double sc = 0.0, ep = 0.0, em = 0.0;
+                for (int i = 0; i < n; ++i) {
+                    sc = std::max(sc, std::fabs(S0[i * n + c]));
+                    ep = std::max(ep, std::fabs(S0[i * n + c] - S0[(n - 1 - i) * n + c]));
+                    em = std::max(em, std::fabs(S0[i * n + c] + S0[(n - 1 - i) * n + c]));
+                }
+                if (ep <= 1e-10 * sc) even.push_back(c);
+                else if (em <= 1e-10 * sc) odd.push_back(c);
+            }
+            if ((int)even.size() != h2 || (int)odd.size() != h2) continue;  // e.g. a repeated eigenvalue
+            std::vector<int> perm(even);
+            perm.insert(perm.end(), odd.begin(), odd.end());
+            double *Sp = &Sd[a][(size_t)p * nn];
+            for (int c = 0; c < n; ++c) {
+                const int q = perm[c];
+                const double sg = c < h2 ? 1.0 : -1.0;
+                for (int i = 0; i < h2; ++i) {
+                    const double v = 0.5 * (S0[i * n + q] + sg * S0[(n - 1 - i) * n + q]);
+                    Sp[i * n + c] = v;
+                    Sp[(n - 1 - i) * n + c] = sg * v;
+                }
+                lamd[a][(size_t)p * n + c] = eg->lam[a][(size_t)p * n + q];
+                for (int c2 = 0; c2 < n; ++c2)
+                    DGd[a][(size_t)p * nn + c * n + c2] = eg->DG[a][(size_t)p * nn + q * n + perm[c2]];
+            }
+            eg->sym[a][p] = 1;
+        }
+    }
     if (hipMalloc(&eg->d_tab, std::max<size_t>(total, 1) * sizeof(double)) != hipSuccess ||
         hipMalloc(&eg->d_tab32, std::max<size_t>(total, 1) * sizeof(float)) != hipSuccess) {
         if (eg->d_tab) hipFree(eg->d_tab);
@@ -584,17 +644,17 @@ fts_status setup_eigs_internal(const fts_level *lv, fts_patch_kind kind, bool st
         eg->view.count[a] = eg->count[a];
         eg->view.S[a] = eg->d_tab + off;
         eg->view.S32[a] = eg->d_tab32 + off;
-        for (double v : eg->S[a]) host[off++] = v;
+        for (double v : Sd[a]) host[off++] = v;
         eg->view.ST[a] = eg->d_tab + off;
         eg->view.ST32[a] = eg->d_tab32 + off;
         for (int s = 0; s < eg->count[a]; ++s)
             for (int m = 0; m < n; ++m)
-                for (int i = 0; i < n; ++i) host[off++] = eg->S[a][(size_t)s * nn + i * n + m];
+                for (int i = 0; i < n; ++i) host[off++] = Sd[a][(size_t)s * nn + i * n + m];
         eg->view.DG[a] = eg->d_tab + off;
-        for (double v : eg->DG[a]) host[off++] = v;
+        for (double v : DGd[a]) host[off++] = v;
         eg->view.lam[a] = eg->d_tab + off;
         eg->view.lam32[a] = eg->d_tab32 + off;
-        for (double v : eg->lam[a]) host[off++] = v;
+        for (double v : lamd[a]) host[off++] = v;
     }
     for (size_t i = 0; i < total; ++i) host32[i] = (float)host[i];
     if (total && (hipMemcpy(eg->d_tab, host.data(), total * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
@@ -607,6 +667,7 @@ fts_status setup_eigs_internal(const fts_level *lv, fts_patch_kind kind, bool st
     {
         std::vector<int> hc;
         for (int a = 0; a < 3; ++a) hc.insert(hc.end(), eg->cls[a].begin(), eg->cls[a].end());
+        for (int a = 0; a < 3; ++a) hc.insert(hc.end(), eg->sym[a].begin(), eg->sym[a].end());
         if (hipMalloc(&eg->d_cls, std::max<size_t>(hc.size(), 1) * sizeof(int)) != hipSuccess ||
             (!hc.empty() &&
              hipMemcpy(eg->d_cls, hc.data(), hc.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)) {
@@ -620,6 +681,10 @@ fts_status setup_eigs_internal(const fts_level *lv, fts_patch_kind kind, bool st
         for (int a = 0; a < 3; ++a) {
             eg->view.cls[a] = eg->d_cls + co;
             co += eg->cls[a].size();
+        }
+        for (int a = 0; a < 3; ++a) {
+            eg->view.sym[a] = eg->d_cls + co;
+            co += eg->sym[a].size();
         }
     }
     if (n <= 16) {
@@ -663,10 +728,10 @@ fts_status setup_eigs_internal(const fts_level *lv, fts_patch_kind kind, bool st
             eg->view.mscale[a] = df + fo;
             eg->view.lmin[a] = df + fo + cnt;
             for (int s = 0; s < cnt; ++s) {
-                const double *S = &eg->S[a][(size_t)s * nn];
-                double smax = 0.0, lmn = eg->lam[a][(size_t)s * n];
+                const double *S = &Sd[a][(size_t)s * nn];
+                double smax = 0.0, lmn = lamd[a][(size_t)s * n];
                 for (int i = 0; i < nn; ++i) smax = std::max(smax, std::fabs(S[i]));
-                for (int i = 0; i < n; ++i) lmn = std::min(lmn, eg->lam[a][(size_t)s * n + i]);
+                for (int i = 0; i < n; ++i) lmn = std::min(lmn, lamd[a][(size_t)s * n + i]);
                 for (int o = 0; o < 16; ++o)
                     for (int k2 = 0; k2 < 16; ++k2) {
                         const double fv = (o < n && k2 < n) ? S[k2 * n + o] / smax : 0.0;

@@ -107,6 +107,37 @@ def test_schwarz_smooth(kind, d, k, ms):
         assert rel(host(xa), sol.apply(r)) < TOL, schedule
 
 
+@pytest.mark.parametrize("kind,k,widths", [("vertex", 3, "uniform"), ("vertex", 3, "mirrored"),
+                                            ("vertex", 4, "uniform"), ("vertex", 4, "mirrored"),
+                                            ("cell", 7, "uniform")])
+def test_schwarz_mirror_symmetric_positions(kind, k, widths):
+    """Positions whose 1-D problem is mirror symmetric (equal widths on both
+    sides) are contracted in even-odd form: on a uniform mesh every interior
+    position; on the mirrored widths (x, y: 1 1 2 2 1 1, z: 0.5 1 1 0.5) one
+    position per axis, next to positions that are not.  Same bar as every
+    FP64 smoother result, and the FP32 contractions within the FP32 bound."""
+    announce("mirror", kind, k, widths)
+    if widths == "uniform":
+        m = uniform_mesh(3, k, (5, 4, 5) if kind == "vertex" else (3, 3, 3))
+    else:
+        wx, wz = np.array([1.0, 1.0, 2.0, 2.0, 1.0, 1.0]), np.array([0.5, 1.0, 1.0, 0.5])
+        m = Mesh(3, k, (wx / wx.sum(), wx / wx.sum(), wz / wz.sum()), 1.0)
+    A = sipg.assemble(m)
+    subs = schwarz.cell_subdomains(m) if kind == "cell" else schwarz.vertex_patch_subdomains(m)
+    sol = schwarz.ExactLocalSolvers(A, subs, cache=False)
+    x, b = random_vector(m.ndofs, 1), random_vector(m.ndofs, 0)
+    omega = 0.7 if kind == "cell" else 0.3
+    ref = schwarz.additive_smooth(A, sol, x, b, omega)
+    lv = glevel(m)
+    eg = fts.Eigs(lv, kind)
+    xg = dev(x)
+    fts.schwarz_smooth(lv, eg, omega, dev(b), xg, nsweeps=1)
+    assert rel(host(xg), ref) < TOL
+    xg = dev(x)
+    fts.schwarz_smooth(lv, eg, omega, dev(b), xg, nsweeps=1, prec="f32")
+    assert rel(host(xg) - x, ref - x) < 1e-4
+
+
 def test_staged_schedule_is_deterministic():
     """Repeated staged applications give bit-identical results."""
     m = omesh(3, 3, (5, 4, 3), 19)
