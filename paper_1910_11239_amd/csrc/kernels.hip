@@ -159,6 +159,107 @@ __device__ __forceinline__ void schwarz_generic(const LevelView &g, const EigVie
 // axes; the last backward contraction also ends in registers and is written
 // to the staging buffer (or added to x) directly.  Index arithmetic happens
 // once per thread, not once per element.
+//
+// Tables of one subdomain: S and S^T per axis, the eigenvalues along z and
+// the sum of the x and y eigenvalues of this thread's z-line.
+template <typename T>
+struct PatchTabs {
+    cptr<T> S[3], ST[3], lam2;
+    T lr;
+};
+
+template <typename T, int N>
+__device__ __forceinline__ PatchTabs<T> patch_tabs(const EigView &e, const int *tp, bool act, int a1, int a2) {
+    constexpr int nn = N * N;
+    PatchTabs<T> pt;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        pt.S[a] = uniform_table(EigTab<T>::S(e, a) + (size_t)tp[a] * nn);
+        pt.ST[a] = uniform_table(EigTab<T>::ST(e, a) + (size_t)tp[a] * nn);
+    }
+    pt.lam2 = uniform_table(EigTab<T>::L(e, 2) + (size_t)tp[2] * N);
+    // the z-line l has mode indices (l % N, l / N) along x and y (idle
+    // threads l >= N^2 read mode 0)
+    pt.lr = (T)uniform_table(EigTab<T>::L(e, 0) + (size_t)tp[0] * N)[act ? a1 : 0] +
+            (T)uniform_table(EigTab<T>::L(e, 1) + (size_t)tp[1] * N)[act ? a2 : 0];
+    return pt;
+}
+
+// The local solve of one subdomain: src = this thread's line of the residual
+// (NO runs of N1 values, NC1 apart); on return w holds the thread's line of
+// the correction.  EO: even-odd contractions (mirror-symmetric eigenbases
+// along all three axes, EigView::sym).  Ts: N^3 values of LDS; the function
+// starts and ends with every thread free to use its own part of Ts.
+template <int N, int N1, int NO, int NC1, typename T, bool EO>
+__device__ __forceinline__ void lines3_solve(const double *__restrict__ src, bool act, int l, const PatchTabs<T> &pt,
+                                             T om, T *Ts, T *w) {
+    constexpr int nn = N * N;
+    auto fwd = [&](const T *in, T *out, int a) {
+        if constexpr (EO) eo_fwd<N>(in, out, pt.S[a]);
+        else matvec_regs<N>(in, out, pt.ST[a]);
+    };
+    auto bwd = [&](const T *in, T *out, int a) {
+        if constexpr (EO) eo_bwd<N>(in, out, pt.S[a]);
+        else matvec_regs<N>(in, out, pt.S[a]);
+    };
+    T v[N];
+    if (act) {
+#pragma unroll
+        for (int o0 = 0; o0 < NO; ++o0)
+#pragma unroll
+            for (int i0 = 0; i0 < N1; ++i0) v[o0 * N1 + i0] = (T)src[o0 * NC1 + i0];
+        fwd(v, w, 0);
+#pragma unroll
+        for (int a = 0; a < N; ++a) Ts[N * l + a] = w[a];
+    }
+    __syncthreads();
+    const int yb = line_base<3, N>(1, l), zb = line_base<3, N>(2, l);
+    if (act) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = Ts[yb + i * N];
+        fwd(v, w, 1);
+#pragma unroll
+        for (int i = 0; i < N; ++i) Ts[yb + i * N] = w[i];
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = Ts[zb + i * nn];
+        fwd(v, w, 2);
+#pragma unroll
+        for (int m = 0; m < N; ++m) w[m] = w[m] * (om * recip(pt.lr + (T)pt.lam2[m]));
+        bwd(w, v, 2);
+#pragma unroll
+        for (int i = 0; i < N; ++i) Ts[zb + i * nn] = v[i];
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = Ts[yb + i * N];
+        bwd(v, w, 1);
+#pragma unroll
+        for (int i = 0; i < N; ++i) Ts[yb + i * N] = w[i];
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+        for (int a = 0; a < N; ++a) v[a] = Ts[N * l + a];
+        bwd(v, w, 0);
+    }
+}
+
+template <int N, int N1, int NO, int NC1, typename T>
+__device__ __forceinline__ void lines3_solve_any(bool eo, const double *__restrict__ src, bool act, int l,
+                                                 const PatchTabs<T> &pt, T om, T *Ts, T *w) {
+    if constexpr (N % 2 == 0) {
+        if (eo) {
+            lines3_solve<N, N1, NO, NC1, T, true>(src, act, l, pt, om, Ts, w);
+            return;
+        }
+    }
+    lines3_solve<N, N1, NO, NC1, T, false>(src, act, l, pt, om, Ts, w);
+}
+
 template <int N1, int KIND, typename T, bool STAGE>
 __device__ __forceinline__ void schwarz_lines3(const LevelView &g, const EigView &e, const SubGrid &sg,
                                                const double *__restrict__ r, double *__restrict__ x,
@@ -183,98 +284,82 @@ __device__ __forceinline__ void schwarz_lines3(const LevelView &g, const EigView
     const int64_t cs1 = g.m[0], cs2 = (int64_t)g.m[0] * g.m[1];
     const int64_t cell0 = pos[0] + (pos[1] + o1) * cs1 + (pos[2] + o2) * cs2;
     const int iofs = i1 * N1 + i2 * N1 * N1;
-    constexpr int nn = N * N;
-    const cptr<T> S0 = uniform_table(EigTab<T>::S(e, 0) + (size_t)tp[0] * nn);
-    const cptr<T> S1 = uniform_table(EigTab<T>::S(e, 1) + (size_t)tp[1] * nn);
-    const cptr<T> S2 = uniform_table(EigTab<T>::S(e, 2) + (size_t)tp[2] * nn);
-    const cptr<T> ST0 = uniform_table(EigTab<T>::ST(e, 0) + (size_t)tp[0] * nn);
-    const cptr<T> ST1 = uniform_table(EigTab<T>::ST(e, 1) + (size_t)tp[1] * nn);
-    const cptr<T> ST2 = uniform_table(EigTab<T>::ST(e, 2) + (size_t)tp[2] * nn);
-    const cptr<T> L2 = uniform_table(EigTab<T>::L(e, 2) + (size_t)tp[2] * N);
-    // the z-line l has mode indices (l % N, l / N) along x and y (idle
-    // threads l >= N^2 read mode 0)
-    const T lr = (T)uniform_table(EigTab<T>::L(e, 0) + (size_t)tp[0] * N)[act ? a1 : 0] +
-                 (T)uniform_table(EigTab<T>::L(e, 1) + (size_t)tp[1] * N)[act ? a2 : 0];
-    const T om = (T)omega;
-    // the same sequence with plain or even-odd contractions (mirror-symmetric
-    // eigenbases along all three axes: most patches of a uniform mesh)
-    auto solve = [&](auto eo) {
-        constexpr bool EO = decltype(eo)::value;
-        auto fwd = [&](const T *in, T *out, cptr<T> S, cptr<T> ST) {
-            if constexpr (EO) eo_fwd<N>(in, out, S);
-            else matvec_regs<N>(in, out, ST);
-        };
-        auto bwd = [&](const T *in, T *out, cptr<T> S) {
-            if constexpr (EO) eo_bwd<N>(in, out, S);
-            else matvec_regs<N>(in, out, S);
-        };
-        T v[N], w[N];
-        if (act) {
-            const double *src = r + cell0 * NC1 + iofs;
+    const PatchTabs<T> pt = patch_tabs<T, N>(e, tp, act, a1, a2);
+    const bool eo = __builtin_amdgcn_readfirstlane(e.sym[0][tp[0]] & e.sym[1][tp[1]] & e.sym[2][tp[2]]) != 0;
+    T w[N];
+    lines3_solve_any<N, N1, NO, NC1, T>(eo, r + cell0 * NC1 + iofs, act, l, pt, (T)omega, Ts, w);
+    if (act) {
+        if constexpr (STAGE) {
+            T *dst = W + (int64_t)s * (NSC * NC1) + (2 * o1 + 4 * o2) * NC1 + iofs;
 #pragma unroll
             for (int o0 = 0; o0 < NO; ++o0)
 #pragma unroll
-                for (int i0 = 0; i0 < N1; ++i0) v[o0 * N1 + i0] = (T)src[o0 * NC1 + i0];
-            fwd(v, w, S0, ST0);
+                for (int i0 = 0; i0 < N1; ++i0) dst[o0 * NC1 + i0] = w[o0 * N1 + i0];
+        } else {
+            double *dst = x + cell0 * NC1 + iofs;
 #pragma unroll
-            for (int a = 0; a < N; ++a) Ts[N * l + a] = w[a];
-        }
-        __syncthreads();
-        const int yb = line_base<3, N>(1, l), zb = line_base<3, N>(2, l);
-        if (act) {
+            for (int o0 = 0; o0 < NO; ++o0)
 #pragma unroll
-            for (int i = 0; i < N; ++i) v[i] = Ts[yb + i * N];
-            fwd(v, w, S1, ST1);
-#pragma unroll
-            for (int i = 0; i < N; ++i) Ts[yb + i * N] = w[i];
-        }
-        __syncthreads();
-        if (act) {
-#pragma unroll
-            for (int i = 0; i < N; ++i) v[i] = Ts[zb + i * nn];
-            fwd(v, w, S2, ST2);
-#pragma unroll
-            for (int m = 0; m < N; ++m) w[m] = w[m] * (om * recip(lr + (T)L2[m]));
-            bwd(w, v, S2);
-#pragma unroll
-            for (int i = 0; i < N; ++i) Ts[zb + i * nn] = v[i];
-        }
-        __syncthreads();
-        if (act) {
-#pragma unroll
-            for (int i = 0; i < N; ++i) v[i] = Ts[yb + i * N];
-            bwd(v, w, S1);
-#pragma unroll
-            for (int i = 0; i < N; ++i) Ts[yb + i * N] = w[i];
-        }
-        __syncthreads();
-        if (act) {
-#pragma unroll
-            for (int a = 0; a < N; ++a) v[a] = Ts[N * l + a];
-            bwd(v, w, S0);
-            if constexpr (STAGE) {
-                T *dst = W + (int64_t)s * (NSC * NC1) + (2 * o1 + 4 * o2) * NC1 + iofs;
-#pragma unroll
-                for (int o0 = 0; o0 < NO; ++o0)
-#pragma unroll
-                    for (int i0 = 0; i0 < N1; ++i0) dst[o0 * NC1 + i0] = w[o0 * N1 + i0];
-            } else {
-                double *dst = x + cell0 * NC1 + iofs;
-#pragma unroll
-                for (int o0 = 0; o0 < NO; ++o0)
-#pragma unroll
-                    for (int i0 = 0; i0 < N1; ++i0) dst[o0 * NC1 + i0] += (double)w[o0 * N1 + i0];
-            }
-        }
-    };
-    if constexpr (N % 2 == 0) {
-        const int symm = __builtin_amdgcn_readfirstlane(e.sym[0][tp[0]] & e.sym[1][tp[1]] & e.sym[2][tp[2]]);
-        if (symm) {
-            solve(std::true_type{});
-            return;
+                for (int i0 = 0; i0 < N1; ++i0) dst[o0 * NC1 + i0] += (double)w[o0 * N1 + i0];
         }
     }
-    solve(std::false_type{});
+}
+
+// Staged vertex patches (3-D, direct-line configuration), a run of up to cz
+// patches consecutive along z per workgroup.  Patches j and j+1 of a run
+// share the cell layer above patch j: its correction from patch j is kept
+// in LDS and added to that of patch j+1 before patch j+1 writes its lower
+// layer, and patch j writes no upper layer.  The staging buffer then holds
+// 4 + 4 / cz cell blocks per patch instead of 8; k_patch_gather skips the
+// upper-layer blocks that were merged (the same rule, cz).  Deterministic.
+template <int N1, typename T>
+__global__ void __launch_bounds__((SwCfg<3, N1, 1>::THREADS))
+k_schwarz_zrun(LevelView g, EigView e, SubGrid sg, int cz, const double *__restrict__ r, T *__restrict__ W,
+               double omega) {
+    using C = SwCfg<3, N1, 1>;
+    constexpr int N = C::N, NC1 = C::NC1, NSC = C::NSC, LINES = C::LINES, HALF = N1 * N * N;
+    static_assert(C::PPB == 1, "one patch per workgroup");
+    __shared__ T Ts[N * N * N];
+    __shared__ T carry[2][HALF];  // [k][i2][a1]: the upper layer of the previous patch
+    const int l = threadIdx.x;
+    const int nxy = sg.cnt[0] * sg.cnt[1];
+    const int b = blockIdx.x;
+    const int j0 = b % sg.cnt[0], j1 = (b / sg.cnt[0]) % sg.cnt[1], run = b / nxy;
+    const int jz0 = run * cz, jz1 = min(sg.cnt[2], jz0 + cz);
+    int tp[3];
+    tp[0] = __builtin_amdgcn_readfirstlane(e.cls[0][j0]);
+    tp[1] = __builtin_amdgcn_readfirstlane(e.cls[1][j1]);
+    const bool act = l < LINES;
+    const int a1 = l % N, a2 = l / N;
+    const int o1 = a1 / N1, i1 = a1 % N1, o2 = a2 / N1, i2 = a2 % N1;
+    const int64_t cs1 = g.m[0], cs2 = (int64_t)g.m[0] * g.m[1];
+    const int iofs = i1 * N1 + i2 * N1 * N1;
+    const int ci = i2 * N + a1;  // this thread's place in a carry layer
+    for (int jz = jz0; jz < jz1; ++jz) {
+        tp[2] = __builtin_amdgcn_readfirstlane(e.cls[2][jz]);
+        const PatchTabs<T> pt = patch_tabs<T, N>(e, tp, act, a1, a2);
+        const bool eo = __builtin_amdgcn_readfirstlane(e.sym[0][tp[0]] & e.sym[1][tp[1]] & e.sym[2][tp[2]]) != 0;
+        const int64_t cell0 = j0 + (j1 + o1) * cs1 + (jz + o2) * cs2;
+        T w[N];
+        lines3_solve_any<N, N1, 2, NC1, T>(eo, r + cell0 * NC1 + iofs, act, l, pt, (T)omega, Ts, w);
+        if (act) {
+            const int64_t s = j0 + (int64_t)sg.cnt[0] * (j1 + (int64_t)sg.cnt[1] * jz);
+            T *dst = W + s * (NSC * NC1) + (2 * o1 + 4 * o2) * NC1 + iofs;
+            if (o2 == 1 && jz + 1 < jz1) {
+#pragma unroll
+                for (int k = 0; k < N; ++k) carry[jz & 1][k * (N1 * N) + ci] = w[k];
+            } else {
+                if (o2 == 0 && jz > jz0) {
+#pragma unroll
+                    for (int k = 0; k < N; ++k) w[k] += carry[(jz - 1) & 1][k * (N1 * N) + ci];
+                }
+#pragma unroll
+                for (int o0 = 0; o0 < 2; ++o0)
+#pragma unroll
+                    for (int i0 = 0; i0 < N1; ++i0) dst[o0 * NC1 + i0] = w[o0 * N1 + i0];
+            }
+        }
+    }
 }
 
 template <int D, int N1, int KIND, typename T, bool STAGE>
@@ -311,7 +396,8 @@ struct GatherCfg {
 
 template <int D, int N1, typename WT, bool SCALED, int V>
 __global__ void __launch_bounds__(256) k_patch_gather(LevelView g, const WT *__restrict__ W,
-                                                      const double *__restrict__ Wsc, double *__restrict__ x) {
+                                                      const double *__restrict__ Wsc, double *__restrict__ x,
+                                                      int cz) {
     constexpr int NC1 = ipow(N1, D), NSC = 1 << D;
     static_assert(NC1 % V == 0, "a thread's DoFs must lie in one cell");
     using WV = typename VecOf<WT, V>::type;
@@ -328,7 +414,10 @@ __global__ void __launch_bounds__(256) k_patch_gather(LevelView g, const WT *__r
     for (int o = 0; o < NSC; ++o) {
         const int a0 = c0 - (o & 1), a1 = c1 - ((o >> 1) & 1), a2 = D == 3 ? c2 - ((o >> 2) & 1) : 0;
         const bool in = a0 >= 0 && a0 < cnt0 && a1 >= 0 && a1 < cnt1 && (D == 2 || (a2 >= 0 && a2 < g.m[2] - 1));
-        if (in) {
+        // upper layer of a patch whose successor along z is in the same run
+        // of cz patches: merged into the successor's lower layer
+        const bool merged = D == 3 && (o >> 2) && a2 + 1 < g.m[2] - 1 && (a2 + 1) % cz != 0;
+        if (in && !merged) {
             const int64_t sidx = a0 + (int64_t)cnt0 * (a1 + (int64_t)cnt1 * a2);
             const WV w = *(const WV *)(W + sidx * (NSC * NC1) + o * NC1 + i);
             XV wd;
@@ -345,16 +434,17 @@ __global__ void __launch_bounds__(256) k_patch_gather(LevelView g, const WT *__r
 // Vector width V when x is aligned for it (a caller may pass a view of a
 // larger vector), else one DoF per thread.
 template <int D, int N1, typename WT, bool SCALED>
-static void launch_gather(const fts_level *lv, const WT *W, const double *Wsc, double *x, hipStream_t st) {
+static void launch_gather(const fts_level *lv, const WT *W, const double *Wsc, double *x, hipStream_t st,
+                          int cz = 1) {
     constexpr int V = GatherCfg<D, N1>::V;
     const int64_t n = lv->ndofs;
     if (reinterpret_cast<uintptr_t>(x) % (V * sizeof(double)) == 0) {
         const int64_t nt = n / V;
         k_patch_gather<D, N1, WT, SCALED, V><<<dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st>>>(lv->view, W,
-                                                                                                       Wsc, x);
+                                                                                                       Wsc, x, cz);
     } else {
         k_patch_gather<D, N1, WT, SCALED, 1><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>(lv->view, W,
-                                                                                                      Wsc, x);
+                                                                                                      Wsc, x, cz);
     }
 }
 
@@ -904,6 +994,7 @@ struct RunSchwarz {
         using C = SwCfg<D, N1, KIND>;
         const bool staged = KIND == 1 && eg->schedule == FTS_SCHEDULE_STAGED;
         const int ncolor = (KIND && !staged) ? (1 << D) : 1;
+        int cz = 1;  // patches per run along z in the staging buffer (k_schwarz_zrun)
         for (int color = 0; color < ncolor; ++color) {
             SubGrid sg{};
             sg.parity = -1;
@@ -923,6 +1014,21 @@ struct RunSchwarz {
             if (sg.nsub == 0) continue;
             const int64_t blocks = (sg.nsub + C::PPB - 1) / C::PPB;
             if (blocks > INT_MAX) return fail(FTS_E_SIZE, "too many subdomains for one launch");
+            if constexpr (D == 3 && KIND == 1 && C::PPB == 1) {
+                // runs of cz patches along z, as long as enough workgroups remain
+                cz = 1;
+                while (cz < 8 && sg.nsub / (2 * cz) >= 6144) cz *= 2;
+                if (staged && cz > 1) {
+                    const int64_t runs = (sg.cnt[2] + cz - 1) / cz;
+                    k_schwarz_zrun<N1, T><<<dim3((unsigned)((int64_t)sg.cnt[0] * sg.cnt[1] * runs)),
+                                            dim3(C::THREADS), 0, st>>>(lv->view, eg->view, sg, cz, r,
+                                                                       reinterpret_cast<T *>(eg->d_stage), omega);
+                    fts_status s = check_launch("k_schwarz_zrun");
+                    if (s != FTS_OK) return s;
+                    continue;
+                }
+                cz = 1;
+            }
             if (staged)
                 k_schwarz<D, N1, KIND, T, true><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(
                     lv->view, eg->view, sg, r, x, reinterpret_cast<T *>(eg->d_stage), omega);
@@ -933,7 +1039,7 @@ struct RunSchwarz {
             if (s != FTS_OK) return s;
         }
         if (staged) {
-            launch_gather<D, N1, T, false>(lv, reinterpret_cast<const T *>(eg->d_stage), nullptr, x, st);
+            launch_gather<D, N1, T, false>(lv, reinterpret_cast<const T *>(eg->d_stage), nullptr, x, st, cz);
             return check_launch("k_patch_gather");
         }
         return FTS_OK;

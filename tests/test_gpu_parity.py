@@ -138,6 +138,30 @@ def test_schwarz_mirror_symmetric_positions(kind, k, widths):
     assert rel(host(xg) - x, ref - x) < 1e-4
 
 
+@pytest.mark.parametrize("k,m,cz,widths", [(3, 25, 2, "random"), (4, 32, 4, "uniform"), (3, 48, 8, "random")])
+def test_staged_runs_along_z_match_colored(k, m, cz, widths):
+    """Launches with many vertex patches stage runs of cz patches along z and
+    merge the cell layer two neighbours of a run share (cz = 2, 4, 8 at these
+    sizes, which are too large for the oracle): the staged result equals the
+    colored schedule, which adds each patch to x directly, up to rounding
+    order; the same with FP32 contractions.  Both schedules are checked
+    against the oracle on small meshes above."""
+    announce("zrun", k, m, cz, widths)
+    rng = np.random.default_rng(23)
+    ws = uniform_widths(3, (m, m, m)) if widths == "uniform" else loguniform_widths(rng, 3, (m, m, m), 0.25, 4.0)
+    lv = fts.Level(3, k, ws, 1.0)
+    eg = fts.Eigs(lv, "vertex")
+    r = dev(random_vector(lv.ndofs, 2))
+    for prec, tol in (("f64", 1e-13), ("f32", 1e-6)):
+        out = {}
+        for schedule in ("staged", "colored"):
+            eg.set_schedule(schedule)
+            xa = dev(np.zeros(lv.ndofs))
+            fts.schwarz_apply(lv, eg, 0.5, r, xa, prec)
+            out[schedule] = host(xa)
+        assert rel(out["staged"], out["colored"]) < tol, prec
+
+
 def test_staged_schedule_is_deterministic():
     """Repeated staged applications give bit-identical results."""
     m = omesh(3, 3, (5, 4, 3), 19)
