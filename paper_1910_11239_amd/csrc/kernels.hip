@@ -701,16 +701,38 @@ __device__ __forceinline__ int qline_base(int a, int L) {
 }
 __device__ __forceinline__ int qline_stride(int a) { return a == 0 ? 1 : (a == 1 ? kQy : kQz); }
 
-template <int N1, bool STAGE>
+// RUN (staged only): the workgroup takes a run of up to cz patches along z
+// as k_schwarz_zrun does, and the cell layer two neighbours share stays in
+// registers: thread t owns the line with o2 flipped on every other patch, so
+// the thread that holds patch j's upper layer owns the same lines as the
+// lower layer of patch j+1.
+template <int N1, bool STAGE, bool RUN = false>
 __global__ void __launch_bounds__(256)
 k_schwarz_mfma64(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r, double *__restrict__ x,
-                 double *__restrict__ W, double omega) {
+                 double *__restrict__ W, double omega, int cz = 1) {
     constexpr int N = 2 * N1, NC1 = N1 * N1 * N1, NSC = 8;
     static_assert(N == 16, "one 16 x 16 tile per contraction");
     __shared__ double Ts[16 * kQz];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int64_t s = blockIdx.x;
-    if (!sub_in_color(sg, s)) return;  // uniform: the whole workgroup leaves before any barrier
+    int64_t s;
+    int jz0 = 0, jz1 = 1;
+    if constexpr (RUN) {
+        const int nxy = sg.cnt[0] * sg.cnt[1];
+        const int run = (int)(blockIdx.x / nxy);
+        jz0 = run * cz;
+        jz1 = min(sg.cnt[2], jz0 + cz);
+        s = blockIdx.x % nxy + (int64_t)nxy * jz0;
+    } else {
+        s = blockIdx.x;
+        if (!sub_in_color(sg, s)) return;  // uniform: the whole workgroup leaves before any barrier
+    }
+    const int64_t cs1 = g.m[0], cs2 = (int64_t)g.m[0] * g.m[1];
+    double carry[2 * N1];
+    for (int jz = jz0; jz < jz1; ++jz) {
+    if (RUN && jz > jz0) {
+        s += (int64_t)sg.cnt[0] * sg.cnt[1];
+        __syncthreads();  // every thread has read its previous line from Ts
+    }
     int pos[3];
     {
         const int j0 = (int)(s % sg.cnt[0]);
@@ -721,9 +743,9 @@ k_schwarz_mfma64(LevelView g, EigView e, SubGrid sg, const double *__restrict__ 
     }
     int tp[3];  // table positions (EigView::cls)
     for (int a = 0; a < 3; ++a) tp[a] = __builtin_amdgcn_readfirstlane(e.cls[a][pos[a]]);
-    const int64_t cs1 = g.m[0], cs2 = (int64_t)g.m[0] * g.m[1];
-    // thread t owns the patch line along x with (a1, a2) = (t % 16, t / 16)
-    const int a1 = t % N, a2 = t / N;
+    // thread t owns the patch line along x with (a1, a2) = (t % 16, t / 16),
+    // in a run with the upper and lower half along z swapped on odd patches
+    const int a1 = t % N, a2 = (t / N) ^ (RUN && ((jz - jz0) & 1) ? N1 : 0);
     const int o1 = a1 / N1, i1 = a1 % N1, o2 = a2 / N1, i2 = a2 % N1;
     const int64_t cell0 = pos[0] + (pos[1] + o1) * cs1 + (pos[2] + o2) * cs2;
     const int iofs = i1 * N1 + i2 * N1 * N1;
@@ -803,16 +825,26 @@ k_schwarz_mfma64(LevelView g, EigView e, SubGrid sg, const double *__restrict__ 
     for (int a0 = 0; a0 < N; ++a0) cv[a0] = Ts[lbase + a0];
     if constexpr (STAGE) {
         double *dst = W + s * (NSC * NC1) + (2 * o1 + 4 * o2) * NC1 + iofs;
+        if (RUN && o2 == 1 && jz + 1 < jz1) {
 #pragma unroll
-        for (int o0 = 0; o0 < 2; ++o0)
+            for (int a0 = 0; a0 < N; ++a0) carry[a0] = cv[a0];
+        } else {
+            if (RUN && o2 == 0 && jz > jz0) {
 #pragma unroll
-            for (int i0 = 0; i0 < N1; ++i0) dst[o0 * NC1 + i0] = cv[o0 * N1 + i0];
+                for (int a0 = 0; a0 < N; ++a0) cv[a0] += carry[a0];
+            }
+#pragma unroll
+            for (int o0 = 0; o0 < 2; ++o0)
+#pragma unroll
+                for (int i0 = 0; i0 < N1; ++i0) dst[o0 * NC1 + i0] = cv[o0 * N1 + i0];
+        }
     } else {
         double *dst = x + cell0 * NC1 + iofs;
 #pragma unroll
         for (int o0 = 0; o0 < 2; ++o0)
 #pragma unroll
             for (int i0 = 0; i0 < N1; ++i0) dst[o0 * NC1 + i0] += cv[o0 * N1 + i0];
+    }
     }
 }
 
@@ -1169,6 +1201,7 @@ struct RunSchwarz {
         } else {
             const bool staged = eg->schedule == FTS_SCHEDULE_STAGED;
             const int ncolor = staged ? 1 : 8;
+            int cz = 1;
             for (int color = 0; color < ncolor; ++color) {
                 SubGrid sg{};
                 sg.parity = -1;
@@ -1182,17 +1215,24 @@ struct RunSchwarz {
                 }
                 if (sg.nsub == 0) continue;
                 if (sg.nsub > INT_MAX) return fail(FTS_E_SIZE, "too many subdomains for one launch");
-                if (staged)
-                    k_schwarz_mfma64<N1, true><<<dim3((unsigned)sg.nsub), dim3(256), 0, st>>>(
-                        lv->view, eg->view, sg, r, x, eg->d_stage, omega);
-                else
+                if (staged) {
+                    // runs of cz patches along z, as long as enough workgroups remain
+                    while (cz < 8 && sg.nsub / (2 * cz) >= 6144) cz *= 2;
+                    if (cz > 1)
+                        k_schwarz_mfma64<N1, true, true>
+                            <<<dim3((unsigned)((int64_t)sg.cnt[0] * sg.cnt[1] * ((sg.cnt[2] + cz - 1) / cz))),
+                               dim3(256), 0, st>>>(lv->view, eg->view, sg, r, x, eg->d_stage, omega, cz);
+                    else
+                        k_schwarz_mfma64<N1, true><<<dim3((unsigned)sg.nsub), dim3(256), 0, st>>>(
+                            lv->view, eg->view, sg, r, x, eg->d_stage, omega);
+                } else
                     k_schwarz_mfma64<N1, false><<<dim3((unsigned)sg.nsub), dim3(256), 0, st>>>(
                         lv->view, eg->view, sg, r, x, nullptr, omega);
                 fts_status s = check_launch("k_schwarz_mfma64");
                 if (s != FTS_OK) return s;
             }
             if (staged) {
-                launch_gather<D, N1, double, false>(lv, eg->d_stage, nullptr, x, st);
+                launch_gather<D, N1, double, false>(lv, eg->d_stage, nullptr, x, st, cz);
                 return check_launch("k_patch_gather");
             }
             return FTS_OK;

@@ -138,13 +138,15 @@ def test_schwarz_mirror_symmetric_positions(kind, k, widths):
     assert rel(host(xg) - x, ref - x) < 1e-4
 
 
-@pytest.mark.parametrize("k,m,cz,widths", [(3, 25, 2, "random"), (4, 32, 4, "uniform"), (3, 48, 8, "random")])
+@pytest.mark.parametrize("k,m,cz,widths", [(3, 25, 2, "random"), (4, 32, 4, "uniform"), (3, 48, 8, "random"),
+                                           (7, 26, 2, "uniform"), (7, 34, 4, "random")])
 def test_staged_runs_along_z_match_colored(k, m, cz, widths):
     """Launches with many vertex patches stage runs of cz patches along z and
     merge the cell layer two neighbours of a run share (cz = 2, 4, 8 at these
-    sizes, which are too large for the oracle): the staged result equals the
-    colored schedule, which adds each patch to x directly, up to rounding
-    order; the same with FP32 contractions.  Both schedules are checked
+    sizes, which are too large for the oracle; k = 7 in FP64 runs on the FP64
+    MFMA kernel): the staged result equals the colored schedule, which adds
+    each patch to x directly, up to rounding order; the same with FP32
+    contractions.  Both schedules are checked
     against the oracle on small meshes above."""
     announce("zrun", k, m, cz, widths)
     rng = np.random.default_rng(23)
