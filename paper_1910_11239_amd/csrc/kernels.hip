@@ -527,10 +527,14 @@ struct Mfma16<1> {
     }
 };
 
-template <int N1, int KIND, int BF, bool STAGE>
+// RUN (staged vertex patches only): a run of up to cz patches along z per
+// workgroup as in k_schwarz_mfma64, the shared cell layer carried in
+// registers; the staged values then carry their factor F already (FP32),
+// so that two patches' values can be added, and Wsc is not written.
+template <int N1, int KIND, int BF, bool STAGE, bool RUN = false>
 __global__ void __launch_bounds__(256)
 k_schwarz_mfma(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r, double *__restrict__ x,
-               float *__restrict__ W, double *__restrict__ Wsc, double omega) {
+               float *__restrict__ W, double *__restrict__ Wsc, double omega, int cz = 1) {
     using M = Mfma16<BF>;
     constexpr int D = 3;
     constexpr int N = KIND ? 2 * N1 : N1;
@@ -538,9 +542,30 @@ k_schwarz_mfma(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r,
     constexpr int NC1 = N1 * N1 * N1, NSC = KIND ? 8 : 1;
     __shared__ float Ts[16 * kPz];
     __shared__ float wmax[4];
+    static_assert(!RUN || (KIND == 1 && STAGE), "runs along z: staged vertex patches");
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const int64_t s = blockIdx.x;
-    if (!sub_in_color(sg, s)) return;  // uniform: the whole workgroup leaves before any barrier
+    int64_t s;
+    int jz0 = 0, jz1 = 1;
+    if constexpr (RUN) {
+        const int nxy = sg.cnt[0] * sg.cnt[1];
+        const int run = (int)(blockIdx.x / nxy);
+        jz0 = run * cz;
+        jz1 = min(sg.cnt[2], jz0 + cz);
+        s = blockIdx.x % nxy + (int64_t)nxy * jz0;
+    } else {
+        s = blockIdx.x;
+        if (!sub_in_color(sg, s)) return;  // uniform: the whole workgroup leaves before any barrier
+    }
+    if (N < 16) {
+        for (int p = t; p < 16 * kPz; p += 256) Ts[p] = 0.f;  // padding stays zero through the contractions
+        __syncthreads();
+    }
+    float carry[N];
+    for (int jz = jz0; jz < jz1; ++jz) {
+    if (RUN && jz > jz0) {
+        s += (int64_t)sg.cnt[0] * sg.cnt[1];
+        __syncthreads();  // every thread has read its previous line from Ts
+    }
     int pos[3];
     {
         const int j0 = (int)(s % sg.cnt[0]);
@@ -554,14 +579,12 @@ k_schwarz_mfma(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r,
     int tp[3];  // table positions (EigView::cls)
     for (int a = 0; a < 3; ++a) tp[a] = __builtin_amdgcn_readfirstlane(e.cls[a][pos[a]]);
     const int64_t cs1 = g.m[0], cs2 = (int64_t)g.m[0] * g.m[1];
-    if (N < 16)
-        for (int p = t; p < 16 * kPz; p += 256) Ts[p] = 0.f;
-    __syncthreads();
-    // thread t < N^2 owns the patch line along x with (a1, a2) = (t % N, t / N):
-    // NO runs of k+1 contiguous residual values, all loads issued together
+    // thread t < N^2 owns the patch line along x with (a1, a2) = (t % N, t / N)
+    // (in a run, with the halves along z swapped on odd patches): NO runs of
+    // k+1 contiguous residual values, all loads issued together
     constexpr int NO = KIND ? 2 : 1;
     const bool own = t < N * N;
-    const int a1 = t % N, a2 = t / N;
+    const int a1 = t % N, a2 = (RUN && own && ((jz - jz0) & 1)) ? (t / N + N1) % N : t / N;
     const int o1 = a1 / N1, i1 = a1 % N1, o2 = a2 / N1, i2 = a2 % N1;
     const int64_t cell0 = pos[0] + (pos[1] + o1) * cs1 + (pos[2] + o2) * cs2;
     const int iofs = i1 * N1 + i2 * N1 * N1;
@@ -653,12 +676,29 @@ k_schwarz_mfma(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r,
     const double sx = e.mscale[0][tp[0]], sy = e.mscale[1][tp[1]], sz = e.mscale[2][tp[2]];
     const double lmin = (double)e.lmin[0][tp[0]] + e.lmin[1][tp[1]] + e.lmin[2][tp[2]];
     const double F = (double)rmax * omega * (sx * sy * sz) * (sx * sy * sz) / lmin;
-    if (STAGE && t == 0) Wsc[s] = F;
+    if (STAGE && !RUN && t == 0) Wsc[s] = F;
     if (own) {
         float c[N];
 #pragma unroll
         for (int a0 = 0; a0 < N; ++a0) c[a0] = Ts[lbase + a0];
-        if constexpr (STAGE) {
+        if constexpr (STAGE && RUN) {
+            float *dst = W + s * (NSC * NC1) + (2 * o1 + 4 * o2) * NC1 + iofs;  // F applied here
+#pragma unroll
+            for (int a0 = 0; a0 < N; ++a0) c[a0] = (float)(F * (double)c[a0]);
+            if (o2 == 1 && jz + 1 < jz1) {
+#pragma unroll
+                for (int a0 = 0; a0 < N; ++a0) carry[a0] = c[a0];
+            } else {
+                if (o2 == 0 && jz > jz0) {
+#pragma unroll
+                    for (int a0 = 0; a0 < N; ++a0) c[a0] += carry[a0];
+                }
+#pragma unroll
+                for (int o0 = 0; o0 < NO; ++o0)
+#pragma unroll
+                    for (int i0 = 0; i0 < N1; ++i0) dst[o0 * NC1 + i0] = c[o0 * N1 + i0];
+            }
+        } else if constexpr (STAGE) {
             float *dst = W + s * (NSC * NC1) + (2 * o1 + 4 * o2) * NC1 + iofs;  // F applied by the gather
 #pragma unroll
             for (int o0 = 0; o0 < NO; ++o0)
@@ -671,6 +711,7 @@ k_schwarz_mfma(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r,
 #pragma unroll
                 for (int i0 = 0; i0 < N1; ++i0) dst[o0 * NC1 + i0] += F * (double)c[o0 * N1 + i0];
         }
+    }
     }
 }
 
@@ -745,7 +786,7 @@ k_schwarz_mfma64(LevelView g, EigView e, SubGrid sg, const double *__restrict__ 
     for (int a = 0; a < 3; ++a) tp[a] = __builtin_amdgcn_readfirstlane(e.cls[a][pos[a]]);
     // thread t owns the patch line along x with (a1, a2) = (t % 16, t / 16),
     // in a run with the upper and lower half along z swapped on odd patches
-    const int a1 = t % N, a2 = (t / N) ^ (RUN && ((jz - jz0) & 1) ? N1 : 0);
+    const int a1 = t % N, a2 = (RUN && ((jz - jz0) & 1)) ? (t / N + N1) % N : t / N;
     const int o1 = a1 / N1, i1 = a1 % N1, o2 = a2 / N1, i2 = a2 % N1;
     const int64_t cell0 = pos[0] + (pos[1] + o1) * cs1 + (pos[2] + o2) * cs2;
     const int iofs = i1 * N1 + i2 * N1 * N1;
@@ -1084,6 +1125,7 @@ struct RunSchwarz {
         } else {
             const bool staged = KIND == 1 && eg->schedule == FTS_SCHEDULE_STAGED;
             const int ncolor = (KIND && !staged) ? 8 : 1;
+            int cz = 1;
             for (int color = 0; color < ncolor; ++color) {
                 SubGrid sg{};
                 sg.parity = -1;
@@ -1096,19 +1138,33 @@ struct RunSchwarz {
                     sg.nsub *= sg.cnt[a];
                 }
                 if (sg.nsub == 0) continue;
-                if (staged)
-                    k_schwarz_mfma<N1, KIND, BF, true><<<dim3((unsigned)sg.nsub), dim3(256), 0, st>>>(
-                        lv->view, eg->view, sg, r, x, reinterpret_cast<float *>(eg->d_stage), eg->d_stage_scale,
-                        omega);
-                else
+                if (staged) {
+                    // runs of cz patches along z, as long as enough workgroups remain
+                    while (cz < 8 && sg.nsub / (2 * cz) >= 6144) cz *= 2;
+                    if constexpr (KIND == 1) {
+                        if (cz > 1)
+                            k_schwarz_mfma<N1, KIND, BF, true, true>
+                                <<<dim3((unsigned)((int64_t)sg.cnt[0] * sg.cnt[1] * ((sg.cnt[2] + cz - 1) / cz))),
+                                   dim3(256), 0, st>>>(lv->view, eg->view, sg, r, x,
+                                                       reinterpret_cast<float *>(eg->d_stage), nullptr, omega, cz);
+                    }
+                    if (cz == 1)
+                        k_schwarz_mfma<N1, KIND, BF, true><<<dim3((unsigned)sg.nsub), dim3(256), 0, st>>>(
+                            lv->view, eg->view, sg, r, x, reinterpret_cast<float *>(eg->d_stage),
+                            eg->d_stage_scale, omega);
+                } else
                     k_schwarz_mfma<N1, KIND, BF, false><<<dim3((unsigned)sg.nsub), dim3(256), 0, st>>>(
                         lv->view, eg->view, sg, r, x, nullptr, nullptr, omega);
                 fts_status s = check_launch("k_schwarz_mfma");
                 if (s != FTS_OK) return s;
             }
             if (staged) {
-                launch_gather<D, N1, float, true>(lv, reinterpret_cast<const float *>(eg->d_stage),
-                                                  eg->d_stage_scale, x, st);
+                if (cz > 1)  // the run kernel stores the values with their factor applied
+                    launch_gather<D, N1, float, false>(lv, reinterpret_cast<const float *>(eg->d_stage), nullptr,
+                                                       x, st, cz);
+                else
+                    launch_gather<D, N1, float, true>(lv, reinterpret_cast<const float *>(eg->d_stage),
+                                                      eg->d_stage_scale, x, st);
                 return check_launch("k_patch_gather");
             }
             return FTS_OK;

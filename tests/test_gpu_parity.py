@@ -145,8 +145,9 @@ def test_staged_runs_along_z_match_colored(k, m, cz, widths):
     merge the cell layer two neighbours of a run share (cz = 2, 4, 8 at these
     sizes, which are too large for the oracle; k = 7 in FP64 runs on the FP64
     MFMA kernel): the staged result equals the colored schedule, which adds
-    each patch to x directly, up to rounding order; the same with FP32
-    contractions.  Both schedules are checked
+    each patch to x directly, up to rounding order; the same with FP32 and
+    16-bit MFMA contractions (whose run kernel stores the values with their
+    scale factor applied).  Both schedules are checked
     against the oracle on small meshes above."""
     announce("zrun", k, m, cz, widths)
     rng = np.random.default_rng(23)
@@ -154,7 +155,7 @@ def test_staged_runs_along_z_match_colored(k, m, cz, widths):
     lv = fts.Level(3, k, ws, 1.0)
     eg = fts.Eigs(lv, "vertex")
     r = dev(random_vector(lv.ndofs, 2))
-    for prec, tol in (("f64", 1e-13), ("f32", 1e-6)):
+    for prec, tol in (("f64", 1e-13), ("f32", 1e-6), ("f16", 1e-6), ("bf16", 1e-6)):
         out = {}
         for schedule in ("staged", "colored"):
             eg.set_schedule(schedule)
