@@ -252,14 +252,14 @@ fts_status fts_batch_destroy(fts_batch *bt) {
     if (!bt) return FTS_OK;
     for (auto *e : bt->eigs) fts_eigs_destroy(e);
     for (auto *l : bt->levels) fts_level_destroy(l);
-    if (bt->d_meshes) hipFree(bt->d_meshes);
-    if (bt->d_prefix) hipFree(bt->d_prefix);
-    if (bt->d_order) hipFree(bt->d_order);
-    if (bt->d_counter) hipFree(bt->d_counter);
-    if (bt->d_stage) hipFree(bt->d_stage);
+    if (bt->d_meshes) (void)hipFree(bt->d_meshes);
+    if (bt->d_prefix) (void)hipFree(bt->d_prefix);
+    if (bt->d_order) (void)hipFree(bt->d_order);
+    if (bt->d_counter) (void)hipFree(bt->d_counter);
+    if (bt->d_stage) (void)hipFree(bt->d_stage);
     for (auto &g : bt->res_groups)
-        if (g.blocks) hipFree(g.blocks);
-    if (bt->d_gather) hipFree(bt->d_gather);
+        if (g.blocks) (void)hipFree(g.blocks);
+    if (bt->d_gather) (void)hipFree(bt->d_gather);
     delete bt;
     return FTS_OK;
 }
@@ -447,14 +447,14 @@ fts_status fts_batch_autotune(fts_batch *bt, fts_prec prec, const double *r, voi
                 const int grid = mult * bt->ncu;
                 st = batch_launch_smooth(bt, th, grid, ch, prec, r, 0.1, s);  // warm-up
                 if (st != FTS_OK) break;
-                hipEventRecord(e0, s);
+                if (hipEventRecord(e0, s) != hipSuccess) st = fail(FTS_E_HIP, "autotune timing failed");
                 for (int rep_i = 0; rep_i < 2 && st == FTS_OK; ++rep_i)
                     st = batch_launch_smooth(bt, th, grid, ch, prec, r, 0.1, s);
-                hipEventRecord(e1, s);
-                if (hipEventSynchronize(e1) != hipSuccess) st = fail(FTS_E_HIP, "autotune timing failed");
-                if (st != FTS_OK) break;
                 float ms = 0.f;
-                hipEventElapsedTime(&ms, e0, e1);
+                if (st == FTS_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                     hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                    st = fail(FTS_E_HIP, "autotune timing failed");
+                if (st != FTS_OK) break;
                 ms *= 0.5f;
                 char line[128];
                 std::snprintf(line, sizeof line, "threads=%d grid=%d chunk=%d: %.3f ms\n", th, grid, ch, ms);
@@ -470,8 +470,8 @@ fts_status fts_batch_autotune(fts_batch *bt, fts_prec prec, const double *r, voi
         }
         if (st != FTS_OK) break;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (st != FTS_OK) return st;
     bt->threads = bt_th;
     bt->grid = bt_gr;

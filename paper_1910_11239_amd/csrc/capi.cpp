@@ -120,19 +120,19 @@ fts_status fts_hierarchy_destroy(fts_hierarchy *h) {
     if (!h) return FTS_OK;
     for (auto *e : h->eigs) fts_eigs_destroy(e);
     for (auto *l : h->levels) fts_level_destroy(l);
-    for (auto *p : h->vb) if (p) hipFree(p);
-    for (auto *p : h->vx) if (p) hipFree(p);
-    for (auto *p : h->vr) if (p) hipFree(p);
+    for (auto *p : h->vb) if (p) (void)hipFree(p);
+    for (auto *p : h->vx) if (p) (void)hipFree(p);
+    for (auto *p : h->vr) if (p) (void)hipFree(p);
     coarse_destroy(h->coarse);
-    if (h->host_scalars) hipHostFree(h->host_scalars);
+    if (h->host_scalars) (void)hipHostFree(h->host_scalars);
     for (auto &v : h->xs)
-        for (auto *p : v) if (p) hipFree(p);
+        for (auto *p : v) if (p) (void)hipFree(p);
     for (auto *vv : {&h->lam, &h->lamb, &h->aq, &h->atr, &h->at})
-        for (auto *p : *vv) if (p) hipFree(p);
-    if (h->apart) hipFree(h->apart);
-    if (h->ared) hipFree(h->ared);
-    if (h->agrad) hipFree(h->agrad);
-    if (h->host_grad) hipHostFree(h->host_grad);
+        for (auto *p : *vv) if (p) (void)hipFree(p);
+    if (h->apart) (void)hipFree(h->apart);
+    if (h->ared) (void)hipFree(h->ared);
+    if (h->agrad) (void)hipFree(h->agrad);
+    if (h->host_grad) (void)hipHostFree(h->host_grad);
     delete h;
     return FTS_OK;
 }

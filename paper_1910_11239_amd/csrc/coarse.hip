@@ -377,7 +377,7 @@ static fts_status factor_slabs(rocblas_handle h, CoarseLU *c, double *X, hipStre
 void coarse_destroy(CoarseLU *c) {
     if (!c) return;
     for (void *p : {(void *)c->D, (void *)c->Lo, (void *)c->Up, (void *)c->y, (void *)c->t})
-        if (p) hipFree(p);
+        if (p) (void)hipFree(p);
     delete c;
 }
 
@@ -415,7 +415,7 @@ fts_status coarse_create(const fts_level *l0, hipStream_t stream, CoarseLU **out
     if (st == FTS_OK) st = factor_slabs(h, c, X, stream);
     if (hipStreamSynchronize(stream) != hipSuccess && st == FTS_OK) st = fail(FTS_E_HIP, "coarse factorisation failed");
     if (h) rocblas_destroy_handle(h);
-    if (X) hipFree(X);
+    if (X) (void)hipFree(X);
     if (st != FTS_OK) {
         coarse_destroy(c);
         return st;

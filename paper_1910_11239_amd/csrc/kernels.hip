@@ -536,7 +536,6 @@ __global__ void __launch_bounds__(256)
 k_schwarz_mfma(LevelView g, EigView e, SubGrid sg, const double *__restrict__ r, double *__restrict__ x,
                float *__restrict__ W, double *__restrict__ Wsc, double omega, int cz = 1) {
     using M = Mfma16<BF>;
-    constexpr int D = 3;
     constexpr int N = KIND ? 2 * N1 : N1;
     static_assert(N <= 16, "MFMA path needs n <= 16");
     constexpr int NC1 = N1 * N1 * N1, NSC = KIND ? 8 : 1;

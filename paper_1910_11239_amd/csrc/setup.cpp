@@ -432,7 +432,7 @@ fts_status fts_level_create(const fts_mesh_desc *mesh, fts_level **out) {
     lv->view.pk = lv->k * (lv->k + 1.0);
     lv->view.ncells = lv->ncells;
     if (hipMemcpy(lv->d_tab, host.data(), total * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
-        hipFree(lv->d_tab);
+        (void)hipFree(lv->d_tab);
         delete lv;
         return fail(FTS_E_HIP, "upload of level tables failed");
     }
@@ -442,7 +442,7 @@ fts_status fts_level_create(const fts_mesh_desc *mesh, fts_level **out) {
 
 fts_status fts_level_destroy(fts_level *level) {
     if (!level) return FTS_OK;
-    if (level->d_tab) hipFree(level->d_tab);
+    if (level->d_tab) (void)hipFree(level->d_tab);
     delete level;
     return FTS_OK;
 }
@@ -633,7 +633,7 @@ fts_status setup_eigs_internal(const fts_level *lv, fts_patch_kind kind, bool st
     }
     if (hipMalloc(&eg->d_tab, std::max<size_t>(total, 1) * sizeof(double)) != hipSuccess ||
         hipMalloc(&eg->d_tab32, std::max<size_t>(total, 1) * sizeof(float)) != hipSuccess) {
-        if (eg->d_tab) hipFree(eg->d_tab);
+        if (eg->d_tab) (void)hipFree(eg->d_tab);
         delete eg;
         return fail(FTS_E_HIP, "hipMalloc of eigen tables failed");
     }
@@ -659,8 +659,8 @@ fts_status setup_eigs_internal(const fts_level *lv, fts_patch_kind kind, bool st
     for (size_t i = 0; i < total; ++i) host32[i] = (float)host[i];
     if (total && (hipMemcpy(eg->d_tab, host.data(), total * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
                   hipMemcpy(eg->d_tab32, host32.data(), total * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)) {
-        hipFree(eg->d_tab);
-        hipFree(eg->d_tab32);
+        (void)hipFree(eg->d_tab);
+        (void)hipFree(eg->d_tab32);
         delete eg;
         return fail(FTS_E_HIP, "upload of eigen tables failed");
     }
@@ -671,9 +671,9 @@ fts_status setup_eigs_internal(const fts_level *lv, fts_patch_kind kind, bool st
         if (hipMalloc(&eg->d_cls, std::max<size_t>(hc.size(), 1) * sizeof(int)) != hipSuccess ||
             (!hc.empty() &&
              hipMemcpy(eg->d_cls, hc.data(), hc.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)) {
-            if (eg->d_cls) hipFree(eg->d_cls);
-            hipFree(eg->d_tab);
-            hipFree(eg->d_tab32);
+            if (eg->d_cls) (void)hipFree(eg->d_cls);
+            (void)hipFree(eg->d_tab);
+            (void)hipFree(eg->d_tab32);
             delete eg;
             return fail(FTS_E_HIP, "upload of the table classes failed");
         }
@@ -697,9 +697,9 @@ fts_status setup_eigs_internal(const fts_level *lv, fts_patch_kind kind, bool st
         uint16_t *m16 = reinterpret_cast<uint16_t *>(host16.data());
         float *f32 = reinterpret_cast<float *>(host16.data() + mats);
         if (hipMalloc(&eg->d_mfma, host16.size()) != hipSuccess) {
-            hipFree(eg->d_tab);
-            hipFree(eg->d_tab32);
-            hipFree(eg->d_cls);
+            (void)hipFree(eg->d_tab);
+            (void)hipFree(eg->d_tab32);
+            (void)hipFree(eg->d_cls);
             delete eg;
             return fail(FTS_E_HIP, "hipMalloc of the MFMA tables failed");
         }
@@ -749,10 +749,10 @@ fts_status setup_eigs_internal(const fts_level *lv, fts_patch_kind kind, bool st
             fo += (size_t)cnt * 2;
         }
         if (hipMemcpy(eg->d_mfma, host16.data(), host16.size(), hipMemcpyHostToDevice) != hipSuccess) {
-            hipFree(eg->d_tab);
-            hipFree(eg->d_tab32);
-            hipFree(eg->d_mfma);
-            hipFree(eg->d_cls);
+            (void)hipFree(eg->d_tab);
+            (void)hipFree(eg->d_tab32);
+            (void)hipFree(eg->d_mfma);
+            (void)hipFree(eg->d_cls);
             delete eg;
             return fail(FTS_E_HIP, "upload of the MFMA tables failed");
         }
@@ -763,11 +763,11 @@ fts_status setup_eigs_internal(const fts_level *lv, fts_patch_kind kind, bool st
         const size_t bytes = (size_t)nsub * (1u << lv->dim) * (lv->ndofs / lv->ncells) * sizeof(double);
         if (hipMalloc(&eg->d_stage, std::max<size_t>(bytes, 8)) != hipSuccess ||
             hipMalloc(&eg->d_stage_scale, (size_t)std::max<int64_t>(nsub, 1) * sizeof(double)) != hipSuccess) {
-            if (eg->d_stage) hipFree(eg->d_stage);
-            hipFree(eg->d_tab);
-            hipFree(eg->d_tab32);
-            if (eg->d_mfma) hipFree(eg->d_mfma);
-            hipFree(eg->d_cls);
+            if (eg->d_stage) (void)hipFree(eg->d_stage);
+            (void)hipFree(eg->d_tab);
+            (void)hipFree(eg->d_tab32);
+            if (eg->d_mfma) (void)hipFree(eg->d_mfma);
+            (void)hipFree(eg->d_cls);
             delete eg;
             return fail(FTS_E_HIP, "hipMalloc of the patch staging buffer failed");
         }
@@ -796,12 +796,12 @@ fts_status fts_eigs_set_schedule(fts_eigs *eigs, int32_t schedule) {
 
 fts_status fts_eigs_destroy(fts_eigs *eigs) {
     if (!eigs) return FTS_OK;
-    if (eigs->d_tab) hipFree(eigs->d_tab);
-    if (eigs->d_tab32) hipFree(eigs->d_tab32);
-    if (eigs->d_stage) hipFree(eigs->d_stage);
-    if (eigs->d_stage_scale) hipFree(eigs->d_stage_scale);
-    if (eigs->d_mfma) hipFree(eigs->d_mfma);
-    if (eigs->d_cls) hipFree(eigs->d_cls);
+    if (eigs->d_tab) (void)hipFree(eigs->d_tab);
+    if (eigs->d_tab32) (void)hipFree(eigs->d_tab32);
+    if (eigs->d_stage) (void)hipFree(eigs->d_stage);
+    if (eigs->d_stage_scale) (void)hipFree(eigs->d_stage_scale);
+    if (eigs->d_mfma) (void)hipFree(eigs->d_mfma);
+    if (eigs->d_cls) (void)hipFree(eigs->d_cls);
     delete eigs;
     return FTS_OK;
 }
