@@ -146,9 +146,10 @@ __device__ __forceinline__ void matvec_regs(const T *in, T *out, P Mat) {
 // N even, row-major [i][m]) has its N/2 even columns first (S[N-1-i][m] =
 // S[i][m]) and its N/2 odd ones last (S[N-1-i][m] = -S[i][m]), so only the
 // rows i < N/2 are read and each product costs half the FMAs.
-// out = S^T in:
+// out = S^T in, with ST = S^T (row-major [m][i]: each output reads N/2
+// contiguous coefficients, so few scalar registers are live at a time):
 template <int N, typename T, typename P>
-__device__ __forceinline__ void eo_fwd(const T *in, T *out, P S) {
+__device__ __forceinline__ void eo_fwd(const T *in, T *out, P ST) {
     constexpr int H = N / 2;
     T ue[H], uo[H];
 #pragma unroll
@@ -161,8 +162,8 @@ __device__ __forceinline__ void eo_fwd(const T *in, T *out, P S) {
         T se = 0, so = 0;
 #pragma unroll
         for (int i = 0; i < H; ++i) {
-            se = fma((T)S[i * N + m], ue[i], se);
-            so = fma((T)S[i * N + H + m], uo[i], so);
+            se = fma((T)ST[m * N + i], ue[i], se);
+            so = fma((T)ST[(H + m) * N + i], uo[i], so);
         }
         out[m] = se;
         out[H + m] = so;

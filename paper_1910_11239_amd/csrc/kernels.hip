@@ -195,7 +195,7 @@ __device__ __forceinline__ void lines3_solve(const double *__restrict__ src, boo
                                              T om, T *Ts, T *w) {
     constexpr int nn = N * N;
     auto fwd = [&](const T *in, T *out, int a) {
-        if constexpr (EO) eo_fwd<N>(in, out, pt.S[a]);
+        if constexpr (EO) eo_fwd<N>(in, out, pt.ST[a]);
         else matvec_regs<N>(in, out, pt.ST[a]);
     };
     auto bwd = [&](const T *in, T *out, int a) {
