@@ -103,7 +103,12 @@ int64_t fts_level_ndofs(const fts_level *level);
  * widths) and solves A S = M S diag(lambda) with S^T M S = I (eq.
  * generalizedEVP) in FP64 on the host (Cholesky + cyclic Jacobi), then
  * uploads S (n x n, row-major, column m = eigenvector m) and lambda (n) per
- * (axis, position), n = k+1 for cells and 2(k+1) for patches.  Vertex
+ * (axis, position), n = k+1 for cells and 2(k+1) for patches.  Positions
+ * with bit-identical widths around them share one uploaded table; at a
+ * position whose 1-D problem is mirror symmetric (n even) the uploaded modes
+ * are reordered, even eigenvectors first, and made exactly even or odd (the
+ * local solve is the same operator; fts_eigs_get returns the solver's own
+ * order).  Vertex
  * patches need at least 2 cells per axis.  FTS_E_NOT_SPD if M or A is not
  * positive definite (e.g. too small a penalty).  *out receives the handle,
  * valid while the level lives. */

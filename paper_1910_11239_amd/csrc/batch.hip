@@ -40,11 +40,14 @@ struct BatchBlock {
 };
 
 constexpr int kBatchMaxN = 20;  // vertex patch of degree 9
+// lines per thread and pass of the contractions (measured: 2 beats 1, 3, 4, 6)
+constexpr int kBatchLines = 2;
 
 template <int N1, int TH, typename T>
 __device__ __forceinline__ void batch_patch(const BatchMesh &M, int64_t p, const double *__restrict__ r,
                                             T *__restrict__ W, T om, T *Ts) {
     constexpr int D = 3, N = 2 * N1, NC1 = N1 * N1 * N1, NSC = 8, LINES = N * N, NN = N * N;
+    constexpr int BL = kBatchLines;
     const int t = threadIdx.x;
     int pos[3];
     pos[0] = __builtin_amdgcn_readfirstlane((int)(p % M.cnt[0]));
@@ -61,11 +64,13 @@ __device__ __forceinline__ void batch_patch(const BatchMesh &M, int64_t p, const
     }
     __syncthreads();
     const EigView &e = M.ev;
-    for (int l = t; l < LINES; l += TH)
-        contract_line<D, N, T>(Ts, 0, l, uniform_table(EigTab<T>::ST(e, 0) + (size_t)pos[0] * NN));
+    // BL lines per thread and pass (contract_lines): the 1-D matrices of the
+    // larger degrees do not fit in scalar registers
+    for (int l = t; l < LINES; l += BL * TH)
+        contract_lines<D, N, BL, T>(Ts, 0, l, TH, LINES, uniform_table(EigTab<T>::ST(e, 0) + (size_t)pos[0] * NN));
     __syncthreads();
-    for (int l = t; l < LINES; l += TH)
-        contract_line<D, N, T>(Ts, 1, l, uniform_table(EigTab<T>::ST(e, 1) + (size_t)pos[1] * NN));
+    for (int l = t; l < LINES; l += BL * TH)
+        contract_lines<D, N, BL, T>(Ts, 1, l, TH, LINES, uniform_table(EigTab<T>::ST(e, 1) + (size_t)pos[1] * NN));
     __syncthreads();
     {
         cptr<T> L0 = uniform_table(EigTab<T>::L(e, 0) + (size_t)pos[0] * N);
@@ -73,17 +78,22 @@ __device__ __forceinline__ void batch_patch(const BatchMesh &M, int64_t p, const
         cptr<T> ST2 = uniform_table(EigTab<T>::ST(e, 2) + (size_t)pos[2] * NN);
         cptr<T> S2 = uniform_table(EigTab<T>::S(e, 2) + (size_t)pos[2] * NN);
         cptr<T> L2 = uniform_table(EigTab<T>::L(e, 2) + (size_t)pos[2] * N);
-        for (int l = t; l < LINES; l += TH) {
-            const T lr = (T)L0[l % N] + (T)L1[l / N];
-            last_axis_solve<D, N, T>(Ts, l, ST2, S2, L2, lr, om);
+        for (int l = t; l < LINES; l += BL * TH) {
+            T lr[BL];
+#pragma unroll
+            for (int k = 0; k < BL; ++k) {
+                const int lk = l + k * TH < LINES ? l + k * TH : l;
+                lr[k] = (T)L0[lk % N] + (T)L1[lk / N];
+            }
+            last_axis_solves<D, N, BL, T>(Ts, l, TH, LINES, ST2, S2, L2, lr, om);
         }
     }
     __syncthreads();
-    for (int l = t; l < LINES; l += TH)
-        contract_line<D, N, T>(Ts, 1, l, uniform_table(EigTab<T>::S(e, 1) + (size_t)pos[1] * NN));
+    for (int l = t; l < LINES; l += BL * TH)
+        contract_lines<D, N, BL, T>(Ts, 1, l, TH, LINES, uniform_table(EigTab<T>::S(e, 1) + (size_t)pos[1] * NN));
     __syncthreads();
-    for (int l = t; l < LINES; l += TH)
-        contract_line<D, N, T>(Ts, 0, l, uniform_table(EigTab<T>::S(e, 0) + (size_t)pos[0] * NN));
+    for (int l = t; l < LINES; l += BL * TH)
+        contract_lines<D, N, BL, T>(Ts, 0, l, TH, LINES, uniform_table(EigTab<T>::S(e, 0) + (size_t)pos[0] * NN));
     __syncthreads();
     T *Wm = W + M.stage_off + p * (NSC * NC1);
     for (int q = t; q < NSC * NC1; q += TH) {
