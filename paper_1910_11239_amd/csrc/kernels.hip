@@ -892,90 +892,111 @@ k_schwarz_mfma64(LevelView g, EigView e, SubGrid sg, const double *__restrict__ 
 // Transfers (Sec. 2.2).  Child c of a coarse cell sits at offset o in
 // {0,1}^d; its coefficients are (E_{o_d} x..x E_{o_1}) applied to the coarse
 // coefficients, E_o[i][j] = phi_j((xi_i + o)/2).  Restriction applies the
-// transposes and sums over the 2^d children.
+// transposes and sums over the 2^d children.  All 2^d children at once:
+// with the stacked 1-D matrix Es = [E_0; E_1] (2 n1 x n1, the level table E)
+// the children of a cell form one (2 n1)^d tensor, Es x..x Es times the
+// coarse coefficients, so prolongation is d contractions that each double
+// one axis (n1 -> 2 n1) and restriction d transposed contractions that
+// halve one, one workgroup per coarse cell and one thread per line.
 template <int D, int N1>
 struct XferCfg {
+    static constexpr int N2 = 2 * N1;
     static constexpr int NC = ipow(N1, D);
-    static constexpr int LINES = ipow(N1, D - 1);
-    static constexpr int THREADS = LINES <= 64 ? 64 : rup64(LINES);
-    static constexpr int PPB = THREADS / LINES;
+    static constexpr int NT = ipow(N2, D);
+    static constexpr int MAXL = ipow(N2, D - 1);  // lines of the widest stage
+    static constexpr int THREADS = MAXL <= 64 ? 64 : rup64(MAXL);
 };
 
-template <int D, int N1, bool TRANS>
-__device__ __forceinline__ void embed_line(double *Tq, int a, int l, const double *E) {
-    const int base = line_base<D, N1>(a, l), st = line_stride<N1>(a);
-    double in[N1], out[N1];
-#pragma unroll
-    for (int i = 0; i < N1; ++i) in[i] = Tq[base + i * st];
-#pragma unroll
-    for (int o = 0; o < N1; ++o) {
-        double s = 0.0;
-#pragma unroll
-        for (int i = 0; i < N1; ++i) s = fma(TRANS ? E[i * N1 + o] : E[o * N1 + i], in[i], s);
-        out[o] = s;
+// Stage a works along axis a of the (2 n1)^d tensor (strides 1, 2 n1,
+// (2 n1)^2) while the axes below a have extent 2 n1 and those above n1:
+// N2^a N1^(d-1-a) lines; line l's first element.
+template <int D, int N1>
+__device__ __forceinline__ int xfer_line_base(int a, int l) {
+    constexpr int N2 = 2 * N1;
+    if constexpr (D == 2) {
+        return a == 0 ? l * N2 : l;
+    } else {
+        if (a == 0) return (l % N1) * N2 + (l / N1) * N2 * N2;
+        if (a == 1) return (l % N2) + (l / N2) * N2 * N2;
+        return (l % N2) + (l / N2) * N2;
     }
-#pragma unroll
-    for (int o = 0; o < N1; ++o) Tq[base + o * st] = out[o];
+}
+template <int D, int N1>
+__device__ __forceinline__ int xfer_lines(int a) {
+    return ipow(2 * N1, a) * ipow(N1, D - 1 - a);
 }
 
 template <int D, int N1, bool RESTRICT>
 __global__ void __launch_bounds__((XferCfg<D, N1>::THREADS))
 k_transfer(LevelView gc, LevelView gf, const double *__restrict__ src, double *__restrict__ dst) {
     using C = XferCfg<D, N1>;
-    constexpr int NC = C::NC, LINES = C::LINES, PPB = C::PPB, TH = C::THREADS;
-    __shared__ double Tw[PPB * NC];
-    __shared__ double Acc[PPB * NC];
-    const int t = threadIdx.x, q = t / LINES, l = t % LINES;
-    const int64_t c0 = (int64_t)blockIdx.x * PPB;
+    constexpr int N2 = C::N2, NC = C::NC, NT = C::NT, TH = C::THREADS;
+    __shared__ double T[NT];
+    const int t = threadIdx.x;
+    const int64_t cc = blockIdx.x;
+    int c[3];
+    cell_coords(cc, gc.m, c);
     const int64_t fs1 = gf.m[0], fs2 = (int64_t)gf.m[0] * gf.m[1];
-    auto child_cell = [&](int64_t cc, int ch) {
-        int c[3];
-        cell_coords(cc, gc.m, c);
-        return (int64_t)(2 * c[0] + (ch & 1)) + (2 * c[1] + ((ch >> 1) & 1)) * fs1 +
-               (D == 3 ? (int64_t)(2 * c[2] + ((ch >> 2) & 1)) * fs2 : 0);
+    const cptr<double> Es = uniform_table(gc.E);  // [2 n1][n1]
+    // global index of element p of the children's tensor
+    auto fine_index = [&](int p) {
+        const int f0 = p % N2, f1 = (p / N2) % N2, f2 = D == 3 ? p / (N2 * N2) : 0;
+        const int64_t cell = (2 * c[0] + f0 / N1) + (2 * c[1] + f1 / N1) * fs1 +
+                             (D == 3 ? (int64_t)(2 * c[2] + f2 / N1) * fs2 : 0);
+        return cell * NC + (f0 % N1) + N1 * (f1 % N1) + (D == 3 ? N1 * N1 * (f2 % N1) : 0);
+    };
+    // the coarse cell's coefficients sit in the corner [0, n1)^d of the tensor
+    auto corner = [&](int p) {
+        const int i0 = p % N1, i1 = (p / N1) % N1, i2 = D == 3 ? p / (N1 * N1) : 0;
+        return i0 + N2 * i1 + N2 * N2 * i2;
     };
     if constexpr (!RESTRICT) {
-        for (int p = t; p < PPB * NC; p += TH) {
-            const int64_t cc = c0 + p / NC;
-            Acc[p] = cc < gc.ncells ? src[cc * NC + p % NC] : 0.0;
-        }
-    } else {
-        for (int p = t; p < PPB * NC; p += TH) Acc[p] = 0.0;
-    }
-    __syncthreads();
-    const bool act = q < PPB && (c0 + q) < gc.ncells;
-    for (int ch = 0; ch < (1 << D); ++ch) {
-        if constexpr (RESTRICT) {
-            for (int p = t; p < PPB * NC; p += TH) {
-                const int64_t cc = c0 + p / NC;
-                Tw[p] = cc < gc.ncells ? src[child_cell(cc, ch) * NC + p % NC] : 0.0;
-            }
-        } else {
-            for (int p = t; p < PPB * NC; p += TH) Tw[p] = Acc[p];
-        }
+        for (int p = t; p < NC; p += TH) T[corner(p)] = src[cc * NC + p];
         __syncthreads();
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            if (act) embed_line<D, N1, RESTRICT>(Tw + q * NC, a, l, gc.E + ((ch >> a) & 1) * N1 * N1);
+            const int st = a == 0 ? 1 : (a == 1 ? N2 : N2 * N2);
+            for (int l = t; l < xfer_lines<D, N1>(a); l += TH) {
+                const int base = xfer_line_base<D, N1>(a, l);
+                double in[N1];
+#pragma unroll
+                for (int i = 0; i < N1; ++i) in[i] = T[base + i * st];
+#pragma unroll
+                for (int o = 0; o < N2; ++o) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int i = 0; i < N1; ++i) s = fma((double)Es[o * N1 + i], in[i], s);
+                    T[base + o * st] = s;
+                }
+            }
             __syncthreads();
         }
-        for (int p = t; p < PPB * NC; p += TH) {
-            const int64_t cc = c0 + p / NC;
-            if (cc >= gc.ncells) continue;
-            if constexpr (RESTRICT) {
-                Acc[p] += Tw[p];
-            } else {
-                const int64_t gi = child_cell(cc, ch) * NC + p % NC;
-                dst[gi] += Tw[p];
-            }
+        for (int p = t; p < NT; p += TH) {
+            const int64_t gi = fine_index(p);
+            dst[gi] += T[p];
         }
+    } else {
+        for (int p = t; p < NT; p += TH) T[p] = src[fine_index(p)];
         __syncthreads();
-    }
-    if constexpr (RESTRICT) {
-        for (int p = t; p < PPB * NC; p += TH) {
-            const int64_t cc = c0 + p / NC;
-            if (cc < gc.ncells) dst[cc * NC + p % NC] = Acc[p];
+#pragma unroll
+        for (int a = D - 1; a >= 0; --a) {
+            const int st = a == 0 ? 1 : (a == 1 ? N2 : N2 * N2);
+            for (int l = t; l < xfer_lines<D, N1>(a); l += TH) {
+                const int base = xfer_line_base<D, N1>(a, l);
+                double in[N2];
+#pragma unroll
+                for (int o = 0; o < N2; ++o) in[o] = T[base + o * st];
+#pragma unroll
+                for (int i = 0; i < N1; ++i) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int o = 0; o < N2; ++o) s = fma((double)Es[o * N1 + i], in[o], s);
+                    T[base + i * st] = s;
+                }
+            }
+            __syncthreads();
         }
+        for (int p = t; p < NC; p += TH) dst[cc * NC + p] = T[corner(p)];
     }
 }
 
@@ -1341,8 +1362,9 @@ struct RunTransfer {
     static fts_status run(const fts_level *c, const fts_level *f, const double *src, double *dst, bool restrict_,
                           hipStream_t st) {
         using C = XferCfg<D, N1>;
-        const int64_t blocks = (c->ncells + C::PPB - 1) / C::PPB;
+        const int64_t blocks = c->ncells;
         if (blocks == 0) return FTS_OK;
+        if (blocks > INT_MAX) return fail(FTS_E_SIZE, "too many cells for one launch");
         if (restrict_)
             k_transfer<D, N1, true><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(c->view, f->view, src, dst);
         else
