@@ -232,7 +232,10 @@ fts_status fts_coarse_solve(fts_hierarchy *h, const double *b0, double *x0, void
 
 // One smoothing step on level l: Alg. addsmoother (one residual, all local
 // solves) or Alg. multsmoother (a residual before each color).
-static fts_status smooth_step(fts_hierarchy *h, int l, fts_prec prec, const double *b, double *x, hipStream_t s) {
+// One smoothing step x <- S(x, b).  x_zero: x is known to be zero on entry,
+// so the first residual is b itself (A 0 = 0) and is not computed.
+static fts_status smooth_step(fts_hierarchy *h, int l, fts_prec prec, const double *b, double *x, hipStream_t s,
+                              bool x_zero = false) {
     const fts_level *lv = h->levels[l];
     const fts_eigs *eg = h->eigs[l];
     double *r = h->vr[l];
@@ -240,26 +243,30 @@ static fts_status smooth_step(fts_hierarchy *h, int l, fts_prec prec, const doub
     if (h->smoother == FTS_SMOOTHER_MULTIPLICATIVE) {
         const int nc = schwarz_mult_colors(eg);
         for (int c = 0; c < nc && st == FTS_OK; ++c) {
-            st = launch_operator(lv, x, b, r, true, s);
-            if (st == FTS_OK) st = launch_schwarz_color(lv, eg, h->omega[l], prec, r, x, c, s);
+            const bool first = x_zero && c == 0;
+            if (!first) st = launch_operator(lv, x, b, r, true, s);
+            if (st == FTS_OK) st = launch_schwarz_color(lv, eg, h->omega[l], prec, first ? b : r, x, c, s);
         }
         return st;
     }
-    st = launch_operator(lv, x, b, r, true, s);
-    if (st == FTS_OK) st = launch_schwarz(lv, eg, h->omega[l], prec, r, x, s);
+    if (!x_zero) st = launch_operator(lv, x, b, r, true, s);
+    if (st == FTS_OK) st = launch_schwarz(lv, eg, h->omega[l], prec, x_zero ? b : r, x, s);
     return st;
 }
 
-static fts_status vcycle_level(fts_hierarchy *h, int l, fts_prec prec, const double *b, double *x, hipStream_t s) {
+// x <- MG_l(x, b) (Alg. gmg).  x_zero: x is zero on entry (the coarser
+// levels of a V-cycle, and the preconditioner calls of PCG and GMRES).
+static fts_status vcycle_level(fts_hierarchy *h, int l, fts_prec prec, const double *b, double *x, hipStream_t s,
+                               bool x_zero = false) {
     if (l == 0) return coarse_solve(h->coarse, b, x, s);
     const fts_level *lv = h->levels[l];
     double *r = h->vr[l];
     fts_status st = FTS_OK;
-    for (int i = 0; i < h->m_pre && st == FTS_OK; ++i) st = smooth_step(h, l, prec, b, x, s);
+    for (int i = 0; i < h->m_pre && st == FTS_OK; ++i) st = smooth_step(h, l, prec, b, x, s, x_zero && i == 0);
     if (st == FTS_OK) st = launch_operator(lv, x, b, r, true, s);
     if (st == FTS_OK) st = launch_restrict(h->levels[l - 1], lv, r, h->vb[l - 1], s);
     if (st == FTS_OK && l - 1 > 0) st = launch_fill(h->vx[l - 1], h->levels[l - 1]->ndofs, 0.0, s);
-    if (st == FTS_OK) st = vcycle_level(h, l - 1, prec, h->vb[l - 1], h->vx[l - 1], s);
+    if (st == FTS_OK) st = vcycle_level(h, l - 1, prec, h->vb[l - 1], h->vx[l - 1], s, true);
     if (st == FTS_OK) st = launch_prolongate(h->levels[l - 1], lv, h->vx[l - 1], x, s);
     for (int i = 0; i < h->m_post && st == FTS_OK; ++i) st = smooth_step(h, l, prec, b, x, s);
     return st;
@@ -306,7 +313,7 @@ fts_status fts_pcg(fts_hierarchy *h, fts_prec prec, const double *b, double *x, 
     int it = 0;
     if (rel > rtol && maxit > 0) {
         FTS_TRY(launch_fill(z, N, 0.0, s));
-        FTS_TRY(vcycle_level(h, h->nlevels - 1, prec, r, z, s));
+        FTS_TRY(vcycle_level(h, h->nlevels - 1, prec, r, z, s, true));
         FTS_HIP_CHECK(hipMemcpyAsync(p, z, N * sizeof(double), hipMemcpyDeviceToDevice, s));
         FTS_TRY(launch_dot2(r, z, nullptr, N, part, dout, s));
         FTS_TRY(readback(h, dout, s, v));
@@ -325,7 +332,7 @@ fts_status fts_pcg(fts_hierarchy *h, fts_prec prec, const double *b, double *x, 
             if (!(rel > rtol)) break;
             std::swap(z, zo);
             FTS_TRY(launch_fill(z, N, 0.0, s));
-            FTS_TRY(vcycle_level(h, h->nlevels - 1, prec, r, z, s));
+            FTS_TRY(vcycle_level(h, h->nlevels - 1, prec, r, z, s, true));
             FTS_TRY(launch_dot2(r, z, zo, N, part, dout, s));
             FTS_TRY(readback(h, dout, s, v));
             // flexible (Polak-Ribiere) update: beta = r.(z - z_old) / rz_old
@@ -395,7 +402,7 @@ fts_status fts_gmres(fts_hierarchy *h, fts_prec prec, const double *b, double *x
         for (int j = 0; j < m; ++j) {
             double *Vj = V + (int64_t)j * N, *Zj = Z + (int64_t)j * N;
             GM_TRY(launch_fill(Zj, N, 0.0, s));
-            GM_TRY(vcycle_level(h, L, prec, Vj, Zj, s));  // z_j = MG(0, v_j)
+            GM_TRY(vcycle_level(h, L, prec, Vj, Zj, s, true));  // z_j = MG(0, v_j)
             GM_TRY(launch_operator(lv, Zj, nullptr, w, false, s));
             for (int i = 0; i <= j; ++i) {  // modified Gram-Schmidt
                 double hij;
