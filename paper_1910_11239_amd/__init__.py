@@ -427,13 +427,17 @@ def _vcycle_fn():
         @staticmethod
         def forward(ctx, b, omegas, gammas, solver):
             h = solver.hierarchy(gammas.detach().cpu().numpy())
-            h.set_omega(omegas.detach().cpu().numpy())
+            om = np.array(omegas.detach().cpu().numpy(), dtype=np.float64)
+            h.set_omega(om)
             u = torch.zeros_like(b)
             inputs = []
             for _ in range(solver.ncycles):
                 inputs.append(u.clone())
                 h.vcycle(b, u)
-            ctx.h, ctx.inputs = h, inputs
+            # the hierarchy is shared by every call with these penalties: keep
+            # this call's damping so that backward recomputes the same sweeps
+            ctx.h, ctx.inputs, ctx.omegas = h, inputs, om
+            ctx.param_like = ((omegas.device, omegas.dtype), (gammas.device, gammas.dtype))
             ctx.save_for_backward(b)
             return u
 
@@ -441,6 +445,7 @@ def _vcycle_fn():
         def backward(ctx, grad_u):
             (b,) = ctx.saved_tensors
             h = ctx.h
+            h.set_omega(ctx.omegas)
             lam = grad_u.contiguous().clone()
             lam_b = torch.zeros_like(b)
             lam_x = torch.empty_like(b)
@@ -451,7 +456,9 @@ def _vcycle_fn():
                 dom += o
                 dpen += pnl
                 lam, lam_x = lam_x, lam
-            return lam_b, torch.as_tensor(dom), torch.as_tensor(dpen), None
+            (om_dev, om_dt), (g_dev, g_dt) = ctx.param_like
+            return (lam_b, torch.as_tensor(dom).to(device=om_dev, dtype=om_dt),
+                    torch.as_tensor(dpen).to(device=g_dev, dtype=g_dt), None)
 
     return VCycleFn
 

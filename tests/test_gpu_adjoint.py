@@ -26,7 +26,8 @@ def _fine(d, k, ms_coarse, nl, seed):
 
 
 @pytest.mark.parametrize("kind,d,k,msc,nl,om", [("vertex", 3, 2, (2, 1, 1), 3, 0.125), ("cell", 2, 3, (2, 2), 3, 0.6),
-                                                ("vertex", 2, 4, (1, 2), 3, 0.25)])
+                                                ("vertex", 2, 4, (1, 2), 3, 0.25), ("vertex", 3, 5, (2, 1, 1), 2, 0.125),
+                                                ("cell", 3, 5, (1, 1, 2), 2, 0.6), ("vertex", 2, 8, (1, 2), 3, 0.25)])
 def test_vcycle_adjoint_against_oracle_tangents(kind, d, k, msc, nl, om):
     """For a linear functional c.x_out of one V-cycle, the adjoint outputs
     (dL/dx_in, dL/db, dL/domega_l, dL/dgamma_l) contracted with a direction equal
@@ -115,6 +116,44 @@ def test_autograd_iterations_small():
     e = np.full(nl, h)  # shared penalty factor: sum of the per-level gradients
     fd = (L(b.detach(), om0, ga0 + e) - L(b.detach(), om0, ga0 - e)) / (2 * h)
     assert abs(fd - gga.sum()) <= 1e-6 * abs(gga.sum()) + 1e-9
+
+
+def test_autograd_interleaved_forwards_keep_their_damping():
+    """Two forwards that share a hierarchy (same penalties) but use different
+    damping, then the two backwards in reverse order: each gradient is that of
+    its own forward map (oracle tangent), and parameters on the GPU get their
+    gradients on the GPU."""
+    announce("autograd interleaved")
+    d, k, nl = 3, 2, 3
+    fine = _fine(d, k, (2, 1, 1), nl, 6)
+    N = fine.ndofs
+    solver = fts.VCycleIterations(d, k, fine.widths, nl, "vertex", 2, 2, ncycles=2)
+    ustar = dev(random_vector(N, 1))
+    runs = []
+    for om in (0.125, 0.08):
+        b = dev(random_vector(N, 0)).requires_grad_(True)
+        omegas = torch.tensor([0.0, om, om], dtype=torch.float64, device="cuda", requires_grad=True)
+        gammas = torch.tensor([1.0, 1.0, 1.0], dtype=torch.float64, device="cuda", requires_grad=True)
+        loss = torch.sum((solver(b, omegas, gammas) - ustar) ** 2)
+        runs.append((om, b, omegas, gammas, loss))
+    for om, b, omegas, gammas, loss in reversed(runs):
+        loss.backward()
+        assert omegas.grad.device.type == "cuda" and gammas.grad.device.type == "cuda"
+        oh = multigrid.Hierarchy(fine, nl, "vertex", [0.0, om, om], m_pre=2, m_post=2, gamma_hats=[1.0] * nl)
+        th = tangent.TangentHierarchy(oh)
+        bn, us = host(b.detach()), host(ustar)
+        z = np.zeros(nl)
+        gom = omegas.grad.detach().cpu().numpy()
+        for l in range(1, nl):
+            e = np.zeros(nl)
+            e[l] = 1.0
+            uu, du = th.iterate(bn, np.zeros(N), e, z, 2)
+            ref = 2 * (uu - us) @ du
+            assert abs(gom[l] - ref) <= 1e-9 * abs(ref), ("omega", om, l, gom[l], ref)
+        db_dir = random_vector(N, 7)
+        uu, du = th.iterate(bn, db_dir, z, z, 2)
+        gb = b.grad.detach().cpu().numpy()
+        assert abs(gb @ db_dir - 2 * (uu - us) @ du) <= 1e-10 * abs(2 * (uu - us) @ du)
 
 
 @pytest.mark.slow

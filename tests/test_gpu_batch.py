@@ -7,7 +7,7 @@ import pytest
 from oracle.mesh import Mesh
 from oracle import sipg, schwarz
 from synthetic import loguniform_widths, random_vector, batched_meshes
-from gpu_util import dev, host, rel, announce
+from gpu_util import dev, host, rel, rel2, announce
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -16,7 +16,8 @@ if not torch.cuda.is_available():
 
 import paper_1910_11239_amd as fts  # noqa: E402
 
-SPECS = [(2, (4, 3, 5)), (3, (3, 3, 3)), (4, (2, 3, 2)), (1, (3, 2, 2)), (6, (2, 2, 3)), (7, (3, 2, 2)), (9, (2, 2, 2))]
+SPECS = [(2, (4, 3, 5)), (3, (3, 3, 3)), (4, (2, 3, 2)), (5, (3, 2, 3)), (1, (3, 2, 2)), (6, (2, 2, 3)),
+         (7, (3, 2, 2)), (8, (2, 3, 2)), (9, (2, 2, 2))]
 
 
 def _meshes():
@@ -75,16 +76,17 @@ def test_batch_fp32_error_and_autotune():
     out = host(xg)
     for i, (kind, ref, _) in enumerate(_oracle_sweeps(meshes, 0.4, bs, xs)):
         off, n = batch.offsets[i]
-        err = rel(out[off:off + n] - xs[i], ref - xs[i])
+        err = rel2(out[off:off + n] - xs[i], ref - xs[i])
         print("mesh", i, "k", meshes[i].k, "fp32 correction error", err)
         assert err < 1e-5
 
 
 def test_batched_workload_runs_and_is_consistent():
     """The 64-mesh workload (k ~ U{2..9}, m ~ U{8..24}, per-slab widths
-    log-uniform in [0.25, 4]): the batched FP64 sweep equals, mesh by mesh, the
-    single-mesh FP64 path within 1e-12 on two sampled meshes (the single-mesh
-    path is parity-tested against the oracle), and FP32 stays within 1e-5."""
+    log-uniform in [0.25, 4]): the batched FP64 sweep equals the single-mesh
+    FP64 path within 1e-12 on the first mesh of every degree present and on the
+    last mesh (the single-mesh path is parity-tested against the oracle at
+    every degree), and FP32 stays within 1e-5."""
     announce("batched workload")
     specs = batched_meshes()
     batch = fts.Batch([(k, w, 1.0) for k, w in specs])
@@ -99,11 +101,16 @@ def test_batched_workload_runs_and_is_consistent():
     err = float(torch.linalg.norm(d32 - d64) / torch.linalg.norm(d64))
     print("FP32 vs FP64 correction, whole batch:", err)
     assert err < 1e-5
-    for i in (0, len(specs) - 1):
+    first = {}
+    for i, (k, _) in enumerate(specs):
+        first.setdefault(k, i)
+    assert set(first) == set(range(2, 10))
+    for i in sorted(set(first.values()) | {len(specs) - 1}):
         k, w = specs[i]
+        announce("batched workload mesh", i, "k", k, "m", len(w[0]))
         off, n = batch.offsets[i]
         lv = fts.Level(3, k, w, 1.0)
         eg = fts.Eigs(lv, "vertex")
         xs = x0[off:off + n].clone()
         fts.schwarz_smooth(lv, eg, 0.125, b[off:off + n].clone(), xs, 1)
-        assert rel(host(xs), host(x64[off:off + n])) < 1e-12
+        assert rel(host(xs), host(x64[off:off + n])) < 1e-12, (i, k)

@@ -13,7 +13,7 @@ import scipy.linalg as sla
 from oracle.mesh import Mesh, uniform_mesh
 from oracle import sipg, onedim, schwarz, multigrid
 from synthetic import loguniform_widths, random_vector, uniform_widths, CONFIGS
-from gpu_util import dev, host, rel, announce
+from gpu_util import dev, host, rel, rel2, announce
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -34,8 +34,9 @@ def glevel(m):
     return fts.Level(m.dim, m.k, m.widths, m.gamma_hat)
 
 
-OP_CASES = [(2, 1, (5, 3)), (2, 3, (5, 4)), (2, 9, (3, 2)), (3, 1, (4, 3, 5)), (3, 2, (3, 4, 3)),
-            (3, 4, (4, 3, 5)), (3, 7, (3, 2, 3)), (3, 9, (2, 2, 3))]
+OP_CASES = [(2, 1, (5, 3)), (2, 3, (5, 4)), (2, 5, (4, 3)), (2, 8, (3, 4)), (2, 9, (3, 2)), (3, 1, (4, 3, 5)),
+            (3, 2, (3, 4, 3)), (3, 4, (4, 3, 5)), (3, 5, (3, 4, 2)), (3, 6, (2, 3, 3)), (3, 7, (3, 2, 3)),
+            (3, 8, (2, 3, 2)), (3, 9, (2, 2, 3))]
 
 
 @pytest.mark.parametrize("d,k,ms", OP_CASES)
@@ -74,10 +75,13 @@ def test_setup_1d_eigs(kind, d, k, ms):
             assert np.allclose(lam, sla.eigh(A0, M0, eigvals_only=True), rtol=1e-12, atol=0)
 
 
-SMOOTH_CASES = [("cell", 2, 3, (5, 4)), ("cell", 3, 4, (3, 4, 3)), ("cell", 3, 9, (2, 2, 1)),
-                ("vertex", 2, 3, (5, 4)), ("vertex", 2, 9, (3, 3)), ("vertex", 3, 1, (5, 4, 3)),
-                ("vertex", 3, 2, (4, 3, 5)), ("vertex", 3, 4, (3, 4, 3)), ("vertex", 3, 6, (3, 3, 2)),
-                ("vertex", 3, 7, (3, 4, 3))]  # k = 7: FP64 MFMA local solves
+SMOOTH_CASES = [("cell", 2, 3, (5, 4)), ("cell", 3, 4, (3, 4, 3)), ("cell", 3, 5, (3, 2, 3)),
+                ("cell", 3, 8, (2, 3, 2)), ("cell", 3, 9, (2, 2, 1)),
+                ("vertex", 2, 3, (5, 4)), ("vertex", 2, 5, (4, 3)), ("vertex", 2, 8, (3, 4)),
+                ("vertex", 2, 9, (3, 3)), ("vertex", 3, 1, (5, 4, 3)),
+                ("vertex", 3, 2, (4, 3, 5)), ("vertex", 3, 4, (3, 4, 3)), ("vertex", 3, 5, (3, 4, 3)),
+                ("vertex", 3, 6, (3, 3, 2)), ("vertex", 3, 7, (3, 4, 3)),  # k = 7: FP64 MFMA local solves
+                ("vertex", 3, 8, (3, 2, 3))]
 
 
 @pytest.mark.parametrize("kind,d,k,ms", SMOOTH_CASES)
@@ -135,7 +139,7 @@ def test_schwarz_mirror_symmetric_positions(kind, k, widths):
     assert rel(host(xg), ref) < TOL
     xg = dev(x)
     fts.schwarz_smooth(lv, eg, omega, dev(b), xg, nsweeps=1, prec="f32")
-    assert rel(host(xg) - x, ref - x) < 1e-4
+    assert rel2(host(xg) - x, ref - x) < 1e-4
 
 
 @pytest.mark.parametrize("k,m,cz,widths", [(3, 25, 2, "random"), (4, 32, 4, "uniform"), (3, 48, 8, "random"),
@@ -162,7 +166,7 @@ def test_staged_runs_along_z_match_colored(k, m, cz, widths):
             xa = dev(np.zeros(lv.ndofs))
             fts.schwarz_apply(lv, eg, 0.5, r, xa, prec)
             out[schedule] = host(xa)
-        assert rel(out["staged"], out["colored"]) < tol, prec
+        assert rel2(out["staged"], out["colored"]) < tol, prec
 
 
 def test_staged_schedule_is_deterministic():
@@ -236,7 +240,9 @@ def test_transfers(d, k, ms):
 
 
 @pytest.mark.parametrize("kind,d,k,ms,nl", [("vertex", 3, 2, (8, 4, 4), 3), ("cell", 2, 3, (8, 8), 3),
-                                            ("vertex", 2, 4, (8, 4), 3), ("vertex", 3, 4, (4, 4, 4), 2)])
+                                            ("vertex", 2, 4, (8, 4), 3), ("vertex", 3, 4, (4, 4, 4), 2),
+                                            ("vertex", 3, 5, (4, 4, 4), 2), ("cell", 3, 5, (4, 4, 2), 2),
+                                            ("vertex", 2, 8, (8, 4), 3), ("vertex", 3, 8, (4, 2, 2), 2)])
 def test_vcycle(kind, d, k, ms, nl):
     announce("vcycle", kind, d, k, ms, nl)
     from oracle.mesh import refine
@@ -319,6 +325,79 @@ def test_avs_3d_q4_full_size_sampled():
         assert rel(x_h[m.cell_dofs(c)], xv) < TOL
 
 
+def _full_size_sampled(m, omega, res_cells, smooth_cells, precs):
+    """One residual and one vertex-patch sweep of the full-size mesh `m` on the
+    GPU (the launch configuration the benchmark uses), against the oracle's
+    values recomputed exactly on sampled cells from their neighbourhoods:
+    FP64 at the parity bar, reduced-precision corrections within their bounds."""
+    from oracle import sampled
+    b, x0 = random_vector(m.ndofs, 0), random_vector(m.ndofs, 1)
+    lv = glevel(m)
+    eg = fts.Eigs(lv, "vertex")
+    bg = dev(b)
+    x0g = dev(x0)
+    rg = torch.empty_like(bg)
+    lv.residual(bg, x0g, rg)
+    r_h = host(rg)
+    del rg
+    outs = {}
+    for prec in precs:
+        xg = x0g.clone()
+        fts.schwarz_smooth(lv, eg, omega, bg, xg, 1, prec=prec)
+        outs[prec] = {c: host(xg[m.cell_dofs(c)[0]:m.cell_dofs(c)[-1] + 1]) for c in smooth_cells}
+        del xg
+    rs = sampled.residual_cells(m, x0, b, res_cells)
+    for c, rv in rs.items():
+        assert rel(r_h[m.cell_dofs(c)], rv) < TOL, c
+    xs = sampled.smooth_cells(m, x0, b, omega, "vertex", smooth_cells)
+    for c, xv in xs.items():
+        d0 = m.cell_dofs(c)
+        for prec, bound in precs.items():
+            got = outs[prec][c]
+            if prec == "f64":
+                assert rel(got, xv) < TOL, (prec, c)
+            else:
+                err = rel2(got - x0[d0], xv - x0[d0])
+                print(prec, "cell", c, "correction error vs oracle", err)
+                assert err < bound, (prec, c, err)
+
+
+def test_mixed_3d_q7_full_size_sampled():
+    """The 48^3 Q7 fine level (56,623,104 DoFs) at full size: residual and one
+    vertex-patch sweep with FP64 contractions (FP64 MFMA local solves in runs
+    along z) at the parity bar, and FP32 / FP16 / BF16 contractions within
+    their error bounds, against sampled oracle cells (corner, edge, interior)."""
+    cfg = CONFIGS["mixed_3d_q7"]
+    announce("mixed_3d_q7 full-size sampled")
+    m = Mesh(3, cfg["k"], uniform_widths(3, cfg["m"]), cfg["gamma_hat"])
+    mm = cfg["m"] - 1
+    _full_size_sampled(m, cfg["omega"], [(0, 0, 0), (mm, mm, mm), (0, 7, mm), (24, 24, 24), (47, 3, 20)],
+                       [(0, 0, 0), (mm, 0, 11), (23, 30, 17)],
+                       {"f64": None, "f32": 1e-4, "f16": 1.5e-3, "bf16": 1.2e-2})
+
+
+def test_adjoint_3d_q5_full_size_sampled():
+    """The 32^3 Q5 fine level (7,077,888 DoFs): residual and one FP64
+    vertex-patch sweep against sampled oracle cells."""
+    cfg = CONFIGS["adjoint_3d_q5"]
+    announce("adjoint_3d_q5 fine level full-size sampled")
+    m = Mesh(3, cfg["k"], uniform_widths(3, cfg["m"]), cfg["gamma_hat"])
+    mm = cfg["m"] - 1
+    _full_size_sampled(m, cfg["omega"], [(0, 0, 0), (mm, mm, mm), (0, 5, mm), (16, 16, 16), (1, 30, 7)],
+                       [(0, 0, 0), (mm, 9, 0), (16, 16, 16), (5, 1, 30)], {"f64": None, "f32": 1e-4})
+
+
+def test_q8_26_cubed_full_size_sampled():
+    """k = 8 on 26^3 random rectilinear cells (12,812,904 DoFs): enough patches
+    (15,625) for runs of 2 patches along z; residual and FP64 / FP32 sweep
+    against sampled oracle cells."""
+    announce("q8 26^3 sampled")
+    rng = np.random.default_rng(29)
+    m = Mesh(3, 8, loguniform_widths(rng, 3, (26, 26, 26), 0.25, 4.0), 1.0)
+    _full_size_sampled(m, 0.125, [(0, 0, 0), (25, 25, 25), (12, 0, 5), (11, 13, 12)],
+                       [(0, 0, 0), (25, 0, 25), (0, 12, 7)], {"f64": None, "f32": 1e-4})
+
+
 @pytest.mark.parametrize("d,k,ms", [(3, 4, (4, 3, 3))])
 def test_f32_contractions_error_bound(d, k, ms):
     """FP32 contractions (FP64 residual and accumulation): error of one sweep
@@ -334,7 +413,7 @@ def test_f32_contractions_error_bound(d, k, ms):
     eg = fts.Eigs(lv, "vertex")
     xg = dev(x)
     fts.schwarz_smooth(lv, eg, 0.3, dev(b), xg, 1, prec="f32")
-    err = rel(host(xg) - x, ref - x)
+    err = rel2(host(xg) - x, ref - x)
     print("f32 relative error of the correction", err)
     assert err < 1e-4
 
@@ -405,7 +484,7 @@ def test_mfma_contractions_error_bound(kind, k, ms, prec, bound):
         eg.set_schedule(schedule)
         xa = dev(np.zeros(m.ndofs))
         fts.schwarz_apply(lv, eg, 0.4, dev(r), xa, prec=prec)
-        err = rel(host(xa), ref)
+        err = rel2(host(xa), ref)
         print(prec, kind, k, schedule, "relative error", err)
         assert err < bound
 
