@@ -166,6 +166,22 @@ fts_status fts_schwarz_smooth(const fts_level *level, const fts_eigs *eigs, doub
 fts_status fts_schwarz_apply(const fts_level *level, const fts_eigs *eigs, double omega,
                              fts_prec prec, const double *r, double *x, void *stream);
 
+/* Allocation-free form of fts_schwarz_smooth, for callers that cannot
+ * allocate device memory or pass a workspace (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments and result
+ * as fts_schwarz_smooth without ws / ws_bytes: the residual lives in a static
+ * device array of FTS_NOALLOC_SCRATCH_BYTES bytes (32 MiB, i.e. levels of up
+ * to 4,194,304 DoFs; each device the library runs on holds its own copy until
+ * the process ends), looked up once per device at the first call on it.
+ * Larger levels fail with FTS_E_SIZE.  The call allocates nothing.  Every call
+ * on one device shares that array: calls that overlap on one device (other
+ * streams, other threads) race and must be serialised by the caller; calls
+ * ordered on one stream are safe (each call overwrites the whole residual
+ * before reading it). */
+#define FTS_NOALLOC_SCRATCH_BYTES (32u * 1024u * 1024u)
+fts_status fts_schwarz_smooth_noalloc(const fts_level *level, const fts_eigs *eigs, double omega, fts_prec prec,
+                                      const double *b, double *x, int32_t nsweeps, void *stream);
+
 /* Multiplicative Schwarz smoother (Alg. multsmoother, eq. coloredschwarz):
  * nsweeps times, for each color c = 0..C-1 in turn: r = b - A x, then
  * x += omega sum_{j in color c} R_j^T A_j^-1 R_j r.  Colors (Sec. 2.3): cells

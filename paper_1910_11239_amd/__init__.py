@@ -47,6 +47,7 @@ _SIGS = {
     "fts_smooth_ws_bytes": (_SZ, [_VP]),
     "fts_schwarz_smooth": (_I32, [_VP, _VP, _D, _I32, _VP, _VP, _I32, _VP, _SZ, _VP]),
     "fts_schwarz_smooth_mult": (_I32, [_VP, _VP, _D, _I32, _VP, _VP, _I32, _VP, _SZ, _VP]),
+    "fts_schwarz_smooth_noalloc": (_I32, [_VP, _VP, _D, _I32, _VP, _VP, _I32, _VP]),
     "fts_schwarz_apply": (_I32, [_VP, _VP, _D, _I32, _VP, _VP, _VP]),
     "fts_restrict": (_I32, [_VP, _VP, _VP, _VP, _VP]),
     "fts_prolongate_add": (_I32, [_VP, _VP, _VP, _VP, _VP]),
@@ -209,6 +210,16 @@ def schwarz_smooth(level, eigs, omega, b, x, nsweeps=1, prec="f64", ws=None):
     _check(lib().fts_schwarz_smooth(level._h, eigs._h, float(omega), PREC[prec], _ptr(b, level.ndofs, "b"),
                                     _ptr(x, level.ndofs, "x"), int(nsweeps), _ptr(ws, None, "ws"),
                                     ws.numel() * 8, _stream()), "fts_schwarz_smooth")
+    return x
+
+
+def schwarz_smooth_noalloc(level, eigs, omega, b, x, nsweeps=1, prec="f64"):
+    """fts_schwarz_smooth without a workspace argument: the residual lives in
+    the library's static device array (levels of up to 4,194,304 DoFs); the
+    call allocates nothing."""
+    _check(lib().fts_schwarz_smooth_noalloc(level._h, eigs._h, float(omega), PREC[prec], _ptr(b, level.ndofs, "b"),
+                                            _ptr(x, level.ndofs, "x"), int(nsweeps), _stream()),
+           "fts_schwarz_smooth_noalloc")
     return x
 
 
