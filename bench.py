@@ -68,10 +68,23 @@ def measured_traffic(kernel):
     return rec["bytes_per_call"]
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(cfg):
-    """The oracle's V-cycle on the same workload reduced to 8^3 fine cells
-    (3 levels 8^3/4^3/2^3, Q4, omega 0.5, 2/2 sweeps); setup excluded."""
-    from threadpoolctl import threadpool_info
+    """The oracle (plain FP64 numpy/scipy: sparse quadrature matrix, dense-LU
+    patch solves) on the same workload reduced to 8^3 fine cells (64,000 DoFs;
+    3 levels 8^3/4^3/2^3, Q4, omega 0.5, 2/2 sweeps): one residual, one
+    smoother sweep and one V-cycle, each with one BLAS thread and with all the
+    host's threads; setup excluded.  value = V-cycle DoFs/s, all threads."""
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle.mesh import uniform_mesh
     from oracle import multigrid
     fine = uniform_mesh(3, cfg["k"], 8, gamma_hat=cfg["gamma_hat"])
@@ -79,16 +92,34 @@ def cpu_baseline(cfg):
     h = multigrid.Hierarchy(fine, nl, "vertex", [0.0] + [cfg["omega"]] * (nl - 1),
                             m_pre=cfg["m_pre"], m_post=cfg["m_post"])
     b = random_vector(fine.ndofs, cfg["seed_b"])
-    times = []
-    for _ in range(3):
-        t = time.perf_counter()
-        h.vcycle(np.zeros_like(b), b)
-        times.append(time.perf_counter() - t)
-    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    return {"value": fine.ndofs / float(np.median(times)), "unit": "DoFs/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": "oracle V-cycle (sparse quadrature matrix, dense-LU patch solves) on the same "
-                      "workload reduced to 8^3 fine cells (64,000 DoFs), median of 3, setup excluded"}
+    x = random_vector(fine.ndofs, cfg["seed_x"])
+    A = h.A[-1]
+
+    def med(fn, reps):
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t)
+        return float(np.median(ts))
+
+    threads_all = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    timings = {}
+    for label, limit in (("1_thread", 1), ("all_threads", None)):
+        with threadpool_limits(limit):
+            timings[label] = {
+                "residual_s": med(lambda: b - A @ x, 5),
+                "sweep_s": med(lambda: h.smooth(nl - 1, x.copy(), b), 3),
+                "vcycle_s": med(lambda: h.vcycle(np.zeros_like(b), b), 3),
+            }
+    for v in timings.values():
+        for key in list(v):
+            v[key.replace("_s", "_dofs_per_s")] = fine.ndofs / v[key]
+    return {"value": fine.ndofs / timings["all_threads"]["vcycle_s"], "unit": "DoFs/s", "cores": int(threads_all),
+            "kind": "oracle", "cpu_model": _cpu_model(), "os_cpu_count": os.cpu_count(),
+            "timings": timings,
+            "sample": "oracle residual (x5), smoother sweep (x3) and V-cycle (x3, the value) on the same workload "
+                      "reduced to 8^3 fine cells (64,000 DoFs), medians, 1 thread and all threads, setup excluded"}
 
 
 def mixed_vs_fp64(steps_hint=1):
@@ -114,7 +145,11 @@ def mixed_vs_fp64(steps_hint=1):
     fine, eg = hier.levels[-1], hier.eigs[-1]
     r = torch.as_tensor(random_vector(N, 5)).cuda()
     xa = torch.zeros_like(r)
+    rr = torch.empty_like(r)
     patch_flops = wm.smoother_flops(dim, k, (m,) * dim, "vertex")
+    apply_bytes = wm.patch_apply_bytes(dim, k, (m,) * dim)
+    res_bytes = wm.residual_bytes(dim, k, (m,) * dim)
+    t_res = _events_time(lambda: fine.residual(b, xa, rr), 5)
     for prec in ("f64", "f32", "f16", "bf16"):
         x = torch.zeros(N, dtype=torch.float64, device="cuda")
         hier.pcg(b, x, rtol=cfg["rtol"], maxit=3, prec=prec, ws=ws)  # warm-up
@@ -126,9 +161,14 @@ def mixed_vs_fp64(steps_hint=1):
         dt = time.perf_counter() - t
         t_apply = _events_time(lambda: fts.schwarz_apply(fine, eg, cfg["omega"], r, xa, prec=prec), 3)
         sol[prec] = x
+        sweep_ms = t_res + t_apply
         out[prec] = {"iterations": it, "seconds": dt, "final_relres": rel,
                      "patch_apply_ms": t_apply,
-                     "patch_apply_tflops": patch_flops / (t_apply * 1e-3) / 1e12}
+                     "patch_apply_tflops": patch_flops / (t_apply * 1e-3) / 1e12,
+                     "patch_apply_hbm_gbs": apply_bytes / (t_apply * 1e-3) / 1e9,
+                     "sweep_ms": sweep_ms,
+                     "sweep_dofs_per_s": N / (sweep_ms * 1e-3),
+                     "sweep_hbm_gbs": (res_bytes + apply_bytes) / (sweep_ms * 1e-3) / 1e9}
     for prec in out:
         out[prec]["rel_diff_vs_f64"] = float(torch.linalg.norm(sol[prec] - sol["f64"]) /
                                              torch.linalg.norm(sol["f64"]))
@@ -137,7 +177,14 @@ def mixed_vs_fp64(steps_hint=1):
     torch.cuda.empty_cache()
     return {"workload": "mixed_3d_q7: 3-D DG Q7, 48^3 cells (56,623,104 DoFs), CG to 1e-10 with a 5-level "
                         "vertex-patch V-cycle (omega 0.125, 2+2 sweeps, dense LU on 13,824 DoFs)",
-            "setup_s": setup_s, "by_precision": out}
+            "setup_s": setup_s, "residual_ms": t_res,
+            "algorithmic_bytes": {"residual": res_bytes, "patch_apply": apply_bytes,
+                                  "note": "residual reads x, b and writes r (24 B/DoF); the patch apply reads r "
+                                          "and reads and writes x (24 B/DoF); a sweep is both (48 B/DoF)"},
+            "error_vs_oracle": "each precision's ||x - x_oracle|| / ||x_oracle|| against the exact discrete "
+                               "solution (oracle global fast diagonalisation) is checked by "
+                               "tests/test_gpu_parity.py::test_mixed_3d_q7_cg_error_vs_oracle",
+            "by_precision": out}
 
 
 def batched_workload():
@@ -376,8 +423,33 @@ def main():
     }
     del hier
     torch.cuda.empty_cache()
+    apply_bytes = wm.patch_apply_bytes(dim, k, ncells)
+    smoother = {
+        "avs_3d_q4_fp64_patch_apply": {
+            "kernel": kernels["vertex_patch_apply_fp64"]["kernel"], "bound": "alu",
+            "achieved": round(patch_flops / (t_patch * 1e-3) / 1e12, 3), "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(patch_flops / (t_patch * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
+            "hbm_gbs": round(apply_bytes / (t_patch * 1e-3) / 1e9, 1),
+            "hbm_frac": round(apply_bytes / (t_patch * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic("avs_3d_q4_fp64_patch_apply"),
+            "algorithmic": f"{patch_flops:.4g} flop and {apply_bytes:.4g} bytes (read r, read and write x) per call"},
+    }
+    out["smoother_roofline"] = smoother
     if not args.no_mixed:
         out["mixed_vs_fp64"] = mixed_vs_fp64()
+        mx = out["mixed_vs_fp64"]
+        for prec in ("f16", "bf16"):
+            bp = mx["by_precision"][prec]
+            smoother[f"mixed_3d_q7_{prec}_sweep"] = {
+                "kernel": "residual (FP64) + 16-bit MFMA vertex-patch apply", "bound": "hbm",
+                "achieved": round(bp["sweep_hbm_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(bp["sweep_hbm_gbs"] / HBM_PEAK_GBS, 4),
+                "apply_hbm_gbs": round(bp["patch_apply_hbm_gbs"], 1),
+                "apply_frac": round(bp["patch_apply_hbm_gbs"] / HBM_PEAK_GBS, 4),
+                "ms": bp["sweep_ms"], "dofs_per_s": bp["sweep_dofs_per_s"],
+                "traffic": measured_traffic(f"mixed_3d_q7_{prec}_sweep"),
+                "algorithmic": "48 B/DoF per sweep: residual 24 (read x, b, write r) + apply 24 (read r, "
+                               "read and write x), 56,623,104 DoFs"}
     if not args.no_batched:
         out["batched"] = batched_workload()
     if not args.no_mult:

@@ -125,7 +125,7 @@ int32_t fts_eigs_n(const fts_eigs *eigs);
 
 /* How overlapping vertex patches are summed (both give the additive operator
  * of eq. additiveschwarz; they differ only in rounding order):
- *   FTS_SCHEDULE_STAGED  (default) one launch over all patches writes each
+ *   FTS_SCHEDULE_STAGED  one launch over all patches writes each
  *        patch's correction to a staging buffer owned by the eigs handle
  *        (2^d (k+1)^d doubles per patch, allocated by fts_setup_1d_eigs);
  *        a second launch adds, per cell, the corrections of its 2^d patches
@@ -133,9 +133,17 @@ int32_t fts_eigs_n(const fts_eigs *eigs);
  *        be ordered on one stream (they share the staging buffer).
  *   FTS_SCHEDULE_COLORED 2^d launches, one per parquet color (patches of one
  *        color share no cell, Sec. 2.3), each adding into x directly.
+ *   FTS_SCHEDULE_OWNER   16-bit contractions of 3-D vertex patches: one
+ *        launch in which a workgroup owns a tile of 3 x 3 cells (x, y) and a
+ *        range of cell layers (z), computes every patch touching its cells
+ *        (patches on tile borders are computed by each neighbouring tile) and
+ *        sums their corrections in on-chip memory in a fixed order before
+ *        updating x once; no staging buffer.  Deterministic.  Other
+ *        precisions and cells fall back to FTS_SCHEDULE_STAGED.  The default.
  * Ignored for cells (disjoint, one launch). */
 #define FTS_SCHEDULE_STAGED 0
 #define FTS_SCHEDULE_COLORED 1
+#define FTS_SCHEDULE_OWNER 2
 fts_status fts_eigs_set_schedule(fts_eigs *eigs, int32_t schedule);
 
 /* ---- a4: matrix-free SIPG operator --------------------------------------- */
@@ -157,7 +165,7 @@ size_t fts_smooth_ws_bytes(const fts_level *level);
  *     r = b - A x;   x <- x + omega * sum_j R_j^T A_j^-1 R_j r
  * with A_j^-1 = (S x..x S) diag(1/Lambda) (S x..x S)^T (eq. fastinverse).
  * Overlapping vertex patches are summed as set by fts_eigs_set_schedule
- * (default: staged, deterministic).  ws: device workspace of
+ * (default: owner tiles for 16-bit, else staged; deterministic).  ws: device workspace of
  * fts_smooth_ws_bytes bytes. */
 fts_status fts_schwarz_smooth(const fts_level *level, const fts_eigs *eigs, double omega,
                               fts_prec prec, const double *b, double *x, int32_t nsweeps, void *ws,

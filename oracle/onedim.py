@@ -142,7 +142,7 @@ def global_fastdiag_solve(mesh, b):
 def _apply_axis(T, Mat, a, d):
     """Contract Mat (out x in) with tensor axis ``a`` (numpy axis d-1-a)."""
     ax = d - 1 - a
-    T = np.moveaxis(T, ax, -1) @ Mat.T
+    T = np.tensordot(T, Mat, axes=([ax], [1]))  # contracted axis moved last
     return np.moveaxis(T, -1, ax)
 
 

@@ -186,8 +186,10 @@ class Eigs:
             self._h = None
 
     def set_schedule(self, schedule):
-        """'staged' (default, deterministic) or 'colored' (2^d parquet colors)."""
-        _check(lib().fts_eigs_set_schedule(self._h, {"staged": 0, "colored": 1}[schedule]),
+        """'owner' (default: owner-computes tiles for 16-bit 3-D vertex patches,
+        staged otherwise), 'staged' (deterministic staging buffer + gather) or
+        'colored' (2^d parquet colors)."""
+        _check(lib().fts_eigs_set_schedule(self._h, {"staged": 0, "colored": 1, "owner": 2}[schedule]),
                "fts_eigs_set_schedule")
 
     def get(self, axis, index):

@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libfts.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["setup.cpp", "capi.cpp", "kernels.hip", "coarse.hip", "batch.hip", "noalloc.hip"]
+SOURCES = ["setup.cpp", "capi.cpp", "kernels.hip", "coarse.hip", "batch.hip", "noalloc.hip", "tile.hip"]
 
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
@@ -29,9 +29,15 @@ CFLAGS = [
 ]
 
 
+# per-source flags: the owner-tile kernel chains 16-bit MFMA results straight
+# into the next MFMA, so their results go to ordinary VGPRs (no accumulation-
+# register reads between the contractions)
+EXTRA = {"tile.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def _compile(src):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *CFLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")

@@ -135,7 +135,7 @@ struct fts_eigs {
                                 // FP64 or FP32 values, sized for FP64)
     double *d_stage_scale = nullptr;  // one FP64 factor per patch for the 16-bit path
     void *d_mfma = nullptr;     // 16-bit MFMA tables (n <= 16 only)
-    int schedule = FTS_SCHEDULE_STAGED;
+    int schedule = FTS_SCHEDULE_OWNER;  // owner tiles for 16-bit 3-D vertex patches, else staged
     fts::EigView view{};
 };
 
@@ -158,6 +158,10 @@ fts_status launch_sum_acc(const double *x, int64_t n, double scale, double *part
 fts_status launch_axpy(double a, const double *x, double *y, int64_t n, hipStream_t stream);
 fts_status launch_schwarz(const fts_level *lv, const fts_eigs *eg, double omega, fts_prec prec,
                           const double *r, double *x, hipStream_t stream);
+// 16-bit local solves of 3-D vertex patches by owner-computes tiles (tile.hip):
+// x += omega sum_j R_j^T A_j^-1 R_j r; r must be 16-byte aligned.
+fts_status launch_schwarz_mfma_tile(const fts_level *lv, const fts_eigs *eg, double omega, int bf, const double *r,
+                                    double *x, hipStream_t stream);
 // Colors of the multiplicative smoother: 2 (red-black cells) or 2^(d+1)
 // (vertex patches); one color's local solves added to x in place.
 int schwarz_mult_colors(const fts_eigs *eg);

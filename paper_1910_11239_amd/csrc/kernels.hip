@@ -1085,7 +1085,7 @@ struct RunSchwarz {
     static fts_status go(const fts_level *lv, const fts_eigs *eg, double omega, const double *r, double *x,
                          hipStream_t st) {
         using C = SwCfg<D, N1, KIND>;
-        const bool staged = KIND == 1 && eg->schedule == FTS_SCHEDULE_STAGED;
+        const bool staged = KIND == 1 && eg->schedule != FTS_SCHEDULE_COLORED;
         const int ncolor = (KIND && !staged) ? (1 << D) : 1;
         int cz = 1;  // patches per run along z in the staging buffer (k_schwarz_zrun)
         for (int color = 0; color < ncolor; ++color) {
@@ -1143,7 +1143,11 @@ struct RunSchwarz {
         if constexpr (D != 3 || (KIND ? 2 * N1 : N1) > 16) {
             return fail(FTS_E_UNSUPPORTED, "16-bit MFMA contractions need d = 3 and n <= 16");
         } else {
-            const bool staged = KIND == 1 && eg->schedule == FTS_SCHEDULE_STAGED;
+            if constexpr (KIND == 1) {
+                if (eg->schedule == FTS_SCHEDULE_OWNER && reinterpret_cast<uintptr_t>(r) % 16 == 0)
+                    return launch_schwarz_mfma_tile(lv, eg, omega, BF, r, x, st);
+            }
+            const bool staged = KIND == 1 && eg->schedule != FTS_SCHEDULE_COLORED;
             const int ncolor = (KIND && !staged) ? 8 : 1;
             int cz = 1;
             for (int color = 0; color < ncolor; ++color) {
@@ -1275,7 +1279,7 @@ struct RunSchwarz {
         if constexpr (D != 3 || N1 != 8) {
             return fail(FTS_E_UNSUPPORTED, "FP64 MFMA local solves need d = 3 and k = 7");
         } else {
-            const bool staged = eg->schedule == FTS_SCHEDULE_STAGED;
+            const bool staged = eg->schedule != FTS_SCHEDULE_COLORED;
             const int ncolor = staged ? 1 : 8;
             int cz = 1;
             for (int color = 0; color < ncolor; ++color) {

@@ -143,7 +143,7 @@ def test_schwarz_mirror_symmetric_positions(kind, k, widths):
 
 
 @pytest.mark.parametrize("k,m,cz,widths", [(3, 25, 2, "random"), (4, 32, 4, "uniform"), (3, 48, 8, "random"),
-                                           (7, 26, 2, "uniform"), (7, 34, 4, "random")])
+                                           (7, 26, 2, "uniform"), (7, 34, 4, "random"), (6, 17, 1, "random")])
 def test_staged_runs_along_z_match_colored(k, m, cz, widths):
     """Launches with many vertex patches stage runs of cz patches along z and
     merge the cell layer two neighbours of a run share (cz = 2, 4, 8 at these
@@ -151,8 +151,10 @@ def test_staged_runs_along_z_match_colored(k, m, cz, widths):
     MFMA kernel): the staged result equals the colored schedule, which adds
     each patch to x directly, up to rounding order; the same with FP32 and
     16-bit MFMA contractions (whose run kernel stores the values with their
-    scale factor applied).  Both schedules are checked
-    against the oracle on small meshes above."""
+    scale factor applied).  The owner-computes tiles (16-bit only; other
+    precisions fall back to staging) agree as well, here with ragged tiles
+    and z-segments.  All schedules are checked against the oracle on small
+    meshes above."""
     announce("zrun", k, m, cz, widths)
     rng = np.random.default_rng(23)
     ws = uniform_widths(3, (m, m, m)) if widths == "uniform" else loguniform_widths(rng, 3, (m, m, m), 0.25, 4.0)
@@ -161,12 +163,19 @@ def test_staged_runs_along_z_match_colored(k, m, cz, widths):
     r = dev(random_vector(lv.ndofs, 2))
     for prec, tol in (("f64", 1e-13), ("f32", 1e-6), ("f16", 1e-6), ("bf16", 1e-6)):
         out = {}
-        for schedule in ("staged", "colored"):
+        for schedule in ("staged", "colored", "owner"):
             eg.set_schedule(schedule)
             xa = dev(np.zeros(lv.ndofs))
             fts.schwarz_apply(lv, eg, 0.5, r, xa, prec)
             out[schedule] = host(xa)
         assert rel2(out["staged"], out["colored"]) < tol, prec
+        # the owner tiles contract in the transposed orientation (other FP32
+        # summation order inside the MFMA), so a 16-bit rounding of an
+        # intermediate value comes out one unit apart now and then: about
+        # 1e-5 in the 2-norm, far below the 16-bit error against the oracle
+        # (checked on small meshes and at full size)
+        tol_owner = tol if prec in ("f64", "f32") else 1e-4
+        assert rel2(out["owner"], out["colored"]) < tol_owner, prec
 
 
 def test_staged_schedule_is_deterministic():
@@ -465,6 +474,7 @@ def test_pcg_mixed_precision_reaches_fp64_residual():
 
 
 @pytest.mark.parametrize("kind,k,ms", [("vertex", 3, (4, 3, 5)), ("vertex", 4, (3, 4, 3)), ("vertex", 7, (3, 2, 2)),
+                                       ("vertex", 5, (5, 4, 3)), ("vertex", 7, (5, 7, 4)), ("vertex", 2, (8, 4, 5)),
                                        ("cell", 4, (3, 2, 3)), ("cell", 9, (2, 2, 1))])
 @pytest.mark.parametrize("prec,bound", [("f16", 1.5e-3), ("bf16", 1.2e-2)])
 def test_mfma_contractions_error_bound(kind, k, ms, prec, bound):
@@ -480,7 +490,7 @@ def test_mfma_contractions_error_bound(kind, k, ms, prec, bound):
     ref = 0.4 * sol.apply(r)
     lv = glevel(m)
     eg = fts.Eigs(lv, kind)
-    for schedule in (("staged", "colored") if kind == "vertex" else ("staged",)):
+    for schedule in (("staged", "colored", "owner") if kind == "vertex" else ("staged",)):
         eg.set_schedule(schedule)
         xa = dev(np.zeros(m.ndofs))
         fts.schwarz_apply(lv, eg, 0.4, dev(r), xa, prec=prec)
@@ -503,3 +513,28 @@ def test_pcg_mfma_preconditioner_reaches_fp64_residual(prec):
     print("iterations f64", it64, prec, itl)
     assert rl <= 1e-10 and itl <= it64 + 8
     assert rel(host(xl), host(x64)) < 1e-8
+
+
+def test_mixed_3d_q7_cg_error_vs_oracle():
+    """The 48^3 Q7 workload end to end: FP64 CG preconditioned by the 5-level
+    vertex-patch V-cycle to ||r|| <= 1e-10 ||b||, with the smoother's
+    contractions in FP64, FP32, FP16 and BF16; each solution against the exact
+    discrete solution from the oracle's global fast diagonalisation."""
+    cfg = CONFIGS["mixed_3d_q7"]
+    announce("mixed_3d_q7 CG vs oracle")
+    d, k, mm, nl = cfg["dim"], cfg["k"], cfg["m"], cfg["nlevels"]
+    m = uniform_mesh(d, k, mm, gamma_hat=cfg["gamma_hat"])
+    b = random_vector(m.ndofs, cfg["seed_b"])
+    xs = onedim.global_fastdiag_solve(m, b)
+    h = fts.Hierarchy(d, k, m.widths, nl, "vertex", [0.0] + [cfg["omega"]] * (nl - 1), cfg["gamma_hat"],
+                      cfg["m_pre"], cfg["m_post"])
+    bg = dev(b)
+    xsg = dev(xs)
+    nxs = float(torch.linalg.norm(xsg))
+    for prec in ("f64", "f32", "f16", "bf16"):
+        xg = torch.zeros_like(bg)
+        it, relres, _ = h.pcg(bg, xg, rtol=cfg["rtol"], maxit=200, prec=prec)
+        err = float(torch.linalg.norm(xg - xsg)) / nxs
+        print(prec, "iterations", it, "final relres", relres, "error vs oracle", err)
+        assert relres <= cfg["rtol"]
+        assert err < 1e-8, (prec, err)
