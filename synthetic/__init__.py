@@ -78,6 +78,57 @@ def batched_meshes(cfg=None):
     return out
 
 
+def grid_vertices(widths):
+    """Vertex coordinates (prod(m+1), d) of the rectilinear grid with these
+    per-axis cell widths, x fastest (origin at 0)."""
+    coords = [np.concatenate(([0.0], np.cumsum(np.asarray(w, dtype=np.float64)))) for w in widths]
+    grids = np.meshgrid(*reversed(coords), indexing="ij")
+    return np.stack([g.ravel() for g in reversed(grids)], axis=1)
+
+
+def distorted_vertices(dim, m, levels, distortion, seed):
+    """Distorted meshes of the unit square / cube (the test meshes of Sec. 4):
+    a uniform grid of m cells per axis whose interior vertices are moved by
+    distortion * h_v in a random direction (h_v the shortest edge at the
+    vertex, directions uniform on the sphere, numpy PCG64 from seed), then
+    refined `levels` times by splitting every cell at the midpoints of its
+    reference cell (new vertices on the multilinear cell map).  Returns the
+    cells per axis and the vertex array (prod(m+1), d), x fastest."""
+    rng = np.random.default_rng(seed)
+    ms = (m,) * dim
+    X = grid_vertices([np.full(m, 1.0 / m)] * dim).reshape(tuple(mm + 1 for mm in reversed(ms)) + (dim,))
+    shape = X.shape[:-1]
+    out = X.copy()
+    for idx in np.ndindex(*shape):
+        if any(i == 0 or i == n - 1 for i, n in zip(idx, shape)):
+            continue
+        hv = np.inf
+        for a in range(dim):
+            for s in (-1, 1):
+                nb = list(idx)
+                nb[a] += s
+                hv = min(hv, float(np.linalg.norm(X[tuple(nb)] - X[idx])))
+        direction = rng.normal(size=dim)
+        out[idx] = X[idx] + distortion * hv * direction / np.linalg.norm(direction)
+    X = out
+    for _ in range(levels):
+        shape = X.shape[:-1]
+        fine_shape = tuple(2 * (n - 1) + 1 for n in shape)
+        F = np.zeros(fine_shape + (dim,))
+        for fidx in np.ndindex(*fine_shape):
+            c = [min(f // 2, n - 2) for f, n in zip(fidx, shape)]
+            xi = [(f - 2 * cc) / 2.0 for f, cc in zip(fidx, c)]
+            p = np.zeros(dim)
+            for corner in np.ndindex(*([2] * dim)):
+                wgt = np.prod([xi[a] if corner[a] else 1.0 - xi[a] for a in range(dim)])
+                p += wgt * X[tuple(c[a] + corner[a] for a in range(dim))]
+            F[fidx] = p
+        X = F
+        ms = tuple(2 * mm for mm in ms)
+    # X is indexed [v_{d-1}, ..., v_0]: flatten with v_0 fastest
+    return ms, X.reshape(-1, dim)
+
+
 def sine_modes(seed, dim):
     """Integer frequencies m_t in 1..4 of the smooth target prod_t sin(pi m_t x_t)."""
     return tuple(int(v) for v in np.random.default_rng(seed).integers(1, 5, dim))
