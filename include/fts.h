@@ -369,6 +369,56 @@ fts_status fts_batch_get_launch(const fts_batch *batch, int32_t *threads, int32_
 fts_status fts_batch_autotune(fts_batch *batch, fts_prec prec, const double *r, void *stream,
                               char *report, size_t report_len);
 
+/* ---- Sec. 4: mapped (non-Cartesian) cells, Cartesian surrogate solvers ----- */
+
+/* Logically Cartesian mesh of cells that are the images of the reference cell
+ * [0,1]^d under the multilinear map through their 2^d vertices (Sec. 4).
+ * vertices: HOST array of prod(ncells[a] + 1) points of dim coordinates each,
+ * vertex (v_0, .., v_{d-1}) at index v_0 + (m_0 + 1)(v_1 + (m_1 + 1) v_2), read
+ * during the call only.  Cells and DoFs are numbered as on Cartesian meshes. */
+typedef struct fts_mapped_desc {
+    int32_t dim;            /* 2 or 3 */
+    int32_t degree;         /* k, 1..7 */
+    int32_t ncells[3];      /* cells per axis */
+    const double *vertices; /* host, prod(ncells + 1) x dim */
+    double penalty_factor;  /* gamma_hat > 0 */
+} fts_mapped_desc;
+typedef struct fts_mapped_level fts_mapped_level;
+
+/* Builds the geometry tables of the mesh (cell volumes |K|, face areas |F|
+ * and the penalty of every face, gamma_e = gamma_hat k(k+1)(1/h+ + 1/h-) with
+ * h = |K| / |F|, eq. penalty read for mapped cells) and the Cartesian
+ * surrogate of every cell (eq. avglength: a box whose width along axis t is
+ * the mean length of the cell's edges along t; its faces see the surrogate
+ * widths of the neighbours along t): per cell and axis the 1-D SIPG matrices
+ * of the box (eq. 1Dsipg) and their generalised eigenpairs (eq.
+ * generalizedEVP), uploaded to the current device.  FTS_E_INVAL if a cell map
+ * is not orientation preserving. */
+fts_status fts_mapped_level_create(const fts_mapped_desc *desc, fts_mapped_level **out);
+fts_status fts_mapped_level_destroy(fts_mapped_level *level);
+int64_t fts_mapped_level_ndofs(const fts_mapped_level *level);
+/* Host copy of the surrogate widths (ncells x dim, cell-major). */
+fts_status fts_mapped_surrogate_widths(const fts_mapped_level *level, double *hbar);
+
+/* y = A x with the SIPG form eq. (bfsipg) on the mapped cells: gradients
+ * J^-T grad_xi, volume element det J, face normals and area elements from
+ * Nanson's formula, (k+1)-point Gauss rule per axis on cells and faces;
+ * matrix-free.  r = b - A x for fts_mapped_residual. */
+fts_status fts_mapped_apply_operator(const fts_mapped_level *level, const double *x, double *y, void *stream);
+fts_status fts_mapped_residual(const fts_mapped_level *level, const double *b, const double *x, double *r,
+                               void *stream);
+
+/* Additive cell smoother with the surrogate local solvers (eq. schwarzproj):
+ * x += omega sum_K R_K^T Atilde_K^-1 R_K r, Atilde_K^-1 by fast
+ * diagonalisation of the surrogate box (eq. fastinverse). */
+fts_status fts_mapped_schwarz_apply(const fts_mapped_level *level, double omega, const double *r, double *x,
+                                    void *stream);
+/* Workspace bytes of fts_mapped_schwarz_smooth (one residual vector). */
+size_t fts_mapped_smooth_ws_bytes(const fts_mapped_level *level);
+/* nsweeps of r = b - A x; x += omega sum_K R_K^T Atilde_K^-1 R_K r. */
+fts_status fts_mapped_schwarz_smooth(const fts_mapped_level *level, double omega, const double *b, double *x,
+                                     int32_t nsweeps, void *ws, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -76,6 +76,15 @@ _SIGS = {
     "fts_batch_get_launch": (_I32, [_VP, _VP, _VP, _VP]),
     "fts_batch_autotune": (_I32, [_VP, _I32, _VP, _VP, ctypes.c_char_p, _SZ]),
     "fts_pcg": (_I32, [_VP, _I32, _VP, _VP, _D, _I32, _VP, _SZ, _VP, _VP, _VP, _VP]),
+    "fts_mapped_level_create": (_I32, [_VP, _VP]),
+    "fts_mapped_level_destroy": (_I32, [_VP]),
+    "fts_mapped_level_ndofs": (_I64, [_VP]),
+    "fts_mapped_surrogate_widths": (_I32, [_VP, _VP]),
+    "fts_mapped_apply_operator": (_I32, [_VP, _VP, _VP, _VP]),
+    "fts_mapped_residual": (_I32, [_VP, _VP, _VP, _VP, _VP]),
+    "fts_mapped_schwarz_apply": (_I32, [_VP, _D, _VP, _VP, _VP]),
+    "fts_mapped_smooth_ws_bytes": (_SZ, [_VP]),
+    "fts_mapped_schwarz_smooth": (_I32, [_VP, _D, _VP, _VP, _I32, _VP, _SZ, _VP]),
 }
 
 
@@ -342,6 +351,64 @@ class Hierarchy:
         _check(lib().fts_coarse_solve(self._h, _ptr(b0, n0, "b0"), _ptr(x0, n0, "x0"), _stream()),
                "fts_coarse_solve")
         return x0
+
+
+class MappedDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("degree", ctypes.c_int32), ("ncells", ctypes.c_int32 * 3),
+                ("vertices", ctypes.c_void_p), ("penalty_factor", ctypes.c_double)]
+
+
+class MappedLevel:
+    """Mesh of multilinearly mapped cells with Cartesian surrogate local solvers
+    (fts_mapped_*).  verts: (prod(ncells + 1), dim) array, x fastest."""
+
+    def __init__(self, dim, k, ncells, verts, gamma_hat=1.0):
+        self.dim, self.k = dim, k
+        self.ncells = tuple(int(m) for m in ncells)
+        self._verts = np.ascontiguousarray(np.asarray(verts, dtype=np.float64))
+        d = MappedDesc()
+        d.dim, d.degree, d.penalty_factor = dim, k, float(gamma_hat)
+        for a in range(3):
+            d.ncells[a] = self.ncells[a] if a < dim else 1
+        d.vertices = self._verts.ctypes.data
+        h = ctypes.c_void_p()
+        _check(lib().fts_mapped_level_create(ctypes.byref(d), ctypes.byref(h)), "fts_mapped_level_create")
+        self._h = h
+        self.ndofs = int(lib().fts_mapped_level_ndofs(self._h))
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.fts_mapped_level_destroy(self._h)
+            self._h = None
+
+    def surrogate_widths(self):
+        out = np.zeros((int(np.prod(self.ncells)), self.dim))
+        _check(lib().fts_mapped_surrogate_widths(self._h, out.ctypes.data), "fts_mapped_surrogate_widths")
+        return out
+
+    def apply(self, x, y):
+        _check(lib().fts_mapped_apply_operator(self._h, _ptr(x, self.ndofs, "x"), _ptr(y, self.ndofs, "y"),
+                                               _stream()), "fts_mapped_apply_operator")
+        return y
+
+    def residual(self, b, x, r):
+        _check(lib().fts_mapped_residual(self._h, _ptr(b, self.ndofs, "b"), _ptr(x, self.ndofs, "x"),
+                                         _ptr(r, self.ndofs, "r"), _stream()), "fts_mapped_residual")
+        return r
+
+    def schwarz_apply(self, omega, r, x):
+        _check(lib().fts_mapped_schwarz_apply(self._h, float(omega), _ptr(r, self.ndofs, "r"),
+                                              _ptr(x, self.ndofs, "x"), _stream()), "fts_mapped_schwarz_apply")
+        return x
+
+    def schwarz_smooth(self, omega, b, x, nsweeps=1, ws=None):
+        import torch
+        if ws is None:
+            ws = torch.empty(self.ndofs, dtype=torch.float64, device=x.device)
+        _check(lib().fts_mapped_schwarz_smooth(self._h, float(omega), _ptr(b, self.ndofs, "b"),
+                                               _ptr(x, self.ndofs, "x"), int(nsweeps), _ptr(ws, None, "ws"),
+                                               ws.numel() * 8, _stream()), "fts_mapped_schwarz_smooth")
+        return x
 
 
 class Batch:

@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libfts.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["setup.cpp", "capi.cpp", "kernels.hip", "coarse.hip", "batch.hip", "noalloc.hip", "tile.hip"]
+SOURCES = ["setup.cpp", "capi.cpp", "kernels.hip", "coarse.hip", "batch.hip", "noalloc.hip", "tile.hip", "mapped.hip"]
 
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",

@@ -49,6 +49,12 @@ struct Ref1D {
     void interface_penalty(double hl, double hr, double *B) const;
 };
 
+// (k+1)-point Gauss rule on [0, 1] (points xq, weights wq) and the values
+// V[q][i] = phi_i(xq_q) and derivatives D[q][i] = phi_i'(xq_q) of the
+// Gauss-Lobatto Lagrange basis of degree k there.
+void gauss_basis(int k, std::vector<double> &xq, std::vector<double> &wq, std::vector<double> &V,
+                 std::vector<double> &D);
+
 // Generalised symmetric-definite eigenproblem A S = M S diag(lam), S^T M S = I,
 // by Cholesky of M and cyclic Jacobi on L^-1 A L^-T (FP64, host).
 // Returns FTS_E_NOT_SPD if M is not positive definite or an eigenvalue <= 0.

@@ -1,0 +1,749 @@
+// Meshes of mapped (non-Cartesian) cells and the Cartesian surrogate local
+// solvers of Sec. 4: the matrix-free SIPG operator on multilinearly mapped
+// cells and the additive cell smoother whose local solvers are the
+// fast-diagonalisation inverses of rectangular surrogate cells
+// (eq. schwarzproj, eq. avglength).
+//
+// Geometry: a logically Cartesian mesh, cell c = image of [0, 1]^d under the
+// multilinear map through its 2^d vertices.  The operator is eq. (bfsipg)
+// with grad phi = J^-T grad_xi phi, volume element det J, face normal
+// n = J^-T e_t / |J^-T e_t| and area element det J |J^-T e_t| (Nanson),
+// evaluated by the (k+1)-point Gauss rule per axis on cells and faces; the
+// penalty's h+- orthogonal to a face is |K| / |F|.  One workgroup per cell;
+// every tensor of a cell (values, reference gradients, fluxes) lives in LDS
+// and each 1-D contraction is one pass over the output tensor.
+#include <algorithm>
+#include <cmath>
+
+#include "device_common.h"
+
+namespace fts {
+
+struct MappedView {
+    int m[3];
+    int64_t ncells;
+    const double *verts;  // prod(m + 1) x dim vertex coordinates, x fastest
+    const double *V, *D;  // n1 x n1: phi_i and phi_i' at the Gauss points [q][i]
+    const double *xq, *wq;  // n1 Gauss points and weights on [0, 1]
+    const double *dend;   // 2 x n1: phi_i'(0), phi_i'(1)
+    const double *pen;    // ncells x 2d: penalty coefficient of face (t, side) at 2t + side
+    const double *S;      // ncells x d x n1 x n1: surrogate eigenvectors, row-major [i][m]
+    const double *lam;    // ncells x d x n1: surrogate eigenvalues
+};
+
+}  // namespace fts
+
+struct fts_mapped_level {
+    int dim = 0, k = 0, n1 = 0;
+    int m[3] = {1, 1, 1};
+    double gamma_hat = 1.0;
+    int64_t ncells = 0, ndofs = 0;
+    std::vector<double> hbar;  // surrogate widths, ncells x dim
+    double *d_tab = nullptr;
+    fts::MappedView view{};
+};
+
+namespace fts {
+
+constexpr int kMapThreads = 64;
+
+// out = contraction of the tensor `in` (extents e[0..D-1], x fastest) along
+// axis a with the matrix M: out[.., o, ..] = sum_i M(o, i) in[.., i, ..], where
+// M(o, i) = M[o * ld + i] (trans = false) or M[i * ld + o] (trans = true); the
+// output extent along a is nout.  acc: add to out.  Ends with a barrier.
+template <int D>
+__device__ void contract(const double *in, const int *e, int a, const double *M, int ld, bool trans, int nout,
+                         double *out, bool acc) {
+    int eo[3] = {1, 1, 1};
+    for (int b = 0; b < D; ++b) eo[b] = e[b];
+    eo[a] = nout;
+    const int total = eo[0] * eo[1] * eo[2];
+    int stride_in = 1;
+    for (int b = 0; b < a; ++b) stride_in *= e[b];
+    for (int p = threadIdx.x; p < total; p += blockDim.x) {
+        int o[3] = {p % eo[0], (p / eo[0]) % eo[1], p / (eo[0] * eo[1])};
+        const int oa = o[a];
+        o[a] = 0;
+        const int base = o[0] + e[0] * (o[1] + e[1] * o[2]);
+        double s = 0.0;
+        for (int i = 0; i < e[a]; ++i) s += (trans ? M[i * ld + oa] : M[oa * ld + i]) * in[base + i * stride_in];
+        out[p] = acc ? out[p] + s : s;
+    }
+    __syncthreads();
+}
+
+// Jacobian J[b][a] = d x_b / d xi_a of the multilinear map through the corners
+// X[corner * D + b] (corner = sum_a o_a 2^a) at xi; returns det J and J^-1.
+template <int D>
+__device__ double jacobian_inverse(const double *X, const double *xi, double Ji[D][D]) {
+    double J[D][D];
+    for (int b = 0; b < D; ++b)
+        for (int a = 0; a < D; ++a) J[b][a] = 0.0;
+    for (int cidx = 0; cidx < (1 << D); ++cidx)
+        for (int a = 0; a < D; ++a) {
+            double dN = ((cidx >> a) & 1) ? 1.0 : -1.0;
+            for (int a2 = 0; a2 < D; ++a2)
+                if (a2 != a) dN *= ((cidx >> a2) & 1) ? xi[a2] : 1.0 - xi[a2];
+            for (int b = 0; b < D; ++b) J[b][a] += dN * X[cidx * D + b];
+        }
+    double det;
+    if constexpr (D == 2) {
+        det = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        const double id = 1.0 / det;
+        Ji[0][0] = J[1][1] * id;
+        Ji[0][1] = -J[0][1] * id;
+        Ji[1][0] = -J[1][0] * id;
+        Ji[1][1] = J[0][0] * id;
+    } else {
+        const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
+        const double id = 1.0 / det;
+        Ji[0][0] = c00 * id;
+        Ji[1][0] = c01 * id;
+        Ji[2][0] = c02 * id;
+        Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
+        Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
+        Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
+        Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
+        Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
+        Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
+    }
+    return det;
+}
+
+template <int D>
+__device__ void load_corners(const MappedView &g, int64_t cell, double *X) {
+    int c[3] = {(int)(cell % g.m[0]), (int)((cell / g.m[0]) % g.m[1]), (int)(cell / ((int64_t)g.m[0] * g.m[1]))};
+    for (int e2 = threadIdx.x; e2 < (1 << D) * D; e2 += blockDim.x) {
+        const int cidx = e2 / D, b = e2 % D;
+        int v[3] = {0, 0, 0};
+        for (int a = 0; a < D; ++a) v[a] = c[a] + ((cidx >> a) & 1);
+        const int64_t vi = v[0] + (int64_t)(g.m[0] + 1) * (v[1] + (int64_t)(g.m[1] + 1) * v[2]);
+        X[e2] = g.verts[vi * D + b];
+    }
+}
+
+// y = A x (or r = b - A x) on every cell; grid = ncells, one cell per workgroup.
+template <int D, int N1, bool RES>
+__global__ void __launch_bounds__(kMapThreads)
+k_mapped_operator(MappedView g, const double *__restrict__ x, const double *__restrict__ bvec,
+                  double *__restrict__ y) {
+    constexpr int NC = D == 2 ? N1 * N1 : N1 * N1 * N1;
+    constexpr int NF = D == 2 ? N1 : N1 * N1;  // points of a face
+    __shared__ double sV[N1 * N1], sD[N1 * N1], sxq[N1], swq[N1], sde[2 * N1];
+    __shared__ double X[8 * 3], Xn[8 * 3];
+    __shared__ double U[NC], Un[NC], Y[NC], T1[NC], T2[NC];
+    __shared__ double G[D][NC];   // reference gradients, then fluxes
+    __shared__ double Fv[2][NF];  // face values (this cell, neighbour)
+    __shared__ double Fg[2][D][NF];  // face reference gradients
+    __shared__ double Cv[NF], Cg[D][NF];  // face test coefficients
+    const int64_t cell = blockIdx.x;
+    const int t = threadIdx.x;
+    for (int e2 = t; e2 < N1 * N1; e2 += blockDim.x) {
+        sV[e2] = g.V[e2];
+        sD[e2] = g.D[e2];
+    }
+    for (int e2 = t; e2 < N1; e2 += blockDim.x) {
+        sxq[e2] = g.xq[e2];
+        swq[e2] = g.wq[e2];
+        sde[e2] = g.dend[e2];
+        sde[N1 + e2] = g.dend[N1 + e2];
+    }
+    load_corners<D>(g, cell, X);
+    for (int e2 = t; e2 < NC; e2 += blockDim.x) {
+        U[e2] = x[cell * NC + e2];
+        Y[e2] = 0.0;
+    }
+    __syncthreads();
+    const int ec[3] = {N1, N1, D == 3 ? N1 : 1};
+
+    // ---- volume: grad_xi u at the Gauss points, flux w det J J^-1 J^-T grad_xi u, test
+    for (int a = 0; a < D; ++a) {
+        contract<D>(U, ec, 0, a == 0 ? sD : sV, N1, false, N1, T1, false);
+        if constexpr (D == 2) {
+            contract<D>(T1, ec, 1, a == 1 ? sD : sV, N1, false, N1, G[a], false);
+        } else {
+            contract<D>(T1, ec, 1, a == 1 ? sD : sV, N1, false, N1, T2, false);
+            contract<D>(T2, ec, 2, a == 2 ? sD : sV, N1, false, N1, G[a], false);
+        }
+    }
+    for (int p = t; p < NC; p += blockDim.x) {
+        const int q[3] = {p % N1, (p / N1) % N1, p / (N1 * N1)};
+        double xi[D], w = 1.0;
+        for (int a = 0; a < D; ++a) {
+            xi[a] = sxq[q[a]];
+            w *= swq[q[a]];
+        }
+        double Ji[D][D];
+        const double det = jacobian_inverse<D>(X, xi, Ji);
+        double gr[D], fl[D];
+        for (int a = 0; a < D; ++a) gr[a] = G[a][p];
+        // physical gradient J^-T gr, then back: flux_a = w det sum_b Ji[a][b] (J^-T gr)_b
+        double ph[D];
+        for (int b = 0; b < D; ++b) {
+            ph[b] = 0.0;
+            for (int a = 0; a < D; ++a) ph[b] += Ji[a][b] * gr[a];
+        }
+        for (int a = 0; a < D; ++a) {
+            fl[a] = 0.0;
+            for (int b = 0; b < D; ++b) fl[a] += Ji[a][b] * ph[b];
+            fl[a] *= w * det;
+        }
+        for (int a = 0; a < D; ++a) G[a][p] = fl[a];
+    }
+    __syncthreads();
+    for (int a = 0; a < D; ++a) {
+        if constexpr (D == 2) {
+            contract<D>(G[a], ec, 0, a == 0 ? sD : sV, N1, true, N1, T1, false);
+            contract<D>(T1, ec, 1, a == 1 ? sD : sV, N1, true, N1, Y, true);
+        } else {
+            contract<D>(G[a], ec, 0, a == 0 ? sD : sV, N1, true, N1, T1, false);
+            contract<D>(T1, ec, 1, a == 1 ? sD : sV, N1, true, N1, T2, false);
+            contract<D>(T2, ec, 2, a == 2 ? sD : sV, N1, true, N1, Y, true);
+        }
+    }
+
+    // ---- faces
+    const int cc[3] = {(int)(cell % g.m[0]), (int)((cell / g.m[0]) % g.m[1]),
+                       (int)(cell / ((int64_t)g.m[0] * g.m[1]))};
+    for (int tt = 0; tt < D; ++tt)
+        for (int side = 0; side < 2; ++side) {
+            const bool interior = side == 0 ? cc[tt] > 0 : cc[tt] < g.m[tt] - 1;
+            int64_t nb = -1;
+            if (interior) {
+                int64_t st = 1;
+                for (int a = 0; a < tt; ++a) st *= g.m[a];
+                nb = cell + (side == 0 ? -st : st);
+                load_corners<D>(g, nb, Xn);
+                for (int e2 = t; e2 < NC; e2 += blockDim.x) Un[e2] = x[nb * NC + e2];
+                __syncthreads();
+            }
+            // traces: layer tensors have extent 1 along tt
+            int el[3] = {N1, N1, D == 3 ? N1 : 1};
+            el[tt] = 1;
+            for (int sd = 0; sd < (interior ? 2 : 1); ++sd) {
+                const double *Us = sd == 0 ? U : Un;
+                const int s_here = sd == 0 ? side : 1 - side;
+                const double *dvec = sde + s_here * N1;
+                // value layer (the Gauss-Lobatto node layer on the face) into T1,
+                // normal derivative layer sum_i phi_i'(s) u[.., i, ..] into T2
+                contract<D>(Us, ec, tt, dvec, 0, false, 1, T2, false);
+                {
+                    const int lay = s_here * (N1 - 1);
+                    const int tot = NC / N1;
+                    for (int p = t; p < tot; p += blockDim.x) {
+                        // p enumerates the layer (extent 1 along tt)
+                        int o[3] = {p % el[0], (p / el[0]) % el[1], p / (el[0] * el[1])};
+                        o[tt] = lay;
+                        T1[p] = Us[o[0] + N1 * (o[1] + N1 * o[2])];
+                    }
+                    __syncthreads();
+                }
+                // interpolate along the tangential axes: values, normal derivative,
+                // tangential derivatives
+                const int ta = tt == 0 ? 1 : 0, tb = D == 3 ? (tt == 2 ? 1 : 2) : -1;
+                int e1[3] = {el[0], el[1], el[2]};
+                int e2x[3] = {el[0], el[1], el[2]};
+                e2x[ta] = N1;
+                double *dst_v = Fv[sd];
+                double *dst_n = Fg[sd][tt];
+                if constexpr (D == 2) {
+                    contract<D>(T1, e1, ta, sV, N1, false, N1, dst_v, false);
+                    contract<D>(T2, e1, ta, sV, N1, false, N1, dst_n, false);
+                    contract<D>(T1, e1, ta, sD, N1, false, N1, Fg[sd][ta], false);
+                } else {
+                    // values and normal derivative: V along ta then tb
+                    contract<D>(T1, e1, ta, sV, N1, false, N1, G[0], false);
+                    contract<D>(G[0], e2x, tb, sV, N1, false, N1, dst_v, false);
+                    contract<D>(T2, e1, ta, sV, N1, false, N1, G[0], false);
+                    contract<D>(G[0], e2x, tb, sV, N1, false, N1, dst_n, false);
+                    // tangential derivative along ta: D along ta, V along tb
+                    contract<D>(T1, e1, ta, sD, N1, false, N1, G[0], false);
+                    contract<D>(G[0], e2x, tb, sV, N1, false, N1, Fg[sd][ta], false);
+                    // along tb: V along ta, D along tb
+                    contract<D>(T1, e1, ta, sV, N1, false, N1, G[0], false);
+                    contract<D>(G[0], e2x, tb, sD, N1, false, N1, Fg[sd][tb], false);
+                }
+            }
+            // pointwise face terms: coefficients of phi_i and of grad_xi phi_i
+            const double pen = g.pen[cell * 2 * D + 2 * tt + side];
+            for (int p = t; p < NF; p += blockDim.x) {
+                int o[3] = {p % el[0], (p / el[0]) % el[1], p / (el[0] * el[1])};
+                double xi[D], xin[D], wf = 1.0;
+                for (int a = 0; a < D; ++a) {
+                    if (a == tt) {
+                        xi[a] = side;
+                        xin[a] = 1 - side;
+                    } else {
+                        xi[a] = xin[a] = sxq[o[a]];
+                        wf *= swq[o[a]];
+                    }
+                }
+                double Ji[D][D];
+                const double det = jacobian_inverse<D>(X, xi, Ji);
+                double nrm = 0.0;
+                for (int b = 0; b < D; ++b) nrm += Ji[tt][b] * Ji[tt][b];
+                nrm = sqrt(nrm);
+                const double sgn = side ? 1.0 : -1.0;
+                double n[D];
+                for (int b = 0; b < D; ++b) n[b] = sgn * Ji[tt][b] / nrm;
+                const double dS = wf * fabs(det) * nrm;
+                double dnm = 0.0;  // normal derivative of u on this side
+                for (int b = 0; b < D; ++b) {
+                    double ph = 0.0;
+                    for (int a = 0; a < D; ++a) ph += Ji[a][b] * Fg[0][a][p];
+                    dnm += ph * n[b];
+                }
+                double cv, jmp;
+                if (interior) {
+                    double Jn[D][D];
+                    (void)jacobian_inverse<D>(Xn, xin, Jn);
+                    double dnp = 0.0;
+                    for (int b = 0; b < D; ++b) {
+                        double ph = 0.0;
+                        for (int a = 0; a < D; ++a) ph += Jn[a][b] * Fg[1][a][p];
+                        dnp += ph * n[b];
+                    }
+                    jmp = Fv[0][p] - Fv[1][p];
+                    cv = dS * (pen * jmp - 0.5 * (dnm + dnp));
+                    jmp *= 0.5;
+                } else {
+                    jmp = Fv[0][p];
+                    cv = dS * (pen * jmp - dnm);
+                }
+                // - jmp dS n . grad phi_i = grad_xi phi_i . (J^-1 (-jmp dS n))
+                Cv[p] = cv;
+                for (int a = 0; a < D; ++a) {
+                    double s2 = 0.0;
+                    for (int b = 0; b < D; ++b) s2 += Ji[a][b] * n[b];
+                    Cg[a][p] = -jmp * dS * s2;
+                }
+            }
+            __syncthreads();
+            // test: value and tangential gradient terms land on the node layer of
+            // the face, the normal gradient term spreads over the layers with
+            // phi_i'(side)
+            {
+                const int ta = tt == 0 ? 1 : 0, tb = D == 3 ? (tt == 2 ? 1 : 2) : -1;
+                int e1[3] = {el[0], el[1], el[2]};  // layer extents (N1 on tangential axes)
+                double *L = T1;                        // layer accumulator
+                if constexpr (D == 2) {
+                    contract<D>(Cv, e1, ta, sV, N1, true, N1, L, false);
+                    contract<D>(Cg[ta], e1, ta, sD, N1, true, N1, L, true);
+                    contract<D>(Cg[tt], e1, ta, sV, N1, true, N1, T2, false);
+                } else {
+                    contract<D>(Cv, e1, ta, sV, N1, true, N1, G[0], false);
+                    contract<D>(G[0], e1, tb, sV, N1, true, N1, L, false);
+                    contract<D>(Cg[ta], e1, ta, sD, N1, true, N1, G[0], false);
+                    contract<D>(G[0], e1, tb, sV, N1, true, N1, L, true);
+                    contract<D>(Cg[tb], e1, ta, sV, N1, true, N1, G[0], false);
+                    contract<D>(G[0], e1, tb, sD, N1, true, N1, L, true);
+                    contract<D>(Cg[tt], e1, ta, sV, N1, true, N1, G[0], false);
+                    contract<D>(G[0], e1, tb, sV, N1, true, N1, T2, false);
+                }
+                const double *dvec = sde + side * N1;
+                const int lay = side * (N1 - 1);
+                for (int p = t; p < NC; p += blockDim.x) {
+                    int o[3] = {p % N1, (p / N1) % N1, p / (N1 * N1)};
+                    const int it = o[tt];
+                    o[tt] = 0;
+                    const int lp = o[0] + el[0] * (o[1] + el[1] * o[2]);
+                    double add = dvec[it] * T2[lp];
+                    if (it == lay) add += L[lp];
+                    Y[p] += add;
+                }
+                __syncthreads();
+            }
+        }
+    for (int e2 = t; e2 < NC; e2 += blockDim.x) {
+        const int64_t gi = cell * NC + e2;
+        y[gi] = RES ? bvec[gi] - Y[e2] : Y[e2];
+    }
+}
+
+// x += omega sum_K R_K^T Atilde_K^-1 R_K r with the surrogate tables of each
+// cell: (S_d x .. x S_1) diag(1 / sum_t lambda_t) (S_d x .. x S_1)^T.
+template <int D, int N1>
+__global__ void __launch_bounds__(kMapThreads)
+k_mapped_surrogate(MappedView g, double omega, const double *__restrict__ r, double *__restrict__ x) {
+    constexpr int NC = D == 2 ? N1 * N1 : N1 * N1 * N1;
+    __shared__ double A[NC], B[NC];
+    __shared__ double S[D][N1 * N1], L[D][N1];
+    const int64_t cell = blockIdx.x;
+    const int t = threadIdx.x;
+    for (int e2 = t; e2 < D * N1 * N1; e2 += blockDim.x) S[e2 / (N1 * N1)][e2 % (N1 * N1)] = g.S[cell * D * N1 * N1 + e2];
+    for (int e2 = t; e2 < D * N1; e2 += blockDim.x) L[e2 / N1][e2 % N1] = g.lam[cell * D * N1 + e2];
+    for (int e2 = t; e2 < NC; e2 += blockDim.x) A[e2] = r[cell * NC + e2];
+    __syncthreads();
+    const int ec[3] = {N1, N1, D == 3 ? N1 : 1};
+    // forward: out_m = sum_i S[i][m] in_i along every axis
+    contract<D>(A, ec, 0, S[0], N1, true, N1, B, false);
+    contract<D>(B, ec, 1, S[1], N1, true, N1, A, false);
+    double *cur = A, *oth = B;
+    if constexpr (D == 3) {
+        contract<D>(A, ec, 2, S[2], N1, true, N1, B, false);
+        cur = B;
+        oth = A;
+    }
+    for (int p = t; p < NC; p += blockDim.x) {
+        const int m[3] = {p % N1, (p / N1) % N1, p / (N1 * N1)};
+        double lam = 0.0;
+        for (int a = 0; a < D; ++a) lam += L[a][m[a]];
+        cur[p] *= omega / lam;
+    }
+    __syncthreads();
+    // backward: out_i = sum_m S[i][m] in_m
+    contract<D>(cur, ec, 0, S[0], N1, false, N1, oth, false);
+    contract<D>(oth, ec, 1, S[1], N1, false, N1, cur, false);
+    double *res = cur;
+    if constexpr (D == 3) {
+        contract<D>(cur, ec, 2, S[2], N1, false, N1, oth, false);
+        res = oth;
+    }
+    for (int e2 = t; e2 < NC; e2 += blockDim.x) x[cell * NC + e2] += res[e2];
+}
+
+template <int D, int N1>
+static fts_status launch_mapped_op(const fts_mapped_level *lv, const double *x, const double *b, double *y,
+                                   bool res, hipStream_t st) {
+    const dim3 grid((unsigned)lv->ncells), block(kMapThreads);
+    if (res)
+        k_mapped_operator<D, N1, true><<<grid, block, 0, st>>>(lv->view, x, b, y);
+    else
+        k_mapped_operator<D, N1, false><<<grid, block, 0, st>>>(lv->view, x, b, y);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FTS_OK : hip_fail(e, "k_mapped_operator launch");
+}
+
+template <int D, int N1>
+static fts_status launch_mapped_sur(const fts_mapped_level *lv, double omega, const double *r, double *x,
+                                    hipStream_t st) {
+    k_mapped_surrogate<D, N1><<<dim3((unsigned)lv->ncells), dim3(kMapThreads), 0, st>>>(lv->view, omega, r, x);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FTS_OK : hip_fail(e, "k_mapped_surrogate launch");
+}
+
+constexpr int kMapMaxN1 = 8;  // k <= 7
+
+template <int D, int N1 = 2>
+static fts_status dispatch_mapped(const fts_mapped_level *lv, int what, double omega, const double *x,
+                                  const double *b, double *y, hipStream_t st) {
+    if constexpr (N1 > kMapMaxN1) {
+        return fail(FTS_E_UNSUPPORTED, "mapped meshes: degree above 7");
+    } else {
+        if (lv->n1 != N1) return dispatch_mapped<D, N1 + 1>(lv, what, omega, x, b, y, st);
+        if (what == 2) return launch_mapped_sur<D, N1>(lv, omega, x, y, st);
+        return launch_mapped_op<D, N1>(lv, x, b, y, what == 1, st);
+    }
+}
+
+static fts_status run_mapped(const fts_mapped_level *lv, int what, double omega, const double *x, const double *b,
+                             double *y, hipStream_t st) {
+    if (lv->ncells == 0) return FTS_OK;
+    return lv->dim == 2 ? dispatch_mapped<2>(lv, what, omega, x, b, y, st)
+                        : dispatch_mapped<3>(lv, what, omega, x, b, y, st);
+}
+
+// ---- host geometry (FP64): multilinear map, cell volumes, face areas
+static void host_jacobian(int d, const double *X, const double *xi, double *J) {
+    for (int i = 0; i < d * d; ++i) J[i] = 0.0;
+    for (int cidx = 0; cidx < (1 << d); ++cidx)
+        for (int a = 0; a < d; ++a) {
+            double dN = ((cidx >> a) & 1) ? 1.0 : -1.0;
+            for (int a2 = 0; a2 < d; ++a2)
+                if (a2 != a) dN *= ((cidx >> a2) & 1) ? xi[a2] : 1.0 - xi[a2];
+            for (int b = 0; b < d; ++b) J[b * d + a] += dN * X[cidx * d + b];
+        }
+}
+
+static double host_det_inv(int d, const double *J, double *Ji) {
+    if (d == 2) {
+        const double det = J[0] * J[3] - J[1] * J[2];
+        Ji[0] = J[3] / det;
+        Ji[1] = -J[1] / det;
+        Ji[2] = -J[2] / det;
+        Ji[3] = J[0] / det;
+        return det;
+    }
+    const double c00 = J[4] * J[8] - J[5] * J[7], c01 = J[5] * J[6] - J[3] * J[8], c02 = J[3] * J[7] - J[4] * J[6];
+    const double det = J[0] * c00 + J[1] * c01 + J[2] * c02;
+    Ji[0] = c00 / det;
+    Ji[3] = c01 / det;
+    Ji[6] = c02 / det;
+    Ji[1] = (J[2] * J[7] - J[1] * J[8]) / det;
+    Ji[4] = (J[0] * J[8] - J[2] * J[6]) / det;
+    Ji[7] = (J[1] * J[6] - J[0] * J[7]) / det;
+    Ji[2] = (J[1] * J[5] - J[2] * J[4]) / det;
+    Ji[5] = (J[2] * J[3] - J[0] * J[5]) / det;
+    Ji[8] = (J[0] * J[4] - J[1] * J[3]) / det;
+    return det;
+}
+
+}  // namespace fts
+
+using namespace fts;
+
+extern "C" {
+
+fts_status fts_mapped_level_create(const fts_mapped_desc *desc, fts_mapped_level **out) {
+    if (!desc || !out || !desc->vertices) return fail(FTS_E_INVAL, "fts_mapped_level_create: NULL argument");
+    *out = nullptr;
+    const int d = desc->dim;
+    if (d != 2 && d != 3) return fail(FTS_E_UNSUPPORTED, "mapped meshes: dim must be 2 or 3");
+    if (desc->degree < 1 || desc->degree > kMapMaxN1 - 1)
+        return fail(FTS_E_UNSUPPORTED, "mapped meshes: degree must be in 1..7");
+    if (!(desc->penalty_factor > 0.0) || !std::isfinite(desc->penalty_factor))
+        return fail(FTS_E_INVAL, "penalty_factor must be positive");
+    auto *lv = new fts_mapped_level();
+    lv->dim = d;
+    lv->k = desc->degree;
+    lv->n1 = desc->degree + 1;
+    lv->gamma_hat = desc->penalty_factor;
+    lv->ncells = 1;
+    int64_t nverts = 1;
+    for (int a = 0; a < 3; ++a) {
+        lv->m[a] = a < d ? desc->ncells[a] : 1;
+        if (lv->m[a] < 1) {
+            delete lv;
+            return fail(FTS_E_INVAL, "ncells must be >= 1");
+        }
+        lv->ncells *= lv->m[a];
+        if (a < d) nverts *= lv->m[a] + 1;
+    }
+    const int n1 = lv->n1, nc = d == 2 ? n1 * n1 : n1 * n1 * n1;
+    lv->ndofs = lv->ncells * nc;
+    const double *V0 = desc->vertices;
+    for (int64_t i = 0; i < nverts * d; ++i)
+        if (!std::isfinite(V0[i])) {
+            delete lv;
+            return fail(FTS_E_INVAL, "vertex coordinates must be finite");
+        }
+    std::vector<double> xq, wq, Vb, Db;
+    gauss_basis(lv->k, xq, wq, Vb, Db);
+    Ref1D ref;
+    ref.build(lv->k);
+    const int64_t nce = lv->ncells;
+    auto corners = [&](int64_t cell, double *X) {
+        const int c[3] = {(int)(cell % lv->m[0]), (int)((cell / lv->m[0]) % lv->m[1]),
+                          (int)(cell / ((int64_t)lv->m[0] * lv->m[1]))};
+        for (int cidx = 0; cidx < (1 << d); ++cidx) {
+            int v[3] = {0, 0, 0};
+            for (int a = 0; a < d; ++a) v[a] = c[a] + ((cidx >> a) & 1);
+            const int64_t vi = v[0] + (int64_t)(lv->m[0] + 1) * (v[1] + (int64_t)(lv->m[1] + 1) * v[2]);
+            for (int b = 0; b < d; ++b) X[cidx * d + b] = V0[vi * d + b];
+        }
+    };
+    // cell volumes and face areas (the face between a cell and its upper
+    // neighbour is measured from the lower cell; boundary faces from their cell)
+    std::vector<double> vol(nce), area(nce * 2 * d, 0.0);
+    double X[24], J[9], Ji[9];
+    for (int64_t cell = 0; cell < nce; ++cell) {
+        corners(cell, X);
+        double v = 0.0;
+        for (int p = 0; p < nc; ++p) {
+            const int q[3] = {p % n1, (p / n1) % n1, p / (n1 * n1)};
+            double xi[3], w = 1.0;
+            for (int a = 0; a < d; ++a) {
+                xi[a] = xq[q[a]];
+                w *= wq[q[a]];
+            }
+            host_jacobian(d, X, xi, J);
+            const double det = host_det_inv(d, J, Ji);
+            if (!(det > 0.0)) {
+                delete lv;
+                return fail(FTS_E_INVAL, "a cell map is not orientation preserving (det J <= 0)");
+            }
+            v += w * det;
+        }
+        vol[cell] = v;
+        for (int t = 0; t < d; ++t)
+            for (int side = 0; side < 2; ++side) {
+                double A = 0.0;
+                const int nf = nc / n1;
+                for (int p = 0; p < nf; ++p) {
+                    int o[3] = {0, 0, 0}, r2 = p;
+                    double xi[3], w = 1.0;
+                    for (int a = 0; a < d; ++a) {
+                        if (a == t) {
+                            xi[a] = side;
+                            continue;
+                        }
+                        o[a] = r2 % n1;
+                        r2 /= n1;
+                        xi[a] = xq[o[a]];
+                        w *= wq[o[a]];
+                    }
+                    host_jacobian(d, X, xi, J);
+                    const double det = host_det_inv(d, J, Ji);
+                    double nrm = 0.0;
+                    for (int b = 0; b < d; ++b) nrm += Ji[t * d + b] * Ji[t * d + b];
+                    A += w * std::fabs(det) * std::sqrt(nrm);
+                }
+                area[cell * 2 * d + 2 * t + side] = A;
+            }
+    }
+    // penalty coefficient of each face seen from each cell: gamma_e / 2 inside
+    // (gamma_e = gamma_hat k (k+1) (1/h- + 1/h+), h = |K| / |F|), gamma_e on the boundary
+    std::vector<double> pen(nce * 2 * d);
+    const double gk = lv->gamma_hat * lv->k * (lv->k + 1.0);
+    for (int64_t cell = 0; cell < nce; ++cell) {
+        const int c[3] = {(int)(cell % lv->m[0]), (int)((cell / lv->m[0]) % lv->m[1]),
+                          (int)(cell / ((int64_t)lv->m[0] * lv->m[1]))};
+        int64_t st = 1;
+        for (int t = 0; t < d; ++t) {
+            for (int side = 0; side < 2; ++side) {
+                const bool interior = side == 0 ? c[t] > 0 : c[t] < lv->m[t] - 1;
+                double p;
+                if (interior) {
+                    const int64_t nb = cell + (side == 0 ? -st : st);
+                    const int64_t lower = side == 0 ? nb : cell;
+                    const double F = area[lower * 2 * d + 2 * t + 1];
+                    p = 0.5 * gk * (F / vol[cell] + F / vol[nb]);
+                } else {
+                    p = gk * 2.0 * area[cell * 2 * d + 2 * t + side] / vol[cell];
+                }
+                pen[cell * 2 * d + 2 * t + side] = p;
+            }
+            st *= lv->m[t];
+        }
+    }
+    // surrogate boxes (eq. avglength) and their 1-D eigenpairs per cell and axis
+    lv->hbar.assign(nce * d, 0.0);
+    for (int64_t cell = 0; cell < nce; ++cell) {
+        corners(cell, X);
+        for (int t = 0; t < d; ++t) {
+            double s = 0.0;
+            int cnt = 0;
+            for (int cidx = 0; cidx < (1 << d); ++cidx) {
+                if ((cidx >> t) & 1) continue;
+                const int c2 = cidx | (1 << t);
+                double l2 = 0.0;
+                for (int b = 0; b < d; ++b) l2 += (X[c2 * d + b] - X[cidx * d + b]) * (X[c2 * d + b] - X[cidx * d + b]);
+                s += std::sqrt(l2);
+                ++cnt;
+            }
+            lv->hbar[cell * d + t] = s / cnt;
+        }
+    }
+    std::vector<double> Sall(nce * d * n1 * n1), Lall(nce * d * n1);
+    std::vector<double> A1(n1 * n1), M1(n1 * n1);
+    for (int64_t cell = 0; cell < nce; ++cell) {
+        const int c[3] = {(int)(cell % lv->m[0]), (int)((cell / lv->m[0]) % lv->m[1]),
+                          (int)(cell / ((int64_t)lv->m[0] * lv->m[1]))};
+        int64_t st = 1;
+        for (int t = 0; t < d; ++t) {
+            const double h = lv->hbar[cell * d + t];
+            const double hl = c[t] > 0 ? lv->hbar[(cell - st) * d + t] : -1.0;
+            const double hr = c[t] < lv->m[t] - 1 ? lv->hbar[(cell + st) * d + t] : -1.0;
+            ref.cell_operator(h, hl, hr, lv->gamma_hat, A1.data());
+            for (int i = 0; i < n1 * n1; ++i) M1[i] = h * ref.Mhat[i];
+            const fts_status s2 = sym_gen_eig(n1, A1.data(), M1.data(), &Sall[(cell * d + t) * n1 * n1],
+                                              &Lall[(cell * d + t) * n1]);
+            if (s2 != FTS_OK) {
+                delete lv;
+                return s2;
+            }
+            st *= lv->m[t];
+        }
+    }
+    // upload: vertices, V, D, xq, wq, end derivatives, penalties, S, lambda
+    std::vector<double> dend(2 * n1);
+    for (int i = 0; i < n1; ++i) {
+        dend[i] = ref.d0[i];
+        dend[n1 + i] = ref.d1[i];
+    }
+    const size_t sizes[9] = {(size_t)(nverts * d), (size_t)n1 * n1, (size_t)n1 * n1, (size_t)n1, (size_t)n1,
+                             (size_t)2 * n1, pen.size(), Sall.size(), Lall.size()};
+    const double *srcs[9] = {V0, Vb.data(), Db.data(), xq.data(), wq.data(), dend.data(), pen.data(), Sall.data(),
+                             Lall.data()};
+    size_t total = 0;
+    for (size_t s2 : sizes) total += s2;
+    if (hipMalloc(&lv->d_tab, total * sizeof(double)) != hipSuccess) {
+        delete lv;
+        return fail(FTS_E_HIP, "hipMalloc of the mapped-mesh tables failed");
+    }
+    const double *ptrs[9];
+    size_t off = 0;
+    for (int i = 0; i < 9; ++i) {
+        if (hipMemcpy(lv->d_tab + off, srcs[i], sizes[i] * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(lv->d_tab);
+            delete lv;
+            return fail(FTS_E_HIP, "upload of the mapped-mesh tables failed");
+        }
+        ptrs[i] = lv->d_tab + off;
+        off += sizes[i];
+    }
+    MappedView &vw = lv->view;
+    for (int a = 0; a < 3; ++a) vw.m[a] = lv->m[a];
+    vw.ncells = nce;
+    vw.verts = ptrs[0];
+    vw.V = ptrs[1];
+    vw.D = ptrs[2];
+    vw.xq = ptrs[3];
+    vw.wq = ptrs[4];
+    vw.dend = ptrs[5];
+    vw.pen = ptrs[6];
+    vw.S = ptrs[7];
+    vw.lam = ptrs[8];
+    *out = lv;
+    return FTS_OK;
+}
+
+fts_status fts_mapped_level_destroy(fts_mapped_level *lv) {
+    if (!lv) return FTS_OK;
+    if (lv->d_tab) (void)hipFree(lv->d_tab);
+    delete lv;
+    return FTS_OK;
+}
+
+int64_t fts_mapped_level_ndofs(const fts_mapped_level *lv) { return lv ? lv->ndofs : -1; }
+
+fts_status fts_mapped_surrogate_widths(const fts_mapped_level *lv, double *hbar) {
+    if (!lv || !hbar) return fail(FTS_E_INVAL, "fts_mapped_surrogate_widths: NULL argument");
+    std::copy(lv->hbar.begin(), lv->hbar.end(), hbar);
+    return FTS_OK;
+}
+
+fts_status fts_mapped_apply_operator(const fts_mapped_level *lv, const double *x, double *y, void *stream) {
+    if (!lv || !x || !y) return fail(FTS_E_INVAL, "fts_mapped_apply_operator: NULL argument");
+    if (x == y) return fail(FTS_E_INVAL, "fts_mapped_apply_operator: x and y must not alias");
+    return run_mapped(lv, 0, 0.0, x, nullptr, y, reinterpret_cast<hipStream_t>(stream));
+}
+
+fts_status fts_mapped_residual(const fts_mapped_level *lv, const double *b, const double *x, double *r,
+                               void *stream) {
+    if (!lv || !b || !x || !r) return fail(FTS_E_INVAL, "fts_mapped_residual: NULL argument");
+    if (r == x) return fail(FTS_E_INVAL, "fts_mapped_residual: r must not alias x");
+    return run_mapped(lv, 1, 0.0, x, b, r, reinterpret_cast<hipStream_t>(stream));
+}
+
+fts_status fts_mapped_schwarz_apply(const fts_mapped_level *lv, double omega, const double *r, double *x,
+                                    void *stream) {
+    if (!lv || !r || !x) return fail(FTS_E_INVAL, "fts_mapped_schwarz_apply: NULL argument");
+    if (r == x) return fail(FTS_E_INVAL, "fts_mapped_schwarz_apply: r and x must not alias");
+    return run_mapped(lv, 2, omega, r, nullptr, x, reinterpret_cast<hipStream_t>(stream));
+}
+
+size_t fts_mapped_smooth_ws_bytes(const fts_mapped_level *lv) {
+    return lv ? (size_t)lv->ndofs * sizeof(double) : 0;
+}
+
+fts_status fts_mapped_schwarz_smooth(const fts_mapped_level *lv, double omega, const double *b, double *x,
+                                     int32_t nsweeps, void *ws, size_t ws_bytes, void *stream) {
+    if (!lv || !b || !x || !ws) return fail(FTS_E_INVAL, "fts_mapped_schwarz_smooth: NULL argument");
+    if (ws_bytes < fts_mapped_smooth_ws_bytes(lv))
+        return fail(FTS_E_SIZE, "fts_mapped_schwarz_smooth: workspace too small");
+    double *r = static_cast<double *>(ws);
+    const hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    for (int it = 0; it < nsweeps; ++it) {
+        fts_status s = run_mapped(lv, 1, 0.0, x, b, r, st);
+        if (s != FTS_OK) return s;
+        s = run_mapped(lv, 2, omega, r, nullptr, x, st);
+        if (s != FTS_OK) return s;
+    }
+    return FTS_OK;
+}
+
+}  // extern "C"

@@ -126,6 +126,16 @@ static void lagrange_at(const std::vector<double> &nodes, double x, double *val,
     }
 }
 
+void gauss_basis(int k, std::vector<double> &xq, std::vector<double> &wq, std::vector<double> &V,
+                 std::vector<double> &D) {
+    const int n1 = k + 1;
+    const std::vector<double> nodes = gll_nodes_unit(k);
+    gauss_unit(n1, xq, wq);
+    V.assign(n1 * n1, 0.0);
+    D.assign(n1 * n1, 0.0);
+    for (int q = 0; q < n1; ++q) lagrange_at(nodes, xq[q], &V[q * n1], &D[q * n1]);
+}
+
 void Ref1D::build(int degree) {
     k = degree;
     n1 = k + 1;
