@@ -18,12 +18,17 @@
  *   Streams   every device call is asynchronous on the given stream (a
  *             hipStream_t passed as void*; NULL = default stream).  No call
  *             synchronises the device unless documented.
- *   Ownership handles (fts_level, fts_eigs, fts_hierarchy) own host metadata
- *             and the device tables they allocate at creation (1-D matrices,
- *             eigenvectors, level vectors, coarse factor); *_destroy frees them
- *             and accepts NULL.  Hot calls (apply, residual, smooth, vcycle,
- *             transfers) never allocate; the smoother's residual buffer is a
- *             caller-provided workspace.
+ *   Ownership all device memory comes from the caller: vectors and workspaces
+ *             are passed in, and the tables of the handles (1-D matrices,
+ *             eigenvectors, level vectors, staging buffers, coarse factors,
+ *             batch queues, and the BLAS workspace of the coarse setup) are
+ *             obtained at creation from the allocator registered with
+ *             fts_set_allocator (the Python binding registers torch's
+ *             caching allocator); the library never calls hipMalloc.
+ *             Handles (fts_level, fts_eigs, fts_hierarchy, fts_batch,
+ *             fts_mapped_level) return their memory to that allocator in
+ *             *_destroy, which accepts NULL.  Hot calls (apply, residual,
+ *             smooth, vcycle, transfers) never allocate.
  *   Errors    every function returns fts_status (0 = FTS_OK, < 0 error); the
  *             last error message of the calling thread is available through
  *             fts_last_error.  No exception crosses the ABI, nothing aborts.
@@ -76,6 +81,17 @@ typedef struct fts_mesh_desc {
 typedef struct fts_level fts_level;         /* one mesh with its operator tables */
 typedef struct fts_eigs fts_eigs;           /* 1-D eigenpairs of all subdomains of a level */
 typedef struct fts_hierarchy fts_hierarchy; /* multigrid hierarchy with coarse LU */
+
+/* Device memory allocator of the library: alloc(bytes, ctx) returns device
+ * memory of the current device (aligned to 256 bytes, NULL on failure),
+ * release(ptr, ctx) takes it back.  Every device allocation of the library
+ * goes through it (at handle creation only); with none registered, handle
+ * creation fails with FTS_E_HIP.  Register before creating handles and keep
+ * it until they are destroyed (their memory is returned to the allocator
+ * registered at that time).  Both functions NULL unregisters. */
+typedef void *(*fts_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*fts_free_fn)(void *ptr, void *ctx);
+fts_status fts_set_allocator(fts_alloc_fn alloc, fts_free_fn release, void *ctx);
 
 /* Library version string (static storage). */
 const char *fts_version(void);

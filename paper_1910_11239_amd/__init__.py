@@ -31,7 +31,10 @@ class MeshDesc(ctypes.Structure):
 
 
 _VP, _I32, _I64, _D, _SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+_ALLOC_T = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_T = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 _SIGS = {
+    "fts_set_allocator": (_I32, [_ALLOC_T, _FREE_T, _VP]),
     "fts_version": (ctypes.c_char_p, []),
     "fts_last_error": (_I32, [ctypes.c_char_p, _SZ]),
     "fts_level_create": (_I32, [_VP, _VP]),
@@ -88,6 +91,36 @@ _SIGS = {
 }
 
 
+# Device memory of the library's handles is torch memory: the library asks the
+# allocator registered here (fts_set_allocator), which keeps each block as a
+# torch uint8 tensor until the library releases it.
+_live = {}
+
+
+def _torch_alloc(nbytes, ctx):
+    try:
+        import torch
+        t = torch.empty(int(nbytes), dtype=torch.uint8, device=torch.device("cuda", torch.cuda.current_device()))
+    except Exception:  # reported to the caller of the library as an allocation failure
+        return None
+    _live[t.data_ptr()] = t
+    return t.data_ptr()
+
+
+def _torch_free(ptr, ctx):
+    if ptr is not None and _live is not None:
+        _live.pop(ptr, None)
+
+
+_ALLOC_CB = _ALLOC_T(_torch_alloc)
+_FREE_CB = _FREE_T(_torch_free)
+
+
+def device_bytes_held():
+    """Bytes of torch memory the library's handles hold."""
+    return sum(t.numel() for t in _live.values())
+
+
 def lib():
     """The loaded library; raises if it is not built."""
     global _lib
@@ -99,6 +132,8 @@ def lib():
             f = getattr(handle, name)
             f.restype = res
             f.argtypes = args
+        if handle.fts_set_allocator(_ALLOC_CB, _FREE_CB, None) != 0:
+            raise FtsError("fts_set_allocator failed")
         _lib = handle
     return _lib
 

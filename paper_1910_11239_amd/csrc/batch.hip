@@ -262,14 +262,14 @@ fts_status fts_batch_destroy(fts_batch *bt) {
     if (!bt) return FTS_OK;
     for (auto *e : bt->eigs) fts_eigs_destroy(e);
     for (auto *l : bt->levels) fts_level_destroy(l);
-    if (bt->d_meshes) (void)hipFree(bt->d_meshes);
-    if (bt->d_prefix) (void)hipFree(bt->d_prefix);
-    if (bt->d_order) (void)hipFree(bt->d_order);
-    if (bt->d_counter) (void)hipFree(bt->d_counter);
-    if (bt->d_stage) (void)hipFree(bt->d_stage);
+    if (bt->d_meshes) dev_free(bt->d_meshes);
+    if (bt->d_prefix) dev_free(bt->d_prefix);
+    if (bt->d_order) dev_free(bt->d_order);
+    if (bt->d_counter) dev_free(bt->d_counter);
+    if (bt->d_stage) dev_free(bt->d_stage);
     for (auto &g : bt->res_groups)
-        if (g.blocks) (void)hipFree(g.blocks);
-    if (bt->d_gather) (void)hipFree(bt->d_gather);
+        if (g.blocks) dev_free(g.blocks);
+    if (bt->d_gather) dev_free(bt->d_gather);
     delete bt;
     return FTS_OK;
 }
@@ -335,7 +335,7 @@ fts_status fts_batch_create(const fts_mesh_desc *meshes, int32_t nmesh, fts_batc
         }
         if (blocks.empty()) continue;
         fts_batch::Group g{n1, nullptr, (int64_t)blocks.size()};
-        if (hipMalloc(&g.blocks, blocks.size() * sizeof(BatchBlock)) != hipSuccess ||
+        if (dev_malloc(&g.blocks, blocks.size() * sizeof(BatchBlock)) != hipSuccess ||
             hipMemcpy(g.blocks, blocks.data(), blocks.size() * sizeof(BatchBlock), hipMemcpyHostToDevice) != hipSuccess)
             st = fail(FTS_E_HIP, "batch: upload of residual blocks failed");
         bt->res_groups.push_back(g);
@@ -345,7 +345,7 @@ fts_status fts_batch_create(const fts_mesh_desc *meshes, int32_t nmesh, fts_batc
     bt->ngather = (int64_t)gblocks.size();
     auto up = [&](void **dst, const void *src, size_t bytes) {
         if (st != FTS_OK) return;
-        if (hipMalloc(dst, std::max<size_t>(bytes, 8)) != hipSuccess ||
+        if (dev_malloc(dst, std::max<size_t>(bytes, 8)) != hipSuccess ||
             (bytes && hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess))
             st = fail(FTS_E_HIP, "batch: upload failed");
     };
@@ -353,8 +353,8 @@ fts_status fts_batch_create(const fts_mesh_desc *meshes, int32_t nmesh, fts_batc
     up((void **)&bt->d_prefix, prefix.data(), prefix.size() * sizeof(int64_t));
     up((void **)&bt->d_order, order.data(), order.size() * sizeof(int));
     up((void **)&bt->d_gather, gblocks.data(), gblocks.size() * sizeof(BatchBlock));
-    if (st == FTS_OK && (hipMalloc(&bt->d_counter, sizeof(unsigned long long)) != hipSuccess ||
-                         hipMalloc(&bt->d_stage, (size_t)std::max<int64_t>(stage_total, 1) * sizeof(double)) != hipSuccess))
+    if (st == FTS_OK && (dev_malloc(&bt->d_counter, sizeof(unsigned long long)) != hipSuccess ||
+                         dev_malloc(&bt->d_stage, (size_t)std::max<int64_t>(stage_total, 1) * sizeof(double)) != hipSuccess))
         st = fail(FTS_E_HIP, "batch: allocation of the staging buffer failed");
     if (st == FTS_OK) {
         int dev = 0;

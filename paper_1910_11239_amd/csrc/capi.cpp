@@ -120,18 +120,18 @@ fts_status fts_hierarchy_destroy(fts_hierarchy *h) {
     if (!h) return FTS_OK;
     for (auto *e : h->eigs) fts_eigs_destroy(e);
     for (auto *l : h->levels) fts_level_destroy(l);
-    for (auto *p : h->vb) if (p) (void)hipFree(p);
-    for (auto *p : h->vx) if (p) (void)hipFree(p);
-    for (auto *p : h->vr) if (p) (void)hipFree(p);
+    for (auto *p : h->vb) if (p) dev_free(p);
+    for (auto *p : h->vx) if (p) dev_free(p);
+    for (auto *p : h->vr) if (p) dev_free(p);
     coarse_destroy(h->coarse);
     if (h->host_scalars) (void)hipHostFree(h->host_scalars);
     for (auto &v : h->xs)
-        for (auto *p : v) if (p) (void)hipFree(p);
+        for (auto *p : v) if (p) dev_free(p);
     for (auto *vv : {&h->lam, &h->lamb, &h->aq, &h->atr, &h->at})
-        for (auto *p : *vv) if (p) (void)hipFree(p);
-    if (h->apart) (void)hipFree(h->apart);
-    if (h->ared) (void)hipFree(h->ared);
-    if (h->agrad) (void)hipFree(h->agrad);
+        for (auto *p : *vv) if (p) dev_free(p);
+    if (h->apart) dev_free(h->apart);
+    if (h->ared) dev_free(h->ared);
+    if (h->agrad) dev_free(h->agrad);
     if (h->host_grad) (void)hipHostFree(h->host_grad);
     delete h;
     return FTS_OK;
@@ -195,9 +195,9 @@ fts_status fts_hierarchy_create(const fts_mesh_desc *finest, int32_t nlevels, ft
         h->eigs.push_back(eg);
         double *pb = nullptr, *px = nullptr, *pr = nullptr;
         const size_t bytes = (size_t)lv->ndofs * sizeof(double);
-        if (l < nlevels - 1 && (hipMalloc(&pb, bytes) != hipSuccess || hipMalloc(&px, bytes) != hipSuccess))
-            st = fail(FTS_E_HIP, "hipMalloc of level vectors failed");
-        if (st == FTS_OK && hipMalloc(&pr, bytes) != hipSuccess) st = fail(FTS_E_HIP, "hipMalloc of level vectors failed");
+        if (l < nlevels - 1 && (dev_malloc(&pb, bytes) != hipSuccess || dev_malloc(&px, bytes) != hipSuccess))
+            st = fail(FTS_E_HIP, "device allocation of level vectors failed");
+        if (st == FTS_OK && dev_malloc(&pr, bytes) != hipSuccess) st = fail(FTS_E_HIP, "device allocation of level vectors failed");
         h->vb.push_back(pb);
         h->vx.push_back(px);
         h->vr.push_back(pr);
@@ -473,7 +473,7 @@ fts_status fts_hierarchy_enable_adjoint(fts_hierarchy *h) {
     h->xs.assign(L, {});
     int64_t maxcells = 1;
     auto alloc = [&](int64_t n, double **p) {
-        return hipMalloc(p, (size_t)std::max<int64_t>(n, 1) * sizeof(double)) == hipSuccess;
+        return dev_malloc(p, (size_t)std::max<int64_t>(n, 1) * sizeof(double)) == hipSuccess;
     };
     bool ok = true;
     for (int l = 0; l < L && ok; ++l) {

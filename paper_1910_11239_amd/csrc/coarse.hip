@@ -287,19 +287,22 @@ __global__ void __launch_bounds__(256) k_transpose(const double *__restrict__ in
 }
 
 static fts_status rb_check(rocblas_status st, const char *what) {
-    if (st != rocblas_status_success)
+    // (the size statuses answer calls made during a workspace-size query)
+    if (st != rocblas_status_success && st != rocblas_status_size_increased && st != rocblas_status_size_unchanged)
         return fail(FTS_E_HIP, std::string("rocBLAS failure in ") + what + ": " + rocblas_status_to_string(st));
     return FTS_OK;
 }
 
 // Blocked LU without pivoting of the n x n matrix A (column-major, lda = n), in place.
-static fts_status lu_inplace(rocblas_handle h, double *A, int n, hipStream_t stream) {
+static fts_status lu_inplace(rocblas_handle h, double *A, int n, hipStream_t stream, bool query) {
     const double one = 1.0, mone = -1.0;
     for (int k0 = 0; k0 < n; k0 += kNB) {
         const int kb = std::min(kNB, n - k0), n2 = n - k0 - kb;
         double *A11 = A + k0 + (int64_t)k0 * n;
-        k_lu_diag<<<1, 1024, 0, stream>>>(A11, n, kb);
-        COARSE_TRY(check_launch("k_lu_diag"));
+        if (!query) {
+            k_lu_diag<<<1, 1024, 0, stream>>>(A11, n, kb);
+            COARSE_TRY(check_launch("k_lu_diag"));
+        }
         if (n2 == 0) break;
         double *A12 = A + k0 + (int64_t)(k0 + kb) * n;
         double *A21 = A + (k0 + kb) + (int64_t)k0 * n;
@@ -319,19 +322,22 @@ static fts_status lu_inplace(rocblas_handle h, double *A, int n, hipStream_t str
 
 // Replace the factors L, U stored in A (n x n) by inv(L) (strict lower part)
 // and inv(U) (upper part); X is an n x n temporary.
-static fts_status invert_factors(rocblas_handle h, double *A, int n, double *X, hipStream_t stream) {
+static fts_status invert_factors(rocblas_handle h, double *A, int n, double *X, hipStream_t stream, bool query) {
     const double one = 1.0;
     const int64_t nn = (int64_t)n * n;
     const int grid = (int)std::min<int64_t>((nn + 255) / 256, 1 << 20);
     for (int pass = 0; pass < 2; ++pass) {
         const bool lower = pass == 0;
-        k_set_identity<<<grid, 256, 0, stream>>>(X, n);
-        COARSE_TRY(check_launch("k_set_identity"));
+        if (!query) {
+            k_set_identity<<<grid, 256, 0, stream>>>(X, n);
+            COARSE_TRY(check_launch("k_set_identity"));
+        }
         COARSE_TRY(rb_check(rocblas_dtrsm(h, rocblas_side_left, lower ? rocblas_fill_lower : rocblas_fill_upper,
                                        rocblas_operation_none,
                                        lower ? rocblas_diagonal_unit : rocblas_diagonal_non_unit, n, n, &one, A, n,
                                        X, n),
                          "dtrsm (triangular inverse)"));
+        if (query) continue;
         if (lower) k_pack_triangle<true><<<grid, 256, 0, stream>>>(A, X, n);
         else k_pack_triangle<false><<<grid, 256, 0, stream>>>(A, X, n);
         COARSE_TRY(check_launch("k_pack_triangle"));
@@ -339,8 +345,9 @@ static fts_status invert_factors(rocblas_handle h, double *A, int n, double *X, 
     return FTS_OK;
 }
 
-// Block elimination over the slabs (see the top of this file).
-static fts_status factor_slabs(rocblas_handle h, CoarseLU *c, double *X, hipStream_t stream) {
+// Block elimination over the slabs (see the top of this file).  query: only
+// the BLAS calls, inside a rocBLAS workspace-size query (nothing computed).
+static fts_status factor_slabs(rocblas_handle h, CoarseLU *c, double *X, hipStream_t stream, bool query) {
     const int B = c->B;
     const int64_t BB = (int64_t)B * B;
     const double one = 1.0, mone = -1.0;
@@ -351,7 +358,7 @@ static fts_status factor_slabs(rocblas_handle h, CoarseLU *c, double *X, hipStre
             COARSE_TRY(rb_check(rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, B, B, B, &mone,
                                            c->Lo + (i - 1) * BB, B, c->Up + (i - 1) * BB, B, &one, Di, B),
                              "dgemm (slab update)"));
-        COARSE_TRY(lu_inplace(h, Di, B, stream));
+        COARSE_TRY(lu_inplace(h, Di, B, stream, query));
         if (i + 1 < c->nb) {
             COARSE_TRY(rb_check(rocblas_dtrsm(h, rocblas_side_left, rocblas_fill_lower, rocblas_operation_none,
                                            rocblas_diagonal_unit, B, B, &one, Di, B, c->Up + i * BB, B),
@@ -360,8 +367,9 @@ static fts_status factor_slabs(rocblas_handle h, CoarseLU *c, double *X, hipStre
                                            rocblas_diagonal_non_unit, B, B, &one, Di, B, c->Lo + i * BB, B),
                              "dtrsm (Lo)"));
         }
-        COARSE_TRY(invert_factors(h, Di, B, X, stream));
+        COARSE_TRY(invert_factors(h, Di, B, X, stream, query));
     }
+    if (query) return FTS_OK;
     // The substitution kernels read rows: store every block row-major.
     const dim3 tgrid((B + 31) / 32, (B + 31) / 32), tblock(32, 8);
     for (int blk = 0; blk < 3 * c->nb - 2; ++blk) {
@@ -377,7 +385,7 @@ static fts_status factor_slabs(rocblas_handle h, CoarseLU *c, double *X, hipStre
 void coarse_destroy(CoarseLU *c) {
     if (!c) return;
     for (void *p : {(void *)c->D, (void *)c->Lo, (void *)c->Up, (void *)c->y, (void *)c->t})
-        if (p) (void)hipFree(p);
+        if (p) dev_free(p);
     delete c;
 }
 
@@ -398,24 +406,39 @@ fts_status coarse_create(const fts_level *l0, hipStream_t stream, CoarseLU **out
     const size_t blk = (size_t)B * B * sizeof(double);
     double *X = nullptr;
     fts_status st = FTS_OK;
-    if (hipMalloc(&c->D, nb * blk) != hipSuccess ||
-        (nb > 1 && (hipMalloc(&c->Lo, (nb - 1) * blk) != hipSuccess ||
-                    hipMalloc(&c->Up, (nb - 1) * blk) != hipSuccess)) ||
-        hipMalloc(&c->y, c->N * sizeof(double)) != hipSuccess || hipMalloc(&c->t, B * sizeof(double)) != hipSuccess ||
-        hipMalloc(&X, blk) != hipSuccess)
-        st = fail(FTS_E_HIP, "hipMalloc of the coarse factors failed");
+    if (dev_malloc(&c->D, nb * blk) != hipSuccess ||
+        (nb > 1 && (dev_malloc(&c->Lo, (nb - 1) * blk) != hipSuccess ||
+                    dev_malloc(&c->Up, (nb - 1) * blk) != hipSuccess)) ||
+        dev_malloc(&c->y, c->N * sizeof(double)) != hipSuccess || dev_malloc(&c->t, B * sizeof(double)) != hipSuccess ||
+        dev_malloc(&X, blk) != hipSuccess)
+        st = fail(FTS_E_HIP, "device allocation of the coarse factors failed");
     const int64_t nblk = (int64_t)B * B;
     if (st == FTS_OK) st = launch_fill(c->D, nb * nblk, 0.0, stream);
     if (st == FTS_OK && nb > 1) st = launch_fill(c->Lo, (nb - 1) * nblk, 0.0, stream);
     if (st == FTS_OK && nb > 1) st = launch_fill(c->Up, (nb - 1) * nblk, 0.0, stream);
     if (st == FTS_OK) st = launch_assemble_slabs(l0, SlabBlocks{c->D, c->Lo, c->Up, B}, stream);
     rocblas_handle h = nullptr;
+    void *bws = nullptr;
     if (st == FTS_OK && rocblas_create_handle(&h) != rocblas_status_success)
         st = fail(FTS_E_HIP, "rocblas_create_handle failed");
-    if (st == FTS_OK) st = factor_slabs(h, c, X, stream);
+    if (st == FTS_OK) st = rb_check(rocblas_set_stream(h, stream), "rocblas_set_stream");
+    // the BLAS workspace of the factorisation comes from the registered
+    // allocator: size it with a query pass, then hand it to rocBLAS
+    if (st == FTS_OK) st = rb_check(rocblas_start_device_memory_size_query(h), "workspace query");
+    if (st == FTS_OK) {
+        fts_status sq = factor_slabs(h, c, X, stream, true);
+        size_t wsz = 0;
+        const fts_status se = rb_check(rocblas_stop_device_memory_size_query(h, &wsz), "workspace query");
+        st = sq != FTS_OK ? sq : se;
+        if (st == FTS_OK && wsz > 0 && dev_malloc(&bws, wsz) != hipSuccess)
+            st = fail(FTS_E_HIP, "device allocation of the BLAS workspace failed");
+        if (st == FTS_OK && wsz > 0) st = rb_check(rocblas_set_workspace(h, bws, wsz), "rocblas_set_workspace");
+    }
+    if (st == FTS_OK) st = factor_slabs(h, c, X, stream, false);
     if (hipStreamSynchronize(stream) != hipSuccess && st == FTS_OK) st = fail(FTS_E_HIP, "coarse factorisation failed");
     if (h) rocblas_destroy_handle(h);
-    if (X) (void)hipFree(X);
+    dev_free(bws);
+    if (X) dev_free(X);
     if (st != FTS_OK) {
         coarse_destroy(c);
         return st;

@@ -16,6 +16,16 @@ constexpr int kMaxDegree = 9;
 constexpr int kMaxN1 = kMaxDegree + 1;
 
 void set_error(const std::string &msg);
+
+// Device memory of the library comes from the allocator registered with
+// fts_set_allocator (the caller's, e.g. torch's); without one every
+// allocation fails.  dev_free returns memory to it.
+hipError_t dev_malloc_raw(void **p, size_t bytes);
+void dev_free(void *p);
+template <typename T>
+inline hipError_t dev_malloc(T **p, size_t bytes) {
+    return dev_malloc_raw(reinterpret_cast<void **>(p), bytes);
+}
 fts_status fail(fts_status code, const std::string &msg);
 fts_status hip_fail(hipError_t err, const char *what);
 

@@ -660,15 +660,15 @@ fts_status fts_mapped_level_create(const fts_mapped_desc *desc, fts_mapped_level
                              Lall.data()};
     size_t total = 0;
     for (size_t s2 : sizes) total += s2;
-    if (hipMalloc(&lv->d_tab, total * sizeof(double)) != hipSuccess) {
+    if (dev_malloc(&lv->d_tab, total * sizeof(double)) != hipSuccess) {
         delete lv;
-        return fail(FTS_E_HIP, "hipMalloc of the mapped-mesh tables failed");
+        return fail(FTS_E_HIP, "device allocation of the mapped-mesh tables failed");
     }
     const double *ptrs[9];
     size_t off = 0;
     for (int i = 0; i < 9; ++i) {
         if (hipMemcpy(lv->d_tab + off, srcs[i], sizes[i] * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
-            (void)hipFree(lv->d_tab);
+            dev_free(lv->d_tab);
             delete lv;
             return fail(FTS_E_HIP, "upload of the mapped-mesh tables failed");
         }
@@ -693,7 +693,7 @@ fts_status fts_mapped_level_create(const fts_mapped_desc *desc, fts_mapped_level
 
 fts_status fts_mapped_level_destroy(fts_mapped_level *lv) {
     if (!lv) return FTS_OK;
-    if (lv->d_tab) (void)hipFree(lv->d_tab);
+    if (lv->d_tab) dev_free(lv->d_tab);
     delete lv;
     return FTS_OK;
 }

@@ -5,6 +5,7 @@
 #include <array>
 #include <map>
 #include <cmath>
+#include <mutex>
 #include <cstring>
 
 #include "fts_internal.h"
@@ -14,6 +15,42 @@ namespace fts {
 static thread_local std::string g_last_error;
 
 void set_error(const std::string &msg) { g_last_error = msg; }
+
+namespace {
+std::mutex g_alloc_mutex;
+fts_alloc_fn g_alloc_fn = nullptr;
+fts_free_fn g_free_fn = nullptr;
+void *g_alloc_ctx = nullptr;
+}  // namespace
+
+hipError_t dev_malloc_raw(void **p, size_t bytes) {
+    fts_alloc_fn fn;
+    void *ctx;
+    {
+        std::lock_guard<std::mutex> lock(g_alloc_mutex);
+        fn = g_alloc_fn;
+        ctx = g_alloc_ctx;
+    }
+    *p = nullptr;
+    if (!fn) {
+        set_error("no device allocator registered (fts_set_allocator)");
+        return hipErrorInvalidValue;
+    }
+    *p = fn(bytes > 0 ? bytes : 1, ctx);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+
+void dev_free(void *p) {
+    if (!p) return;
+    fts_free_fn fn;
+    void *ctx;
+    {
+        std::lock_guard<std::mutex> lock(g_alloc_mutex);
+        fn = g_free_fn;
+        ctx = g_alloc_ctx;
+    }
+    if (fn) fn(p, ctx);
+}
 
 fts_status fail(fts_status code, const std::string &msg) {
     set_error(msg);
@@ -407,9 +444,9 @@ fts_status fts_level_create(const fts_mesh_desc *mesh, fts_level **out) {
         total += lv->host_cellop[a].size() + lv->host_iface[a].size() + 2 * lv->h[a].size();
     }
     total += nn + 2 * nn + nn + 2 * lv->n1 + 2 * nn;
-    if (hipMalloc(&lv->d_tab, total * sizeof(double)) != hipSuccess) {
+    if (dev_malloc(&lv->d_tab, total * sizeof(double)) != hipSuccess) {
         delete lv;
-        return fail(FTS_E_HIP, "hipMalloc of level tables failed");
+        return fail(FTS_E_HIP, "device allocation of level tables failed");
     }
     std::vector<double> host(total);
     size_t off = 0;
@@ -442,7 +479,7 @@ fts_status fts_level_create(const fts_mesh_desc *mesh, fts_level **out) {
     lv->view.pk = lv->k * (lv->k + 1.0);
     lv->view.ncells = lv->ncells;
     if (hipMemcpy(lv->d_tab, host.data(), total * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(lv->d_tab);
+        dev_free(lv->d_tab);
         delete lv;
         return fail(FTS_E_HIP, "upload of level tables failed");
     }
@@ -452,7 +489,7 @@ fts_status fts_level_create(const fts_mesh_desc *mesh, fts_level **out) {
 
 fts_status fts_level_destroy(fts_level *level) {
     if (!level) return FTS_OK;
-    if (level->d_tab) (void)hipFree(level->d_tab);
+    if (level->d_tab) dev_free(level->d_tab);
     delete level;
     return FTS_OK;
 }
@@ -641,11 +678,11 @@ fts_status setup_eigs_internal(const fts_level *lv, fts_patch_kind kind, bool st
             eg->sym[a][p] = 1;
         }
     }
-    if (hipMalloc(&eg->d_tab, std::max<size_t>(total, 1) * sizeof(double)) != hipSuccess ||
-        hipMalloc(&eg->d_tab32, std::max<size_t>(total, 1) * sizeof(float)) != hipSuccess) {
-        if (eg->d_tab) (void)hipFree(eg->d_tab);
+    if (dev_malloc(&eg->d_tab, std::max<size_t>(total, 1) * sizeof(double)) != hipSuccess ||
+        dev_malloc(&eg->d_tab32, std::max<size_t>(total, 1) * sizeof(float)) != hipSuccess) {
+        if (eg->d_tab) dev_free(eg->d_tab);
         delete eg;
-        return fail(FTS_E_HIP, "hipMalloc of eigen tables failed");
+        return fail(FTS_E_HIP, "device allocation of eigen tables failed");
     }
     std::vector<double> host(total);
     std::vector<float> host32(total);
@@ -669,8 +706,8 @@ fts_status setup_eigs_internal(const fts_level *lv, fts_patch_kind kind, bool st
     for (size_t i = 0; i < total; ++i) host32[i] = (float)host[i];
     if (total && (hipMemcpy(eg->d_tab, host.data(), total * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
                   hipMemcpy(eg->d_tab32, host32.data(), total * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)) {
-        (void)hipFree(eg->d_tab);
-        (void)hipFree(eg->d_tab32);
+        dev_free(eg->d_tab);
+        dev_free(eg->d_tab32);
         delete eg;
         return fail(FTS_E_HIP, "upload of eigen tables failed");
     }
@@ -678,12 +715,12 @@ fts_status setup_eigs_internal(const fts_level *lv, fts_patch_kind kind, bool st
         std::vector<int> hc;
         for (int a = 0; a < 3; ++a) hc.insert(hc.end(), eg->cls[a].begin(), eg->cls[a].end());
         for (int a = 0; a < 3; ++a) hc.insert(hc.end(), eg->sym[a].begin(), eg->sym[a].end());
-        if (hipMalloc(&eg->d_cls, std::max<size_t>(hc.size(), 1) * sizeof(int)) != hipSuccess ||
+        if (dev_malloc(&eg->d_cls, std::max<size_t>(hc.size(), 1) * sizeof(int)) != hipSuccess ||
             (!hc.empty() &&
              hipMemcpy(eg->d_cls, hc.data(), hc.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess)) {
-            if (eg->d_cls) (void)hipFree(eg->d_cls);
-            (void)hipFree(eg->d_tab);
-            (void)hipFree(eg->d_tab32);
+            if (eg->d_cls) dev_free(eg->d_cls);
+            dev_free(eg->d_tab);
+            dev_free(eg->d_tab32);
             delete eg;
             return fail(FTS_E_HIP, "upload of the table classes failed");
         }
@@ -706,12 +743,12 @@ fts_status setup_eigs_internal(const fts_level *lv, fts_patch_kind kind, bool st
         std::vector<unsigned char> host16(std::max<size_t>(mats + flts, 4));
         uint16_t *m16 = reinterpret_cast<uint16_t *>(host16.data());
         float *f32 = reinterpret_cast<float *>(host16.data() + mats);
-        if (hipMalloc(&eg->d_mfma, host16.size()) != hipSuccess) {
-            (void)hipFree(eg->d_tab);
-            (void)hipFree(eg->d_tab32);
-            (void)hipFree(eg->d_cls);
+        if (dev_malloc(&eg->d_mfma, host16.size()) != hipSuccess) {
+            dev_free(eg->d_tab);
+            dev_free(eg->d_tab32);
+            dev_free(eg->d_cls);
             delete eg;
-            return fail(FTS_E_HIP, "hipMalloc of the MFMA tables failed");
+            return fail(FTS_E_HIP, "device allocation of the MFMA tables failed");
         }
         const uint16_t *dm = static_cast<const uint16_t *>(eg->d_mfma);
         const float *df = reinterpret_cast<const float *>(static_cast<const unsigned char *>(eg->d_mfma) + mats);
@@ -759,10 +796,10 @@ fts_status setup_eigs_internal(const fts_level *lv, fts_patch_kind kind, bool st
             fo += (size_t)cnt * 2;
         }
         if (hipMemcpy(eg->d_mfma, host16.data(), host16.size(), hipMemcpyHostToDevice) != hipSuccess) {
-            (void)hipFree(eg->d_tab);
-            (void)hipFree(eg->d_tab32);
-            (void)hipFree(eg->d_mfma);
-            (void)hipFree(eg->d_cls);
+            dev_free(eg->d_tab);
+            dev_free(eg->d_tab32);
+            dev_free(eg->d_mfma);
+            dev_free(eg->d_cls);
             delete eg;
             return fail(FTS_E_HIP, "upload of the MFMA tables failed");
         }
@@ -771,15 +808,15 @@ fts_status setup_eigs_internal(const fts_level *lv, fts_patch_kind kind, bool st
         int64_t nsub = 1;
         for (int a = 0; a < lv->dim; ++a) nsub *= eg->count[a];
         const size_t bytes = (size_t)nsub * (1u << lv->dim) * (lv->ndofs / lv->ncells) * sizeof(double);
-        if (hipMalloc(&eg->d_stage, std::max<size_t>(bytes, 8)) != hipSuccess ||
-            hipMalloc(&eg->d_stage_scale, (size_t)std::max<int64_t>(nsub, 1) * sizeof(double)) != hipSuccess) {
-            if (eg->d_stage) (void)hipFree(eg->d_stage);
-            (void)hipFree(eg->d_tab);
-            (void)hipFree(eg->d_tab32);
-            if (eg->d_mfma) (void)hipFree(eg->d_mfma);
-            (void)hipFree(eg->d_cls);
+        if (dev_malloc(&eg->d_stage, std::max<size_t>(bytes, 8)) != hipSuccess ||
+            dev_malloc(&eg->d_stage_scale, (size_t)std::max<int64_t>(nsub, 1) * sizeof(double)) != hipSuccess) {
+            if (eg->d_stage) dev_free(eg->d_stage);
+            dev_free(eg->d_tab);
+            dev_free(eg->d_tab32);
+            if (eg->d_mfma) dev_free(eg->d_mfma);
+            dev_free(eg->d_cls);
             delete eg;
-            return fail(FTS_E_HIP, "hipMalloc of the patch staging buffer failed");
+            return fail(FTS_E_HIP, "device allocation of the patch staging buffer failed");
         }
     }
     *out = eg;
@@ -789,6 +826,15 @@ fts_status setup_eigs_internal(const fts_level *lv, fts_patch_kind kind, bool st
 }  // namespace fts
 
 extern "C" {
+
+fts_status fts_set_allocator(fts_alloc_fn alloc, fts_free_fn release, void *ctx) {
+    if (!alloc != !release) return fail(FTS_E_INVAL, "fts_set_allocator: give both functions or neither");
+    std::lock_guard<std::mutex> lock(g_alloc_mutex);
+    g_alloc_fn = alloc;
+    g_free_fn = release;
+    g_alloc_ctx = ctx;
+    return FTS_OK;
+}
 
 fts_status fts_setup_1d_eigs(const fts_level *lv, fts_patch_kind kind, fts_eigs **out) {
     return setup_eigs_internal(lv, kind, true, out);
@@ -806,12 +852,12 @@ fts_status fts_eigs_set_schedule(fts_eigs *eigs, int32_t schedule) {
 
 fts_status fts_eigs_destroy(fts_eigs *eigs) {
     if (!eigs) return FTS_OK;
-    if (eigs->d_tab) (void)hipFree(eigs->d_tab);
-    if (eigs->d_tab32) (void)hipFree(eigs->d_tab32);
-    if (eigs->d_stage) (void)hipFree(eigs->d_stage);
-    if (eigs->d_stage_scale) (void)hipFree(eigs->d_stage_scale);
-    if (eigs->d_mfma) (void)hipFree(eigs->d_mfma);
-    if (eigs->d_cls) (void)hipFree(eigs->d_cls);
+    if (eigs->d_tab) dev_free(eigs->d_tab);
+    if (eigs->d_tab32) dev_free(eigs->d_tab32);
+    if (eigs->d_stage) dev_free(eigs->d_stage);
+    if (eigs->d_stage_scale) dev_free(eigs->d_stage_scale);
+    if (eigs->d_mfma) dev_free(eigs->d_mfma);
+    if (eigs->d_cls) dev_free(eigs->d_cls);
     delete eigs;
     return FTS_OK;
 }

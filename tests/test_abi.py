@@ -90,3 +90,20 @@ def test_hierarchy_validates_before_allocating():
     # 3 cells cannot be coarsened
     assert fts.lib().fts_hierarchy_create(ctypes.byref(d), 2, 1, om.ctypes.data, None, 1, 1, ctypes.byref(h)) == -1
     assert fts.lib().fts_hierarchy_create(ctypes.byref(d), 0, 1, om.ctypes.data, None, 1, 1, ctypes.byref(h)) == -1
+
+
+def test_library_sources_never_call_hipmalloc():
+    """Ownership: every device allocation goes through the allocator the caller
+    registers (fts_set_allocator); the sources call no hipMalloc / hipFree."""
+    import glob
+    import re
+    csrc = os.path.join(ROOT, "paper_1910_11239_amd", "csrc")
+    for f in glob.glob(os.path.join(csrc, "*.cpp")) + glob.glob(os.path.join(csrc, "*.hip")) + \
+            glob.glob(os.path.join(csrc, "*.h")):
+        text = re.sub(r"//[^\n]*", "", open(f).read())
+        assert not re.search(r"(?<!Host)hipMalloc\w*\(|(?<!Host)hipFree\(", text), f
+
+
+def test_allocator_must_be_given_in_pairs():
+    lib = fts.lib()
+    assert lib.fts_set_allocator(fts._ALLOC_CB, ctypes.cast(None, fts._FREE_T), None) == -1
