@@ -17,8 +17,9 @@ Per-kernel rooflines are measured live with events on the launch stream.
                     [--no-mixed] [--no-batched] [--no-mult]
     python bench.py --profile-only | --profile-mixed PREC | --calibrate-copy   (for rocprofv3)
 
-The JSON line also carries the 48^3 Q7 mixed-precision CG comparison, the
-64-mesh batched sweep, the multiplicative smoothers with GMRES, and the CPU
+The JSON line also carries the smoother rooflines, the 48^3 Q7
+mixed-precision CG comparison, the 64-mesh batched sweep, the multiplicative
+smoothers with GMRES, the surrogate smoother on a distorted mesh, and the CPU
 oracle baseline.
 """
 import argparse
@@ -220,6 +221,34 @@ def batched_workload():
             "residual_ms": t_res, "launch": report.strip().splitlines()[-1]}
 
 
+def distorted_workload():
+    """Sec. 4: the 3-D distorted cube (8^3 cells with interior vertices moved
+    by 25 % of the local edge length in random directions, refined twice to
+    32^3 cells), Q3, gamma_hat = 4: one sweep of the additive cell smoother
+    with Cartesian surrogate local solvers = matrix-free mapped SIPG residual
+    + per-cell fast-diagonalisation solves."""
+    import torch
+    import paper_1910_11239_amd as fts
+    from synthetic import distorted_vertices
+    ms, V = distorted_vertices(3, 8, 2, 0.25, 0)
+    lv = fts.MappedLevel(3, 3, ms, V, 4.0)
+    N = lv.ndofs
+    b = torch.as_tensor(random_vector(N, 0)).cuda()
+    x = torch.as_tensor(random_vector(N, 1)).cuda()
+    r = torch.empty_like(x)
+    ws = torch.empty_like(x)
+    t_res = _events_time(lambda: lv.residual(b, x, r), 5)
+    t_apply = _events_time(lambda: lv.schwarz_apply(0.5, r, x), 5)
+    t_sweep = _events_time(lambda: lv.schwarz_smooth(0.5, b, x, 1, ws), 5)
+    del lv
+    torch.cuda.empty_cache()
+    return {"workload": "distorted cube: 8^3 cells, interior vertices moved by 0.25 h_v, refined twice to 32^3 "
+                        "mapped cells, Q3 (2,097,152 DoFs), gamma_hat 4, omega 0.5",
+            "dofs": N, "residual_ms": t_res, "surrogate_apply_ms": t_apply, "sweep_ms": t_sweep,
+            "sweep_dofs_per_s": N / (t_sweep * 1e-3),
+            "residual_gbs": wm.residual_bytes(3, 3, ms) / (t_res * 1e-3) / 1e9}
+
+
 def multiplicative_workload():
     """Multiplicative smoothers on the 3-D Q4 32^3 mesh (4,096,000 DoFs):
     one sweep of the vertex-patch smoother with 2^(d+1) = 16 colors and of the
@@ -278,6 +307,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the 48^3 Q7 mixed-precision CG comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-mesh batched sweep")
     ap.add_argument("--no-mult", action="store_true", help="skip the multiplicative-smoother measurements")
+    ap.add_argument("--no-distorted", action="store_true", help="skip the distorted-mesh surrogate smoother")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + steps of the V-cycle only (for rocprofv3)")
     ap.add_argument("--profile-mixed", choices=["f64", "f32", "f16", "bf16"],
@@ -454,6 +484,8 @@ def main():
         out["batched"] = batched_workload()
     if not args.no_mult:
         out["multiplicative"] = multiplicative_workload()
+    if not args.no_distorted:
+        out["distorted"] = distorted_workload()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out))

@@ -56,11 +56,8 @@ fts_status fts_schwarz_smooth(const fts_level *level, const fts_eigs *eigs, doub
     if (!level || !eigs || !b || !x || !ws) return fail(FTS_E_INVAL, "fts_schwarz_smooth: NULL argument");
     if (eigs->level != level) return fail(FTS_E_INVAL, "fts_schwarz_smooth: eigs belong to another level");
     if (ws_bytes < fts_smooth_ws_bytes(level)) return fail(FTS_E_SIZE, "fts_schwarz_smooth: workspace too small");
-    double *r = static_cast<double *>(ws);
     for (int it = 0; it < nsweeps; ++it) {
-        fts_status st = launch_operator(level, x, b, r, true, S(stream));
-        if (st != FTS_OK) return st;
-        st = launch_schwarz(level, eigs, omega, prec, r, x, S(stream));
+        const fts_status st = smooth_additive(level, eigs, omega, prec, b, x, ws, false, S(stream));
         if (st != FTS_OK) return st;
     }
     return FTS_OK;
@@ -249,9 +246,7 @@ static fts_status smooth_step(fts_hierarchy *h, int l, fts_prec prec, const doub
         }
         return st;
     }
-    if (!x_zero) st = launch_operator(lv, x, b, r, true, s);
-    if (st == FTS_OK) st = launch_schwarz(lv, eg, h->omega[l], prec, x_zero ? b : r, x, s);
-    return st;
+    return smooth_additive(lv, eg, h->omega[l], prec, b, x, r, x_zero, s);
 }
 
 // x <- MG_l(x, b) (Alg. gmg).  x_zero: x is zero on entry (the coarser

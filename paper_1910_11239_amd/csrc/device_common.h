@@ -457,9 +457,9 @@ __device__ __forceinline__ void sipg_line(const double *in, const double *nl, co
 //   x-lines: W_x -> U                       y-lines: U <- h_y h_z M U, W_y -> V
 //   x-lines: U += h_x h_z M V               z-lines: U <- M U,         W_z -> V
 //   y-lines: V <- h_x h_y M V               x-lines: y = U + M V (or b - ...)
-template <int D, int N1, bool RES, bool PEN = false>
+template <int D, int N1, bool RES, bool PEN = false, typename TY = double>
 __device__ __forceinline__ void operator_cells(const LevelView &g, int64_t cell0, const double *__restrict__ x,
-                                               const double *__restrict__ b, double *__restrict__ y) {
+                                               const double *__restrict__ b, TY *__restrict__ y) {
     using C = OpCfg<D, N1>;
     constexpr int NC = C::NC, LINES = C::LINES, CPW = C::CPW, P = C::P, SL = C::SLOT;
     constexpr int HE = (N1 + 1) / 2;
@@ -596,14 +596,14 @@ __device__ __forceinline__ void operator_cells(const LevelView &g, int64_t cell0
             ld(V, 0, v);
             mass(v, m, 1.0);
             ld(U, 0, v);
-            double *dst = y + cell * NC + line_idx(0, 0);
+            TY *dst = y + cell * NC + line_idx(0, 0);
             if constexpr (RES) {
                 const double *bb = b + cell * NC + line_idx(0, 0);
 #pragma unroll
-                for (int j = 0; j < N1; ++j) dst[j] = bb[j] - (v[j] + m[j]);
+                for (int j = 0; j < N1; ++j) dst[j] = (TY)(bb[j] - (v[j] + m[j]));
             } else {
 #pragma unroll
-                for (int j = 0; j < N1; ++j) dst[j] = v[j] + m[j];
+                for (int j = 0; j < N1; ++j) dst[j] = (TY)(v[j] + m[j]);
             }
         }
     } else {
@@ -624,14 +624,14 @@ __device__ __forceinline__ void operator_cells(const LevelView &g, int64_t cell0
             ld(V, 0, v);
             mass(v, m, h[0]);
             ld(U, 0, v);
-            double *dst = y + cell * NC + line_idx(0, 0);
+            TY *dst = y + cell * NC + line_idx(0, 0);
             if constexpr (RES) {
                 const double *bb = b + cell * NC + line_idx(0, 0);
 #pragma unroll
-                for (int j = 0; j < N1; ++j) dst[j] = bb[j] - (v[j] + m[j]);
+                for (int j = 0; j < N1; ++j) dst[j] = (TY)(bb[j] - (v[j] + m[j]));
             } else {
 #pragma unroll
-                for (int j = 0; j < N1; ++j) dst[j] = v[j] + m[j];
+                for (int j = 0; j < N1; ++j) dst[j] = (TY)(v[j] + m[j]);
             }
         }
     }

@@ -175,9 +175,15 @@ fts_status launch_axpy(double a, const double *x, double *y, int64_t n, hipStrea
 fts_status launch_schwarz(const fts_level *lv, const fts_eigs *eg, double omega, fts_prec prec,
                           const double *r, double *x, hipStream_t stream);
 // 16-bit local solves of 3-D vertex patches by owner-computes tiles (tile.hip):
-// x += omega sum_j R_j^T A_j^-1 R_j r; r must be 16-byte aligned.
-fts_status launch_schwarz_mfma_tile(const fts_level *lv, const fts_eigs *eg, double omega, int bf, const double *r,
-                                    double *x, hipStream_t stream);
+// x += omega sum_j R_j^T A_j^-1 R_j r; r (FP64, or FP32 if r_f32) must be
+// 16-byte aligned.
+fts_status launch_schwarz_mfma_tile(const fts_level *lv, const fts_eigs *eg, double omega, int bf, const void *r,
+                                    bool r_f32, double *x, hipStream_t stream);
+// One additive smoothing step x <- x + omega C (b - A x) (Alg. addsmoother);
+// x_zero: x is zero, r = b.  rbuf: ndofs doubles of space for the residual,
+// which is stored in FP32 when the local solves are 16-bit owner tiles.
+fts_status smooth_additive(const fts_level *lv, const fts_eigs *eg, double omega, fts_prec prec, const double *b,
+                           double *x, void *rbuf, bool x_zero, hipStream_t stream);
 // Colors of the multiplicative smoother: 2 (red-black cells) or 2^(d+1)
 // (vertex patches); one color's local solves added to x in place.
 int schwarz_mult_colors(const fts_eigs *eg);

@@ -13,10 +13,10 @@
 
 namespace fts {
 
-template <int D, int N1, bool RES, bool PEN>
+template <int D, int N1, bool RES, bool PEN, typename TY = double>
 __global__ void __launch_bounds__((OpCfg<D, N1>::THREADS))
-k_operator(LevelView g, const double *__restrict__ x, const double *__restrict__ b, double *__restrict__ y) {
-    operator_cells<D, N1, RES, PEN>(g, (int64_t)blockIdx.x * OpCfg<D, N1>::CPW, x, b, y);
+k_operator(LevelView g, const double *__restrict__ x, const double *__restrict__ b, TY *__restrict__ y) {
+    operator_cells<D, N1, RES, PEN, TY>(g, (int64_t)blockIdx.x * OpCfg<D, N1>::CPW, x, b, y);
 }
 
 // ---------------------------------------------------------------------------
@@ -1079,6 +1079,36 @@ fts_status launch_operator(const fts_level *lv, const double *x, const double *b
     return dispatch<RunOperator>(lv->dim, lv->n1, lv, x, b, y, residual, stream);
 }
 
+// r = b - A x computed in FP64 and stored rounded to FP32 (the residual the
+// 16-bit local solves of the owner tiles read).
+template <int D, int N1>
+struct RunResidual32 {
+    static fts_status run(const fts_level *lv, const double *x, const double *b, float *r, hipStream_t st) {
+        using C = OpCfg<D, N1>;
+        if (lv->ncells > INT_MAX) return fail(FTS_E_SIZE, "too many cells for one launch");
+        const int64_t blocks = (lv->ncells + C::CPW - 1) / C::CPW;
+        if (blocks == 0) return FTS_OK;
+        k_operator<D, N1, true, false, float><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(lv->view, x, b, r);
+        return check_launch("k_operator (FP32 residual)");
+    }
+};
+
+fts_status smooth_additive(const fts_level *lv, const fts_eigs *eg, double omega, fts_prec prec, const double *b,
+                           double *x, void *rbuf, bool x_zero, hipStream_t stream) {
+    if (x_zero) return launch_schwarz(lv, eg, omega, prec, b, x, stream);  // r = b - A 0 = b
+    const bool f32r = (prec == FTS_PREC_BF16 || prec == FTS_PREC_F16) && lv->dim == 3 &&
+                      eg->kind == FTS_VERTEX_PATCH && eg->schedule == FTS_SCHEDULE_OWNER && lv->n1 <= 8 &&
+                      reinterpret_cast<uintptr_t>(rbuf) % 16 == 0;
+    if (!f32r) {
+        double *r = static_cast<double *>(rbuf);
+        fts_status st = launch_operator(lv, x, b, r, true, stream);
+        return st == FTS_OK ? launch_schwarz(lv, eg, omega, prec, r, x, stream) : st;
+    }
+    float *r = static_cast<float *>(rbuf);
+    fts_status st = dispatch<RunResidual32>(lv->dim, lv->n1, lv, x, b, r, stream);
+    return st == FTS_OK ? launch_schwarz_mfma_tile(lv, eg, omega, prec == FTS_PREC_BF16, r, true, x, stream) : st;
+}
+
 template <int D, int N1>
 struct RunSchwarz {
     template <int KIND, typename T>
@@ -1145,7 +1175,7 @@ struct RunSchwarz {
         } else {
             if constexpr (KIND == 1) {
                 if (eg->schedule == FTS_SCHEDULE_OWNER && reinterpret_cast<uintptr_t>(r) % 16 == 0)
-                    return launch_schwarz_mfma_tile(lv, eg, omega, BF, r, x, st);
+                    return launch_schwarz_mfma_tile(lv, eg, omega, BF, r, false, x, st);
             }
             const bool staged = KIND == 1 && eg->schedule != FTS_SCHEDULE_COLORED;
             const int ncolor = (KIND && !staged) ? 8 : 1;

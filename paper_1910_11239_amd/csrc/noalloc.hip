@@ -54,11 +54,10 @@ fts_status fts_schwarz_smooth_noalloc(const fts_level *level, const fts_eigs *ei
     if (st != FTS_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     // r is written in full by the residual kernel before the local solves read
-    // it, so nothing carried over from an earlier call is ever read
+    // it (in FP64, or FP32 for the 16-bit owner tiles), so nothing carried
+    // over from an earlier call is ever read
     for (int it = 0; it < nsweeps; ++it) {
-        st = launch_operator(level, x, b, r, true, s);
-        if (st != FTS_OK) return st;
-        st = launch_schwarz(level, eigs, omega, prec, r, x, s);
+        st = smooth_additive(level, eigs, omega, prec, b, x, r, false, s);
         if (st != FTS_OK) return st;
     }
     return FTS_OK;

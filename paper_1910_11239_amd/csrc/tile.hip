@@ -107,9 +107,9 @@ __device__ __forceinline__ void lanegroup_transpose(unsigned (&P)[4][NP]) {
         }
 }
 
-template <int N1, int BF>
+template <int N1, int BF, typename TR>
 __global__ void __launch_bounds__(256)
-k_schwarz_mfma_tile(LevelView g, EigView e, TileGrid tg, const double *__restrict__ r, double *__restrict__ x,
+k_schwarz_mfma_tile(LevelView g, EigView e, TileGrid tg, const TR *__restrict__ r, double *__restrict__ x,
                     float omega) {
     constexpr int N = 2 * N1, NC1 = N1 * N1 * N1;
     static_assert(N <= 16, "one 16 x 16 tile per contraction");
@@ -169,14 +169,22 @@ k_schwarz_mfma_tile(LevelView g, EigView e, TileGrid tg, const double *__restric
                         if constexpr (N1 % 4 == 0) {
                             if (4 * q < N) {
                                 const int ox = (4 * q) / N1, ix = (4 * q) % N1;
-                                const double *src = r + (cbase + ox + oy * cs1 + oz * cs2) * NC1 + iz * N1 * N1 +
-                                                    iy * N1 + ix;
-                                const double2 u0 = *reinterpret_cast<const double2 *>(src);
-                                const double2 u1 = *reinterpret_cast<const double2 *>(src + 2);
-                                rv[s][0] = (float)u0.x;
-                                rv[s][1] = (float)u0.y;
-                                rv[s][2] = (float)u1.x;
-                                rv[s][3] = (float)u1.y;
+                                const TR *src = r + (cbase + ox + oy * cs1 + oz * cs2) * NC1 + iz * N1 * N1 +
+                                                iy * N1 + ix;
+                                if constexpr (sizeof(TR) == 8) {
+                                    const double2 u0 = *reinterpret_cast<const double2 *>(src);
+                                    const double2 u1 = *reinterpret_cast<const double2 *>(src + 2);
+                                    rv[s][0] = (float)u0.x;
+                                    rv[s][1] = (float)u0.y;
+                                    rv[s][2] = (float)u1.x;
+                                    rv[s][3] = (float)u1.y;
+                                } else {
+                                    const float4 u = *reinterpret_cast<const float4 *>(src);
+                                    rv[s][0] = u.x;
+                                    rv[s][1] = u.y;
+                                    rv[s][2] = u.z;
+                                    rv[s][3] = u.w;
+                                }
                             }
                         } else {
 #pragma unroll
@@ -316,9 +324,9 @@ k_schwarz_mfma_tile(LevelView g, EigView e, TileGrid tg, const double *__restric
     if (vz_hi == m2 - 1 && vz_hi >= z0 && vz_hi < z1) flush(vz_hi);
 }
 
-template <int N1>
-static fts_status launch_tile(const fts_level *lv, const fts_eigs *eg, float omega, int bf, const double *r,
-                              double *x, hipStream_t st) {
+template <int N1, typename TR>
+static fts_status launch_tile(const fts_level *lv, const fts_eigs *eg, float omega, int bf, const TR *r, double *x,
+                              hipStream_t st) {
     TileGrid tg{};
     tg.nt[0] = (lv->m[0] + kTile - 1) / kTile;
     tg.nt[1] = (lv->m[1] + kTile - 1) / kTile;
@@ -331,28 +339,35 @@ static fts_status launch_tile(const fts_level *lv, const fts_eigs *eg, float ome
     tg.per_xcd = (tg.ntile + 7) / 8;
     const dim3 grid((unsigned)(8 * tg.per_xcd)), block(256);
     if (bf)
-        k_schwarz_mfma_tile<N1, 1><<<grid, block, 0, st>>>(lv->view, eg->view, tg, r, x, omega);
+        k_schwarz_mfma_tile<N1, 1, TR><<<grid, block, 0, st>>>(lv->view, eg->view, tg, r, x, omega);
     else
-        k_schwarz_mfma_tile<N1, 0><<<grid, block, 0, st>>>(lv->view, eg->view, tg, r, x, omega);
+        k_schwarz_mfma_tile<N1, 0, TR><<<grid, block, 0, st>>>(lv->view, eg->view, tg, r, x, omega);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? FTS_OK : hip_fail(e, "k_schwarz_mfma_tile launch");
 }
 
-fts_status launch_schwarz_mfma_tile(const fts_level *lv, const fts_eigs *eg, double omega, int bf, const double *r,
-                                    double *x, hipStream_t st) {
+fts_status launch_schwarz_mfma_tile(const fts_level *lv, const fts_eigs *eg, double omega, int bf, const void *r,
+                                    bool r_f32, double *x, hipStream_t st) {
     if (lv->dim != 3 || eg->kind != FTS_VERTEX_PATCH)
         return fail(FTS_E_UNSUPPORTED, "owner tiles: 3-D vertex patches only");
     if ((int64_t)lv->m[0] * lv->m[1] * lv->m[2] > INT_MAX) return fail(FTS_E_SIZE, "owner tiles: too many cells");
+    const float om = (float)omega;
+    const double *rd = static_cast<const double *>(r);
+    const float *rf = static_cast<const float *>(r);
+#define FTS_TILE_CASE(n)                                                                           \
+    case n:                                                                                        \
+        return r_f32 ? launch_tile<n>(lv, eg, om, bf, rf, x, st) : launch_tile<n>(lv, eg, om, bf, rd, x, st);
     switch (lv->n1) {
-        case 2: return launch_tile<2>(lv, eg, (float)omega, bf, r, x, st);
-        case 3: return launch_tile<3>(lv, eg, (float)omega, bf, r, x, st);
-        case 4: return launch_tile<4>(lv, eg, (float)omega, bf, r, x, st);
-        case 5: return launch_tile<5>(lv, eg, (float)omega, bf, r, x, st);
-        case 6: return launch_tile<6>(lv, eg, (float)omega, bf, r, x, st);
-        case 7: return launch_tile<7>(lv, eg, (float)omega, bf, r, x, st);
-        case 8: return launch_tile<8>(lv, eg, (float)omega, bf, r, x, st);
+        FTS_TILE_CASE(2)
+        FTS_TILE_CASE(3)
+        FTS_TILE_CASE(4)
+        FTS_TILE_CASE(5)
+        FTS_TILE_CASE(6)
+        FTS_TILE_CASE(7)
+        FTS_TILE_CASE(8)
         default: return fail(FTS_E_UNSUPPORTED, "owner tiles: 16-bit MFMA contractions need n <= 16");
     }
+#undef FTS_TILE_CASE
 }
 
 }  // namespace fts
