@@ -185,7 +185,9 @@ k_batch_residual(const BatchMesh *__restrict__ meshes, const BatchBlock *__restr
     const BatchBlock B = blocks[blockIdx.x];
     const LevelView g = meshes[B.mesh].lv;
     const int64_t off = meshes[B.mesh].dof_off;
-    operator_cells<3, N1, true>(g, B.first, x + off, b + off, r + off);
+    const int64_t left = g.ncells - B.first;
+    const int nact = left < OpCfg<3, N1>::CPW ? (int)left : OpCfg<3, N1>::CPW;
+    operator_cells<3, N1, true>(g, B.first, nact, x + off, b + off, r + off);
 }
 
 template <int D, int N1>

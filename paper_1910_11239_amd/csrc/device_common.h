@@ -445,7 +445,7 @@ __device__ __forceinline__ void sipg_line(const double *in, const double *nl, co
     }
 }
 
-// y = A x (RES: y = b - A x) on the CPW cells cell0, cell0+1, ... of the mesh
+// y = A x (RES: y = b - A x) on the nact <= CPW cells cell0, cell0+1, ... of the mesh
 // described by g (x, b, y: that mesh's vectors).  Shared by the single-mesh
 // and the batched kernels.  Thread (q, l) works on cell cell0 + q and is in
 // turn the owner of line l along x, along y and along z; it reads the lines
@@ -458,8 +458,9 @@ __device__ __forceinline__ void sipg_line(const double *in, const double *nl, co
 //   x-lines: U += h_x h_z M V               z-lines: U <- M U,         W_z -> V
 //   y-lines: V <- h_x h_y M V               x-lines: y = U + M V (or b - ...)
 template <int D, int N1, bool RES, bool PEN = false, typename TY = double>
-__device__ __forceinline__ void operator_cells(const LevelView &g, int64_t cell0, const double *__restrict__ x,
-                                               const double *__restrict__ b, TY *__restrict__ y) {
+__device__ __forceinline__ void operator_cells(const LevelView &g, int64_t cell0, int nact,
+                                               const double *__restrict__ x, const double *__restrict__ b,
+                                               TY *__restrict__ y) {
     using C = OpCfg<D, N1>;
     constexpr int NC = C::NC, LINES = C::LINES, CPW = C::CPW, P = C::P, SL = C::SLOT;
     constexpr int HE = (N1 + 1) / 2;
@@ -471,7 +472,7 @@ __device__ __forceinline__ void operator_cells(const LevelView &g, int64_t cell0
     const int t = threadIdx.x;
     const int q = t / LINES, l = t % LINES;
     const int64_t cell = cell0 + q;
-    const bool act = q < CPW && cell < g.ncells;
+    const bool act = q < nact;
     const cptr<double> LE = uniform_table(g.Leo), ME = uniform_table(g.Meo);
     const cptr<double> LO = LE + HE * HE, MO = ME + HE * HE;
     const cptr<double> d0 = uniform_table(g.d0), d1 = uniform_table(g.d1);
@@ -480,7 +481,7 @@ __device__ __forceinline__ void operator_cells(const LevelView &g, int64_t cell0
     auto li = [](int i0, int i1, int i2) { return i0 + P * (i1 + N1 * i2); };
     constexpr int X = 2;
     if constexpr (XL) {
-        const int ncopy = (int)min((int64_t)CPW, g.ncells - cell0) * NC;
+        const int ncopy = nact * NC;
         const double *src = x + cell0 * NC;
         for (int e = t; e < ncopy; e += C::THREADS) {
             const int qq = e / NC, i = e % NC;

@@ -87,6 +87,62 @@ struct LevelView {
     double gk, pk;            // gamma_hat k (k+1) and k (k+1)
 };
 
+// Cell runs of the matrix-free operator launch.  Workgroups are handed to the
+// 8 XCDs round-robin (block b to XCD b % 8), and each XCD has its own L2.  The
+// rows (y, z) are split into min(8, m_y) groups of consecutive y; at fixed z
+// the rows of a group are one contiguous range of cells (a segment), cut into
+// runs of cpw cells (the last run of a segment may be shorter).  XCD j takes a
+// contiguous range of the order (group, z, run), so the x-, y- and
+// z-neighbours whose lines a cell reads were read shortly before on the same
+// XCD (within one segment of its group).
+struct OpRuns {
+    int m0, m1, m2, cpw, groups;
+    int64_t nblocks;
+};
+
+// first row and row count of group gi
+__host__ __device__ inline void op_group_rows(const OpRuns &o, int gi, int *y0, int *sy) {
+    const int a = (int)((int64_t)gi * o.m1 / o.groups), e = (int)((int64_t)(gi + 1) * o.m1 / o.groups);
+    *y0 = a;
+    *sy = e - a;
+}
+
+inline OpRuns op_runs(const int m[3], int dim, int cpw) {
+    OpRuns o;
+    o.m0 = m[0];
+    o.m1 = m[1];
+    o.m2 = dim == 3 ? m[2] : 1;
+    o.cpw = cpw;
+    o.groups = o.m1 < 8 ? o.m1 : 8;
+    o.nblocks = 0;
+    for (int gi = 0; gi < o.groups; ++gi) {
+        int y0, sy;
+        op_group_rows(o, gi, &y0, &sy);
+        o.nblocks += ((int64_t)sy * o.m0 + cpw - 1) / cpw * o.m2;
+    }
+    return o;
+}
+
+// block b -> first cell and number of cells (1..cpw) of its run
+__host__ __device__ inline void op_run_of_block(const OpRuns &o, int64_t b, int64_t *cell0, int *nact) {
+    const int64_t q = o.nblocks / 8, r = o.nblocks % 8;
+    const int64_t xcd = b % 8, i = b / 8;
+    int64_t L = xcd * q + (xcd < r ? xcd : r) + i;  // position in the (group, z, run) order
+    int y0 = 0, sy = o.m1;
+    int64_t seg = 0, nrun = 1;
+    for (int gi = 0; gi < o.groups; ++gi) {
+        op_group_rows(o, gi, &y0, &sy);
+        seg = (int64_t)sy * o.m0;
+        nrun = (seg + o.cpw - 1) / o.cpw;
+        if (L < nrun * o.m2) break;
+        L -= nrun * o.m2;
+    }
+    const int64_t run = L % nrun, z = L / nrun;
+    *cell0 = (z * o.m1 + y0) * o.m0 + run * o.cpw;
+    const int64_t left = seg - run * o.cpw;
+    *nact = left < o.cpw ? (int)left : o.cpw;
+}
+
 // The coarse matrix stored by slabs of cells (all cells sharing their
 // coordinate along the last axis).  Unknowns are numbered cell by cell with
 // the last axis slowest, so a slab is a contiguous range of B unknowns, and

@@ -15,8 +15,12 @@ namespace fts {
 
 template <int D, int N1, bool RES, bool PEN, typename TY = double>
 __global__ void __launch_bounds__((OpCfg<D, N1>::THREADS))
-k_operator(LevelView g, const double *__restrict__ x, const double *__restrict__ b, TY *__restrict__ y) {
-    operator_cells<D, N1, RES, PEN, TY>(g, (int64_t)blockIdx.x * OpCfg<D, N1>::CPW, x, b, y);
+k_operator(LevelView g, OpRuns runs, const double *__restrict__ x, const double *__restrict__ b,
+           TY *__restrict__ y) {
+    int64_t cell0;
+    int nact;
+    op_run_of_block(runs, blockIdx.x, &cell0, &nact);
+    operator_cells<D, N1, RES, PEN, TY>(g, cell0, nact, x, b, y);
 }
 
 // ---------------------------------------------------------------------------
@@ -1064,12 +1068,14 @@ struct RunOperator {
                           hipStream_t st) {
         using C = OpCfg<D, N1>;
         if (lv->ncells > INT_MAX) return fail(FTS_E_SIZE, "too many cells for one launch");
-        const int64_t blocks = (lv->ncells + C::CPW - 1) / C::CPW;
+        const OpRuns runs = op_runs(lv->view.m, D, C::CPW);
+        const int64_t blocks = runs.nblocks;
         if (blocks == 0) return FTS_OK;
+        if (blocks > INT_MAX) return fail(FTS_E_SIZE, "too many cells for one launch");
         if (res)
-            k_operator<D, N1, true, false><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(lv->view, x, b, y);
+            k_operator<D, N1, true, false><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(lv->view, runs, x, b, y);
         else
-            k_operator<D, N1, false, false><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(lv->view, x, b, y);
+            k_operator<D, N1, false, false><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(lv->view, runs, x, b, y);
         return check_launch("k_operator");
     }
 };
@@ -1086,9 +1092,11 @@ struct RunResidual32 {
     static fts_status run(const fts_level *lv, const double *x, const double *b, float *r, hipStream_t st) {
         using C = OpCfg<D, N1>;
         if (lv->ncells > INT_MAX) return fail(FTS_E_SIZE, "too many cells for one launch");
-        const int64_t blocks = (lv->ncells + C::CPW - 1) / C::CPW;
+        const OpRuns runs = op_runs(lv->view.m, D, C::CPW);
+        const int64_t blocks = runs.nblocks;
         if (blocks == 0) return FTS_OK;
-        k_operator<D, N1, true, false, float><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(lv->view, x, b, r);
+        if (blocks > INT_MAX) return fail(FTS_E_SIZE, "too many cells for one launch");
+        k_operator<D, N1, true, false, float><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(lv->view, runs, x, b, r);
         return check_launch("k_operator (FP32 residual)");
     }
 };
@@ -1673,9 +1681,11 @@ struct RunOperatorPen {
     static fts_status run(const fts_level *lv, const double *x, double *y, hipStream_t st) {
         using C = OpCfg<D, N1>;
         if (lv->ncells > INT_MAX) return fail(FTS_E_SIZE, "too many cells for one launch");
-        const int64_t blocks = (lv->ncells + C::CPW - 1) / C::CPW;
+        const OpRuns runs = op_runs(lv->view.m, D, C::CPW);
+        const int64_t blocks = runs.nblocks;
         if (blocks == 0) return FTS_OK;
-        k_operator<D, N1, false, true><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(lv->view, x, nullptr, y);
+        if (blocks > INT_MAX) return fail(FTS_E_SIZE, "too many cells for one launch");
+        k_operator<D, N1, false, true><<<dim3((unsigned)blocks), dim3(C::THREADS), 0, st>>>(lv->view, runs, x, nullptr, y);
         return check_launch("k_operator (penalty)");
     }
 };
