@@ -323,13 +323,16 @@ def main():
     ap.add_argument("--profile-mixed", choices=["f64", "f32", "f16", "bf16"],
                     help="run warmup + steps V-cycles of the 48^3 Q7 CG preconditioner at this contraction "
                          "precision only (for rocprofv3)")
+    ap.add_argument("--profile-batched", action="store_true",
+                    help="run the 64-mesh batched smoother only: 3 x (FP32 patch apply + gathers, FP64 residual) "
+                         "at 256 threads x 1,024 workgroups x chunks of 4 (for rocprofv3)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB FP64 buffer on the device --steps times (reference kernel of known "
                          "traffic for the rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the smoother and V-cycle are single-GPU kernels "
-              "(multi-GPU halo exchange is not part of this build)", file=sys.stderr)
+              "(a multi-GPU halo exchange is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -343,6 +346,21 @@ def main():
         print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "copies": args.steps}))
         return
     import paper_1910_11239_amd as fts
+    if args.profile_batched:
+        from synthetic import batched_meshes
+        batch = fts.Batch([(k, w, 1.0) for k, w in batched_meshes()])
+        nb = batch.ndofs
+        bb = torch.as_tensor(random_vector(nb, 0)).cuda()
+        xb = torch.zeros(nb, dtype=torch.float64, device="cuda")
+        rb = torch.empty_like(xb)
+        batch.residual(bb, xb, rb)
+        batch.set_launch(256, 1024, 4)
+        for _ in range(3):
+            batch.apply(0.125, rb, xb, prec="f32")
+            batch.residual(bb, xb, rb)
+        torch.cuda.synchronize()
+        print(json.dumps({"batched_dofs": nb}))
+        return
 
     if args.profile_mixed:
         c3 = CONFIGS["mixed_3d_q7"]

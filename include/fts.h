@@ -360,9 +360,9 @@ fts_status fts_batch_mesh_offset(const fts_batch *batch, int32_t mesh, int64_t *
 fts_status fts_batch_residual(fts_batch *batch, const double *b, const double *x, double *r,
                               void *stream);
 /* x += omega sum_j R_j^T A_j^-1 R_j r on every mesh: ONE persistent launch over
- * the patches of all meshes (workgroups dequeue chunks of patches with an
- * atomic counter; a degree switch selects the local solver), then a batched
- * per-cell gather.  prec: FTS_PREC_F64 or FTS_PREC_F32 contractions (update
+ * the patches of all meshes (workgroups dequeue chunks of one mesh's patches
+ * with an atomic counter; a degree switch selects the local solver), then a
+ * batched per-cell gather.  prec: FTS_PREC_F64 or FTS_PREC_F32 contractions (update
  * of x in FP64).  Calls on one batch must be stream-ordered (shared staging
  * buffer and counter). */
 fts_status fts_batch_apply(fts_batch *batch, double omega, fts_prec prec, const double *r, double *x,
@@ -372,13 +372,15 @@ size_t fts_batch_ws_bytes(const fts_batch *batch);
 fts_status fts_batch_smooth(fts_batch *batch, double omega, fts_prec prec, const double *b, double *x,
                             int32_t nsweeps, void *ws, size_t ws_bytes, void *stream);
 
-/* Launch shape of the persistent kernel: threads per workgroup (64, 128 or
- * 256), number of persistent workgroups, patches dequeued per atomic. */
+/* Launch shape of the persistent kernel: threads per workgroup (256 or 512;
+ * a thread owns at most two of the N^2 lines of a patch, N = 2(k+1) <= 20),
+ * number of persistent workgroups, patches per dequeued chunk (a chunk never
+ * spans two meshes). */
 fts_status fts_batch_set_launch(fts_batch *batch, int32_t threads, int32_t grid, int32_t chunk);
 fts_status fts_batch_get_launch(const fts_batch *batch, int32_t *threads, int32_t *grid,
                                 int32_t *chunk);
 /* Autotuner: times the persistent kernel (events on `stream`, synchronising)
- * for threads in {64,128,256} x grid in {1,2,4,8} x (compute units) x chunk
+ * for threads in {256,512} x grid in {1,2,4,8} x (compute units) x chunk
  * in {1,4,16} on the residual r (device, fts_batch_ndofs doubles), keeps the
  * fastest shape and writes a per-candidate report into `report` (may be NULL).
  * Overwrites the batch's staging buffer. */

@@ -215,103 +215,6 @@ __device__ __forceinline__ float recip(float d) {
     return fmaf(y, fmaf(-d, y, 1.0f), y);
 }
 
-// NL lines l0, l0 + dl, l0 + 2 dl, ... (those below nlines) along axis a at
-// once, each matrix entry read once for all of them: divides the scalar
-// loads per FMA by NL when the matrix is too large to stay in scalar
-// registers across lines.  Lines past nlines repeat l0 and are not stored.
-template <int D, int N, int NL, typename T, typename P>
-__device__ __forceinline__ void contract_lines(T *Tq, int a, int l0, int dl, int nlines, P Mat) {
-    const int st = line_stride<N>(a);
-    int base[NL];
-    bool ok[NL];
-#pragma unroll
-    for (int k = 0; k < NL; ++k) {
-        ok[k] = l0 + k * dl < nlines;
-        base[k] = line_base<D, N>(a, ok[k] ? l0 + k * dl : l0);
-    }
-    T in[NL][N], out[NL][N];
-#pragma unroll
-    for (int k = 0; k < NL; ++k)
-#pragma unroll
-        for (int i = 0; i < N; ++i) in[k][i] = Tq[base[k] + i * st];
-#pragma unroll
-    for (int o = 0; o < N; ++o) {
-        T acc[NL];
-#pragma unroll
-        for (int k = 0; k < NL; ++k) acc[k] = 0;
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-            const T m = (T)Mat[o * N + j];
-#pragma unroll
-            for (int k = 0; k < NL; ++k) acc[k] = fma(m, in[k][j], acc[k]);
-        }
-#pragma unroll
-        for (int k = 0; k < NL; ++k) out[k][o] = acc[k];
-    }
-#pragma unroll
-    for (int k = 0; k < NL; ++k)
-        if (ok[k]) {
-#pragma unroll
-            for (int i = 0; i < N; ++i) Tq[base[k] + i * st] = out[k][i];
-        }
-}
-
-// last_axis_solve on NL lines at once (see contract_lines); lr[k]: the
-// eigenvalue sum of the other axes at line k's mode indices.
-template <int D, int N, int NL, typename T, typename P, typename Q>
-__device__ __forceinline__ void last_axis_solves(T *Tq, int l0, int dl, int nlines, P ST, P S, Q lam_last,
-                                                 const T *lr, T omega) {
-    constexpr int a = D - 1;
-    const int st = line_stride<N>(a);
-    int base[NL];
-    bool ok[NL];
-#pragma unroll
-    for (int k = 0; k < NL; ++k) {
-        ok[k] = l0 + k * dl < nlines;
-        base[k] = line_base<D, N>(a, ok[k] ? l0 + k * dl : l0);
-    }
-    T v[NL][N], mid[NL][N];
-#pragma unroll
-    for (int k = 0; k < NL; ++k)
-#pragma unroll
-        for (int i = 0; i < N; ++i) v[k][i] = Tq[base[k] + i * st];
-#pragma unroll
-    for (int o = 0; o < N; ++o) {
-        T acc[NL];
-#pragma unroll
-        for (int k = 0; k < NL; ++k) acc[k] = 0;
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-            const T m = (T)ST[o * N + j];
-#pragma unroll
-            for (int k = 0; k < NL; ++k) acc[k] = fma(m, v[k][j], acc[k]);
-        }
-        const T lm = (T)lam_last[o];
-#pragma unroll
-        for (int k = 0; k < NL; ++k) mid[k][o] = acc[k] * (omega * recip(lr[k] + lm));
-    }
-#pragma unroll
-    for (int o = 0; o < N; ++o) {
-        T acc[NL];
-#pragma unroll
-        for (int k = 0; k < NL; ++k) acc[k] = 0;
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-            const T m = (T)S[o * N + j];
-#pragma unroll
-            for (int k = 0; k < NL; ++k) acc[k] = fma(m, mid[k][j], acc[k]);
-        }
-#pragma unroll
-        for (int k = 0; k < NL; ++k) v[k][o] = acc[k];
-    }
-#pragma unroll
-    for (int k = 0; k < NL; ++k)
-        if (ok[k]) {
-#pragma unroll
-            for (int i = 0; i < N; ++i) Tq[base[k] + i * st] = v[k][i];
-        }
-}
-
 // Last axis: forward transform, eigenvalue scaling and backward transform of
 // the same line, kept in registers.  lam_rest = lambda of the other axes at
 // this line's fixed mode indices.

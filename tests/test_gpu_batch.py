@@ -37,7 +37,7 @@ def _oracle_sweeps(meshes, omega, b, x):
     return outs
 
 
-@pytest.mark.parametrize("launch", [None, (64, 512, 16), (128, 1024, 1)])
+@pytest.mark.parametrize("launch", [None, (512, 512, 16), (256, 1024, 1)])
 def test_batch_fp64_parity(launch):
     announce("batch fp64", launch)
     meshes = _meshes()
