@@ -282,15 +282,17 @@ __device__ __forceinline__ void eo_matvec(const double *in, double *out, double 
         uo[j] = in[j] - in[N - 1 - j];
     }
     if constexpr (N % 2) ue[H] = in[H];
+    // E and O are symmetric (so are Mhat and Lhat): only their upper triangles
+    // are read, which keeps fewer of their entries in scalar registers
 #pragma unroll
     for (int i = 0; i < HE; ++i) {
         double se = 0.0;
 #pragma unroll
-        for (int j = 0; j < HE; ++j) se = fma((double)E[i * HE + j], ue[j], se);
+        for (int j = 0; j < HE; ++j) se = fma((double)E[i <= j ? i * HE + j : j * HE + i], ue[j], se);
         if (i < H) {
             double so = 0.0;
 #pragma unroll
-            for (int j = 0; j < H; ++j) so = fma((double)O[i * H + j], uo[j], so);
+            for (int j = 0; j < H; ++j) so = fma((double)O[i <= j ? i * H + j : j * H + i], uo[j], so);
             out[i] = (se + so) * scale;
             out[N - 1 - i] = (se - so) * scale;
         } else {
@@ -301,8 +303,11 @@ __device__ __forceinline__ void eo_matvec(const double *in, double *out, double 
 
 template <int N1, bool PEN, typename P>
 __device__ __forceinline__ void sipg_line(const double *in, const double *nl, const double *nr, bool hasl, bool hasr,
-                                          double ih, double ihl, double ihr, double gk, P LE, P LO, P d0, P d1,
+                                          double ih, double ihl, double ihr, double gk, P LE, P LO, P d0,
                                           double *out) {
+    // derivatives of the basis at the right end: phi_j'(1) = -phi_{n-1-j}'(0)
+    // (Gauss-Lobatto nodes symmetric about the midpoint), so only d0 is read
+    auto d1 = [&](int j) { return -(double)d0[N1 - 1 - j]; };
     const double eta0 = hasl ? 0.5 : 1.0, eta1 = hasr ? 0.5 : 1.0;
     const double g0 = hasl ? gk * (ih + ihl) : 2.0 * gk * ih;
     const double g1 = hasr ? gk * (ih + ihr) : 2.0 * gk * ih;
@@ -320,7 +325,7 @@ __device__ __forceinline__ void sipg_line(const double *in, const double *nl, co
 #pragma unroll
         for (int j = 0; j < N1; ++j) {
             dx0 = fma((double)d0[j], in[j], dx0);
-            dxn = fma((double)d1[j], in[j], dxn);
+            dxn = fma(d1(j), in[j], dxn);
         }
         double e0 = eta0 * (g0 * x0 + ih * dx0);   // added to out[0]
         double en = eta1 * (g1 * xn - ih * dxn);   // added to out[N1-1]
@@ -328,7 +333,7 @@ __device__ __forceinline__ void sipg_line(const double *in, const double *nl, co
         if (hasl) {
             double dl = 0.0;
 #pragma unroll
-            for (int j = 0; j < N1; ++j) dl = fma((double)d1[j], nl[j], dl);
+            for (int j = 0; j < N1; ++j) dl = fma(d1(j), nl[j], dl);
             const double xl = nl[N1 - 1];
             e0 += 0.5 * (dl * ihl - g0 * xl);
             c0 -= 0.5 * ih * xl;
@@ -344,7 +349,7 @@ __device__ __forceinline__ void sipg_line(const double *in, const double *nl, co
         out[0] += e0;
         out[N1 - 1] += en;
 #pragma unroll
-        for (int o = 0; o < N1; ++o) out[o] = fma((double)d0[o], c0, fma((double)d1[o], c1, out[o]));
+        for (int o = 0; o < N1; ++o) out[o] = fma((double)d0[o], c0, fma(d1(o), c1, out[o]));
     }
 }
 
@@ -378,7 +383,7 @@ __device__ __forceinline__ void operator_cells(const LevelView &g, int64_t cell0
     const bool act = q < nact;
     const cptr<double> LE = uniform_table(g.Leo), ME = uniform_table(g.Meo);
     const cptr<double> LO = LE + HE * HE, MO = ME + HE * HE;
-    const cptr<double> d0 = uniform_table(g.d0), d1 = uniform_table(g.d1);
+    const cptr<double> d0 = uniform_table(g.d0);
     const double gk = PEN ? g.pk : g.gk;
     // padded LDS index of cell-local coefficient (i0, i1, i2)
     auto li = [](int i0, int i1, int i2) { return i0 + P * (i1 + N1 * i2); };
@@ -446,7 +451,7 @@ __device__ __forceinline__ void operator_cells(const LevelView &g, int64_t cell0
             for (int j = 0; j < N1; ++j) nr[j] = src[line_idx(a, j)];
             ihr = g.ih[a][c[a] + 1];
         }
-        sipg_line<N1, PEN>(in, nl, nr, hasl, hasr, g.ih[a][c[a]], ihl, ihr, gk, LE, LO, d0, d1, w);
+        sipg_line<N1, PEN>(in, nl, nr, hasl, hasr, g.ih[a][c[a]], ihl, ihr, gk, LE, LO, d0, w);
     };
     auto ld = [&](int slot, int a, double *v) {
 #pragma unroll

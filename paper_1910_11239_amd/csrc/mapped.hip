@@ -208,7 +208,11 @@ k_mapped_operator(MappedView g, const double *__restrict__ x, const double *__re
     // ---- faces
     const int cc[3] = {(int)(cell % g.m[0]), (int)((cell / g.m[0]) % g.m[1]),
                        (int)(cell / ((int64_t)g.m[0] * g.m[1]))};
+    // faces unrolled: the face axis and side are compile-time constants, so
+    // the small per-point arrays indexed by them stay in registers
+#pragma unroll
     for (int tt = 0; tt < D; ++tt)
+#pragma unroll
         for (int side = 0; side < 2; ++side) {
             const bool interior = side == 0 ? cc[tt] > 0 : cc[tt] < g.m[tt] - 1;
             int64_t nb = -1;
