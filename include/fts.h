@@ -155,11 +155,15 @@ int32_t fts_eigs_n(const fts_eigs *eigs);
  *        (patches on tile borders are computed by each neighbouring tile) and
  *        sums their corrections in on-chip memory in a fixed order before
  *        updating x once; no staging buffer.  Deterministic.  Other
- *        precisions and cells fall back to FTS_SCHEDULE_STAGED.  The default.
+ *        precisions and cells fall back to FTS_SCHEDULE_STAGED.
+ *   FTS_SCHEDULE_AUTO    FTS_SCHEDULE_OWNER on levels of at least 4,096
+ *        cells, FTS_SCHEDULE_STAGED below (where one tile launch is too short
+ *        to fill the GPU and the staged runs are faster).  The default.
  * Ignored for cells (disjoint, one launch). */
 #define FTS_SCHEDULE_STAGED 0
 #define FTS_SCHEDULE_COLORED 1
 #define FTS_SCHEDULE_OWNER 2
+#define FTS_SCHEDULE_AUTO 3
 fts_status fts_eigs_set_schedule(fts_eigs *eigs, int32_t schedule);
 
 /* ---- a4: matrix-free SIPG operator --------------------------------------- */
@@ -181,7 +185,7 @@ size_t fts_smooth_ws_bytes(const fts_level *level);
  *     r = b - A x;   x <- x + omega * sum_j R_j^T A_j^-1 R_j r
  * with A_j^-1 = (S x..x S) diag(1/Lambda) (S x..x S)^T (eq. fastinverse).
  * Overlapping vertex patches are summed as set by fts_eigs_set_schedule
- * (default: owner tiles for 16-bit, else staged; deterministic).  ws: device workspace of
+ * (default FTS_SCHEDULE_AUTO; deterministic).  ws: device workspace of
  * fts_smooth_ws_bytes bytes. */
 fts_status fts_schwarz_smooth(const fts_level *level, const fts_eigs *eigs, double omega,
                               fts_prec prec, const double *b, double *x, int32_t nsweeps, void *ws,

@@ -230,10 +230,11 @@ class Eigs:
             self._h = None
 
     def set_schedule(self, schedule):
-        """'owner' (default: owner-computes tiles for 16-bit 3-D vertex patches,
+        """'auto' (default: 'owner' on levels of at least 4,096 cells, 'staged'
+        below), 'owner' (owner-computes tiles for 16-bit 3-D vertex patches,
         staged otherwise), 'staged' (deterministic staging buffer + gather) or
         'colored' (2^d parquet colors)."""
-        _check(lib().fts_eigs_set_schedule(self._h, {"staged": 0, "colored": 1, "owner": 2}[schedule]),
+        _check(lib().fts_eigs_set_schedule(self._h, {"staged": 0, "colored": 1, "owner": 2, "auto": 3}[schedule]),
                "fts_eigs_set_schedule")
 
     def get(self, axis, index):

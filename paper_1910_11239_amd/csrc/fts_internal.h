@@ -87,6 +87,16 @@ struct LevelView {
     double gk, pk;            // gamma_hat k (k+1) and k (k+1)
 };
 
+// Levels of at least this many cells use the owner tiles under FTS_SCHEDULE_AUTO.
+constexpr int64_t kOwnerMinCells = 4096;
+
+// The schedule a call of the 16-bit vertex-patch smoother actually runs:
+// FTS_SCHEDULE_AUTO resolved by the level size.
+inline int effective_schedule(int schedule, int64_t ncells) {
+    if (schedule != FTS_SCHEDULE_AUTO) return schedule;
+    return ncells >= kOwnerMinCells ? FTS_SCHEDULE_OWNER : FTS_SCHEDULE_STAGED;
+}
+
 // Cell runs of the matrix-free operator launch.  Workgroups are handed to the
 // 8 XCDs round-robin (block b to XCD b % 8), and each XCD has its own L2.  The
 // rows (y, z) are split into min(8, m_y) groups of consecutive y; at fixed z
@@ -207,7 +217,7 @@ struct fts_eigs {
                                 // FP64 or FP32 values, sized for FP64)
     double *d_stage_scale = nullptr;  // one FP64 factor per patch for the 16-bit path
     void *d_mfma = nullptr;     // 16-bit MFMA tables (n <= 16 only)
-    int schedule = FTS_SCHEDULE_OWNER;  // owner tiles for 16-bit 3-D vertex patches, else staged
+    int schedule = FTS_SCHEDULE_AUTO;  // owner tiles for 16-bit 3-D vertex patches on large levels, else staged
     fts::EigView view{};
 };
 

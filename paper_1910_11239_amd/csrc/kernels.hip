@@ -1105,7 +1105,8 @@ fts_status smooth_additive(const fts_level *lv, const fts_eigs *eg, double omega
                            double *x, void *rbuf, bool x_zero, hipStream_t stream) {
     if (x_zero) return launch_schwarz(lv, eg, omega, prec, b, x, stream);  // r = b - A 0 = b
     const bool f32r = (prec == FTS_PREC_BF16 || prec == FTS_PREC_F16) && lv->dim == 3 &&
-                      eg->kind == FTS_VERTEX_PATCH && eg->schedule == FTS_SCHEDULE_OWNER && lv->n1 <= 8 &&
+                      eg->kind == FTS_VERTEX_PATCH && effective_schedule(eg->schedule, lv->ncells) == FTS_SCHEDULE_OWNER &&
+                      lv->n1 <= 8 &&
                       reinterpret_cast<uintptr_t>(rbuf) % 16 == 0;
     if (!f32r) {
         double *r = static_cast<double *>(rbuf);
@@ -1182,7 +1183,8 @@ struct RunSchwarz {
             return fail(FTS_E_UNSUPPORTED, "16-bit MFMA contractions need d = 3 and n <= 16");
         } else {
             if constexpr (KIND == 1) {
-                if (eg->schedule == FTS_SCHEDULE_OWNER && reinterpret_cast<uintptr_t>(r) % 16 == 0)
+                if (effective_schedule(eg->schedule, lv->ncells) == FTS_SCHEDULE_OWNER &&
+                    reinterpret_cast<uintptr_t>(r) % 16 == 0)
                     return launch_schwarz_mfma_tile(lv, eg, omega, BF, r, false, x, st);
             }
             const bool staged = KIND == 1 && eg->schedule != FTS_SCHEDULE_COLORED;

@@ -842,7 +842,8 @@ fts_status fts_setup_1d_eigs(const fts_level *lv, fts_patch_kind kind, fts_eigs 
 
 fts_status fts_eigs_set_schedule(fts_eigs *eigs, int32_t schedule) {
     if (!eigs) return fail(FTS_E_INVAL, "fts_eigs_set_schedule: NULL handle");
-    if (schedule != FTS_SCHEDULE_STAGED && schedule != FTS_SCHEDULE_COLORED && schedule != FTS_SCHEDULE_OWNER)
+    if (schedule != FTS_SCHEDULE_STAGED && schedule != FTS_SCHEDULE_COLORED && schedule != FTS_SCHEDULE_OWNER &&
+        schedule != FTS_SCHEDULE_AUTO)
         return fail(FTS_E_INVAL, "fts_eigs_set_schedule: unknown schedule");
     if (schedule != FTS_SCHEDULE_COLORED && eigs->kind == FTS_VERTEX_PATCH && !eigs->d_stage)
         return fail(FTS_E_INVAL, "fts_eigs_set_schedule: these eigen-data have no staging buffer");
