@@ -125,6 +125,218 @@ __device__ void load_corners(const MappedView &g, int64_t cell, double *X) {
     }
 }
 
+// Layout of the face work arrays (doubles) inside the kernel's work buffer,
+// NF = points of a face: value and normal-derivative node layers of both
+// sides [sd][kind][NF], the first tangential stage [sd][3][NF], values and
+// reference gradients at the face's Gauss points [sd][NF], [sd][D][NF], the
+// test coefficients [NF], [D][NF], the first stage of their test [4][NF] and
+// the layer sums [NF] x 2.
+template <int D, int NF>
+struct FaceWork {
+    static constexpr int LAY = 0, S1 = LAY + 4 * NF, FV = S1 + 6 * NF, FG = FV + 2 * NF, CV = FG + 2 * D * NF,
+                         CG = CV + NF, S2 = CG + D * NF, LT = S2 + 4 * NF, T2T = LT + NF, SIZE = T2T + NF;
+};
+
+// The terms of face (TT, SIDE) of one cell, added to Y: traces of u and of the
+// neighbour's u at the face's Gauss points (node layer at the face and normal
+// derivative layer, then interpolation along the tangential axes TA, TB),
+// the pointwise SIPG integrands (jump, average normal flux, penalty) and
+// their test against the cell's basis.  Every stage is one pass over all of
+// its outputs (both sides, all quantities) and ends with a barrier.
+template <int D, int N1, int TT, int SIDE>
+__device__ __forceinline__ void face_terms(const MappedView &g, int64_t cell, const int *cc,
+                                           const double *__restrict__ x, const double *U, double *Un,
+                                           const double *X, double *Xn, const double *sV, const double *sD,
+                                           const double *sxq, const double *swq, const double *sde, double *work,
+                                           double *Y) {
+    constexpr int NC = D == 2 ? N1 * N1 : N1 * N1 * N1;
+    constexpr int NF = D == 2 ? N1 : N1 * N1;
+    constexpr int TA = TT == 0 ? 1 : 0, TB = D == 3 ? (TT == 2 ? 1 : 2) : 0;
+    using W = FaceWork<D, NF>;
+    double *Lay = work + W::LAY, *S1 = work + W::S1, *Fv = work + W::FV, *Fg = work + W::FG, *Cv = work + W::CV,
+           *Cg = work + W::CG, *S2 = work + W::S2, *Lt = work + W::LT, *T2t = work + W::T2T;
+    const int t = threadIdx.x, nth = blockDim.x;
+    // index in the cell tensor of node it along TT, ia along TA, ib along TB
+    auto cidx = [](int it, int ia, int ib) {
+        int o[3] = {0, 0, 0};
+        o[TT] = it;
+        o[TA] = ia;
+        if constexpr (D == 3) o[TB] = ib;
+        return o[0] + N1 * (o[1] + N1 * o[2]);
+    };
+    const bool interior = SIDE == 0 ? cc[TT] > 0 : cc[TT] < g.m[TT] - 1;
+    if (interior) {
+        int64_t st = 1;
+        for (int a = 0; a < TT; ++a) st *= g.m[a];
+        const int64_t nb = cell + (SIDE == 0 ? -st : st);
+        load_corners<D>(g, nb, Xn);
+        for (int e = t; e < NC; e += nth) Un[e] = x[nb * NC + e];
+        __syncthreads();
+    }
+    const int nsd = interior ? 2 : 1;
+    // node layers: value at the face's node layer and normal derivative
+    for (int e = t; e < nsd * 2 * NF; e += nth) {
+        const int sd = e / (2 * NF), kind = (e / NF) % 2, lp = e % NF;
+        const int ia = lp % N1, ib = lp / N1;
+        const double *Us = sd ? Un : U;
+        const int sh = sd ? 1 - SIDE : SIDE;
+        double v;
+        if (kind == 0) {
+            v = Us[cidx(sh * (N1 - 1), ia, ib)];
+        } else {
+            v = 0.0;
+#pragma unroll
+            for (int i = 0; i < N1; ++i) v += sde[sh * N1 + i] * Us[cidx(i, ia, ib)];
+        }
+        Lay[(sd * 2 + kind) * NF + lp] = v;
+    }
+    __syncthreads();
+    // along TA: V (values), V (normal derivative), D (tangential derivative along TA)
+    for (int e = t; e < nsd * 3 * NF; e += nth) {
+        const int sd = e / (3 * NF), out = (e / NF) % 3, r = e % NF;
+        const int ga = r % N1, ib = r / N1;
+        const double *M = out == 2 ? sD : sV;
+        const double *src = Lay + (sd * 2 + (out == 1 ? 1 : 0)) * NF + N1 * ib;
+        double v = 0.0;
+#pragma unroll
+        for (int ia = 0; ia < N1; ++ia) v += M[ga * N1 + ia] * src[ia];
+        if constexpr (D == 2) {
+            double *dst = out == 0 ? Fv + sd * NF : Fg + (sd * D + (out == 1 ? TT : TA)) * NF;
+            dst[r] = v;
+        } else {
+            S1[(sd * 3 + out) * NF + r] = v;
+        }
+    }
+    __syncthreads();
+    if constexpr (D == 3) {
+        // along TB: values, normal derivative, derivative along TA, derivative along TB
+        for (int e = t; e < nsd * 4 * NF; e += nth) {
+            const int sd = e / (4 * NF), out = (e / NF) % 4, p = e % NF;
+            const int ga = p % N1, gb = p / N1;
+            const double *M = out == 3 ? sD : sV;
+            const double *src = S1 + (sd * 3 + (out == 3 ? 0 : out)) * NF + ga;
+            double v = 0.0;
+#pragma unroll
+            for (int ib = 0; ib < N1; ++ib) v += M[gb * N1 + ib] * src[N1 * ib];
+            double *dst = out == 0 ? Fv + sd * NF : Fg + (sd * D + (out == 1 ? TT : (out == 2 ? TA : TB))) * NF;
+            dst[p] = v;
+        }
+        __syncthreads();
+    }
+    // pointwise face terms: coefficients of phi_i and of grad_xi phi_i
+    const double pen = g.pen[cell * 2 * D + 2 * TT + SIDE];
+    for (int p = t; p < NF; p += nth) {
+        const int ga = p % N1, gb = p / N1;
+        double xi[D], xin[D];
+        xi[TT] = SIDE;
+        xin[TT] = 1 - SIDE;
+        xi[TA] = xin[TA] = sxq[ga];
+        double wf = swq[ga];
+        if constexpr (D == 3) {
+            xi[TB] = xin[TB] = sxq[gb];
+            wf *= swq[gb];
+        }
+        double Ji[D][D];
+        const double det = jacobian_inverse<D>(X, xi, Ji);
+        double nrm = 0.0;
+        for (int b = 0; b < D; ++b) nrm += Ji[TT][b] * Ji[TT][b];
+        nrm = sqrt(nrm);
+        const double sgn = SIDE ? 1.0 : -1.0;
+        double n[D];
+        for (int b = 0; b < D; ++b) n[b] = sgn * Ji[TT][b] / nrm;
+        const double dS = wf * fabs(det) * nrm;
+        double dnm = 0.0;  // normal derivative of u on this side
+        for (int b = 0; b < D; ++b) {
+            double ph = 0.0;
+            for (int a = 0; a < D; ++a) ph += Ji[a][b] * Fg[a * NF + p];
+            dnm += ph * n[b];
+        }
+        double cv, jmp;
+        if (interior) {
+            double Jn[D][D];
+            (void)jacobian_inverse<D>(Xn, xin, Jn);
+            double dnp = 0.0;
+            for (int b = 0; b < D; ++b) {
+                double ph = 0.0;
+                for (int a = 0; a < D; ++a) ph += Jn[a][b] * Fg[(D + a) * NF + p];
+                dnp += ph * n[b];
+            }
+            jmp = Fv[p] - Fv[NF + p];
+            cv = dS * (pen * jmp - 0.5 * (dnm + dnp));
+            jmp *= 0.5;
+        } else {
+            jmp = Fv[p];
+            cv = dS * (pen * jmp - dnm);
+        }
+        // - jmp dS n . grad phi_i = grad_xi phi_i . (J^-1 (-jmp dS n))
+        Cv[p] = cv;
+        for (int a = 0; a < D; ++a) {
+            double s2 = 0.0;
+            for (int b = 0; b < D; ++b) s2 += Ji[a][b] * n[b];
+            Cg[a * NF + p] = -jmp * dS * s2;
+        }
+    }
+    __syncthreads();
+    // test, along TA (transposed): value and tangential-gradient terms land on
+    // the node layer of the face, the normal-gradient term spreads over the
+    // layers with phi_i'(SIDE)
+    if constexpr (D == 2) {
+        for (int e = t; e < 2 * N1; e += nth) {
+            const int out = e / N1, ia = e % N1;
+            double v = 0.0;
+            if (out == 0) {
+#pragma unroll
+                for (int ga = 0; ga < N1; ++ga) v += sV[ga * N1 + ia] * Cv[ga] + sD[ga * N1 + ia] * Cg[TA * NF + ga];
+                Lt[ia] = v;
+            } else {
+#pragma unroll
+                for (int ga = 0; ga < N1; ++ga) v += sV[ga * N1 + ia] * Cg[TT * NF + ga];
+                T2t[ia] = v;
+            }
+        }
+        __syncthreads();
+    } else {
+        for (int e = t; e < 4 * NF; e += nth) {
+            const int out = e / NF, r = e % NF;
+            const int ia = r % N1, gb = r / N1;
+            const double *M = out == 1 ? sD : sV;
+            const double *src = (out == 0 ? Cv : Cg + (out == 1 ? TA : (out == 2 ? TB : TT)) * NF) + N1 * gb;
+            double v = 0.0;
+#pragma unroll
+            for (int ga = 0; ga < N1; ++ga) v += M[ga * N1 + ia] * src[ga];
+            S2[out * NF + r] = v;
+        }
+        __syncthreads();
+        for (int e = t; e < 2 * NF; e += nth) {
+            const int out = e / NF, r = e % NF;
+            const int ia = r % N1, ib = r / N1;
+            double v = 0.0;
+            if (out == 0) {
+#pragma unroll
+                for (int gb = 0; gb < N1; ++gb) {
+                    const int q = ia + N1 * gb;
+                    v += sV[gb * N1 + ib] * (S2[q] + S2[NF + q]) + sD[gb * N1 + ib] * S2[2 * NF + q];
+                }
+                Lt[r] = v;
+            } else {
+#pragma unroll
+                for (int gb = 0; gb < N1; ++gb) v += sV[gb * N1 + ib] * S2[3 * NF + ia + N1 * gb];
+                T2t[r] = v;
+            }
+        }
+        __syncthreads();
+    }
+    for (int p = t; p < NC; p += nth) {
+        int o[3] = {p % N1, (p / N1) % N1, p / (N1 * N1)};
+        const int it = o[TT];
+        const int lp = o[TA] + (D == 3 ? N1 * o[TB] : 0);
+        double add = sde[SIDE * N1 + it] * T2t[lp];
+        if (it == SIDE * (N1 - 1)) add += Lt[lp];
+        Y[p] += add;
+    }
+    __syncthreads();
+}
+
 // y = A x (or r = b - A x) on every cell; grid = ncells, one cell per workgroup.
 template <int D, int N1, bool RES>
 __global__ void __launch_bounds__(kMapThreads)
@@ -134,11 +346,13 @@ k_mapped_operator(MappedView g, const double *__restrict__ x, const double *__re
     constexpr int NF = D == 2 ? N1 : N1 * N1;  // points of a face
     __shared__ double sV[N1 * N1], sD[N1 * N1], sxq[N1], swq[N1], sde[2 * N1];
     __shared__ double X[8 * 3], Xn[8 * 3];
-    __shared__ double U[NC], Un[NC], Y[NC], T1[NC], T2[NC];
-    __shared__ double G[D][NC];   // reference gradients, then fluxes
-    __shared__ double Fv[2][NF];  // face values (this cell, neighbour)
-    __shared__ double Fg[2][D][NF];  // face reference gradients
-    __shared__ double Cv[NF], Cg[D][NF];  // face test coefficients
+    __shared__ double U[NC], Un[NC], Y[NC];
+    // volume stage: T1, T2 and the reference gradients / fluxes G[0..D-1];
+    // then the face stages (FaceWork)
+    constexpr int NW = 5 * NC > FaceWork<D, NF>::SIZE ? 5 * NC : FaceWork<D, NF>::SIZE;
+    __shared__ double work[NW];
+    double *T1 = work, *T2 = work + NC;
+    auto G = [&](int a) { return work + (2 + a) * NC; };
     const int64_t cell = blockIdx.x;
     const int t = threadIdx.x;
     for (int e2 = t; e2 < N1 * N1; e2 += blockDim.x) {
@@ -163,10 +377,10 @@ k_mapped_operator(MappedView g, const double *__restrict__ x, const double *__re
     for (int a = 0; a < D; ++a) {
         contract<D>(U, ec, 0, a == 0 ? sD : sV, N1, false, N1, T1, false);
         if constexpr (D == 2) {
-            contract<D>(T1, ec, 1, a == 1 ? sD : sV, N1, false, N1, G[a], false);
+            contract<D>(T1, ec, 1, a == 1 ? sD : sV, N1, false, N1, G(a), false);
         } else {
             contract<D>(T1, ec, 1, a == 1 ? sD : sV, N1, false, N1, T2, false);
-            contract<D>(T2, ec, 2, a == 2 ? sD : sV, N1, false, N1, G[a], false);
+            contract<D>(T2, ec, 2, a == 2 ? sD : sV, N1, false, N1, G(a), false);
         }
     }
     for (int p = t; p < NC; p += blockDim.x) {
@@ -179,7 +393,7 @@ k_mapped_operator(MappedView g, const double *__restrict__ x, const double *__re
         double Ji[D][D];
         const double det = jacobian_inverse<D>(X, xi, Ji);
         double gr[D], fl[D];
-        for (int a = 0; a < D; ++a) gr[a] = G[a][p];
+        for (int a = 0; a < D; ++a) gr[a] = G(a)[p];
         // physical gradient J^-T gr, then back: flux_a = w det sum_b Ji[a][b] (J^-T gr)_b
         double ph[D];
         for (int b = 0; b < D; ++b) {
@@ -191,176 +405,34 @@ k_mapped_operator(MappedView g, const double *__restrict__ x, const double *__re
             for (int b = 0; b < D; ++b) fl[a] += Ji[a][b] * ph[b];
             fl[a] *= w * det;
         }
-        for (int a = 0; a < D; ++a) G[a][p] = fl[a];
+        for (int a = 0; a < D; ++a) G(a)[p] = fl[a];
     }
     __syncthreads();
     for (int a = 0; a < D; ++a) {
         if constexpr (D == 2) {
-            contract<D>(G[a], ec, 0, a == 0 ? sD : sV, N1, true, N1, T1, false);
+            contract<D>(G(a), ec, 0, a == 0 ? sD : sV, N1, true, N1, T1, false);
             contract<D>(T1, ec, 1, a == 1 ? sD : sV, N1, true, N1, Y, true);
         } else {
-            contract<D>(G[a], ec, 0, a == 0 ? sD : sV, N1, true, N1, T1, false);
+            contract<D>(G(a), ec, 0, a == 0 ? sD : sV, N1, true, N1, T1, false);
             contract<D>(T1, ec, 1, a == 1 ? sD : sV, N1, true, N1, T2, false);
             contract<D>(T2, ec, 2, a == 2 ? sD : sV, N1, true, N1, Y, true);
         }
     }
 
-    // ---- faces
+    // ---- faces, one after the other (fixed order: axis, then lower and upper side)
     const int cc[3] = {(int)(cell % g.m[0]), (int)((cell / g.m[0]) % g.m[1]),
                        (int)(cell / ((int64_t)g.m[0] * g.m[1]))};
-    // faces unrolled: the face axis and side are compile-time constants, so
-    // the small per-point arrays indexed by them stay in registers
-#pragma unroll
-    for (int tt = 0; tt < D; ++tt)
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-            const bool interior = side == 0 ? cc[tt] > 0 : cc[tt] < g.m[tt] - 1;
-            int64_t nb = -1;
-            if (interior) {
-                int64_t st = 1;
-                for (int a = 0; a < tt; ++a) st *= g.m[a];
-                nb = cell + (side == 0 ? -st : st);
-                load_corners<D>(g, nb, Xn);
-                for (int e2 = t; e2 < NC; e2 += blockDim.x) Un[e2] = x[nb * NC + e2];
-                __syncthreads();
-            }
-            // traces: layer tensors have extent 1 along tt
-            int el[3] = {N1, N1, D == 3 ? N1 : 1};
-            el[tt] = 1;
-            for (int sd = 0; sd < (interior ? 2 : 1); ++sd) {
-                const double *Us = sd == 0 ? U : Un;
-                const int s_here = sd == 0 ? side : 1 - side;
-                const double *dvec = sde + s_here * N1;
-                // value layer (the Gauss-Lobatto node layer on the face) into T1,
-                // normal derivative layer sum_i phi_i'(s) u[.., i, ..] into T2
-                contract<D>(Us, ec, tt, dvec, 0, false, 1, T2, false);
-                {
-                    const int lay = s_here * (N1 - 1);
-                    const int tot = NC / N1;
-                    for (int p = t; p < tot; p += blockDim.x) {
-                        // p enumerates the layer (extent 1 along tt)
-                        int o[3] = {p % el[0], (p / el[0]) % el[1], p / (el[0] * el[1])};
-                        o[tt] = lay;
-                        T1[p] = Us[o[0] + N1 * (o[1] + N1 * o[2])];
-                    }
-                    __syncthreads();
-                }
-                // interpolate along the tangential axes: values, normal derivative,
-                // tangential derivatives
-                const int ta = tt == 0 ? 1 : 0, tb = D == 3 ? (tt == 2 ? 1 : 2) : -1;
-                int e1[3] = {el[0], el[1], el[2]};
-                int e2x[3] = {el[0], el[1], el[2]};
-                e2x[ta] = N1;
-                double *dst_v = Fv[sd];
-                double *dst_n = Fg[sd][tt];
-                if constexpr (D == 2) {
-                    contract<D>(T1, e1, ta, sV, N1, false, N1, dst_v, false);
-                    contract<D>(T2, e1, ta, sV, N1, false, N1, dst_n, false);
-                    contract<D>(T1, e1, ta, sD, N1, false, N1, Fg[sd][ta], false);
-                } else {
-                    // values and normal derivative: V along ta then tb
-                    contract<D>(T1, e1, ta, sV, N1, false, N1, G[0], false);
-                    contract<D>(G[0], e2x, tb, sV, N1, false, N1, dst_v, false);
-                    contract<D>(T2, e1, ta, sV, N1, false, N1, G[0], false);
-                    contract<D>(G[0], e2x, tb, sV, N1, false, N1, dst_n, false);
-                    // tangential derivative along ta: D along ta, V along tb
-                    contract<D>(T1, e1, ta, sD, N1, false, N1, G[0], false);
-                    contract<D>(G[0], e2x, tb, sV, N1, false, N1, Fg[sd][ta], false);
-                    // along tb: V along ta, D along tb
-                    contract<D>(T1, e1, ta, sV, N1, false, N1, G[0], false);
-                    contract<D>(G[0], e2x, tb, sD, N1, false, N1, Fg[sd][tb], false);
-                }
-            }
-            // pointwise face terms: coefficients of phi_i and of grad_xi phi_i
-            const double pen = g.pen[cell * 2 * D + 2 * tt + side];
-            for (int p = t; p < NF; p += blockDim.x) {
-                int o[3] = {p % el[0], (p / el[0]) % el[1], p / (el[0] * el[1])};
-                double xi[D], xin[D], wf = 1.0;
-                for (int a = 0; a < D; ++a) {
-                    if (a == tt) {
-                        xi[a] = side;
-                        xin[a] = 1 - side;
-                    } else {
-                        xi[a] = xin[a] = sxq[o[a]];
-                        wf *= swq[o[a]];
-                    }
-                }
-                double Ji[D][D];
-                const double det = jacobian_inverse<D>(X, xi, Ji);
-                double nrm = 0.0;
-                for (int b = 0; b < D; ++b) nrm += Ji[tt][b] * Ji[tt][b];
-                nrm = sqrt(nrm);
-                const double sgn = side ? 1.0 : -1.0;
-                double n[D];
-                for (int b = 0; b < D; ++b) n[b] = sgn * Ji[tt][b] / nrm;
-                const double dS = wf * fabs(det) * nrm;
-                double dnm = 0.0;  // normal derivative of u on this side
-                for (int b = 0; b < D; ++b) {
-                    double ph = 0.0;
-                    for (int a = 0; a < D; ++a) ph += Ji[a][b] * Fg[0][a][p];
-                    dnm += ph * n[b];
-                }
-                double cv, jmp;
-                if (interior) {
-                    double Jn[D][D];
-                    (void)jacobian_inverse<D>(Xn, xin, Jn);
-                    double dnp = 0.0;
-                    for (int b = 0; b < D; ++b) {
-                        double ph = 0.0;
-                        for (int a = 0; a < D; ++a) ph += Jn[a][b] * Fg[1][a][p];
-                        dnp += ph * n[b];
-                    }
-                    jmp = Fv[0][p] - Fv[1][p];
-                    cv = dS * (pen * jmp - 0.5 * (dnm + dnp));
-                    jmp *= 0.5;
-                } else {
-                    jmp = Fv[0][p];
-                    cv = dS * (pen * jmp - dnm);
-                }
-                // - jmp dS n . grad phi_i = grad_xi phi_i . (J^-1 (-jmp dS n))
-                Cv[p] = cv;
-                for (int a = 0; a < D; ++a) {
-                    double s2 = 0.0;
-                    for (int b = 0; b < D; ++b) s2 += Ji[a][b] * n[b];
-                    Cg[a][p] = -jmp * dS * s2;
-                }
-            }
-            __syncthreads();
-            // test: value and tangential gradient terms land on the node layer of
-            // the face, the normal gradient term spreads over the layers with
-            // phi_i'(side)
-            {
-                const int ta = tt == 0 ? 1 : 0, tb = D == 3 ? (tt == 2 ? 1 : 2) : -1;
-                int e1[3] = {el[0], el[1], el[2]};  // layer extents (N1 on tangential axes)
-                double *L = T1;                        // layer accumulator
-                if constexpr (D == 2) {
-                    contract<D>(Cv, e1, ta, sV, N1, true, N1, L, false);
-                    contract<D>(Cg[ta], e1, ta, sD, N1, true, N1, L, true);
-                    contract<D>(Cg[tt], e1, ta, sV, N1, true, N1, T2, false);
-                } else {
-                    contract<D>(Cv, e1, ta, sV, N1, true, N1, G[0], false);
-                    contract<D>(G[0], e1, tb, sV, N1, true, N1, L, false);
-                    contract<D>(Cg[ta], e1, ta, sD, N1, true, N1, G[0], false);
-                    contract<D>(G[0], e1, tb, sV, N1, true, N1, L, true);
-                    contract<D>(Cg[tb], e1, ta, sV, N1, true, N1, G[0], false);
-                    contract<D>(G[0], e1, tb, sD, N1, true, N1, L, true);
-                    contract<D>(Cg[tt], e1, ta, sV, N1, true, N1, G[0], false);
-                    contract<D>(G[0], e1, tb, sV, N1, true, N1, T2, false);
-                }
-                const double *dvec = sde + side * N1;
-                const int lay = side * (N1 - 1);
-                for (int p = t; p < NC; p += blockDim.x) {
-                    int o[3] = {p % N1, (p / N1) % N1, p / (N1 * N1)};
-                    const int it = o[tt];
-                    o[tt] = 0;
-                    const int lp = o[0] + el[0] * (o[1] + el[1] * o[2]);
-                    double add = dvec[it] * T2[lp];
-                    if (it == lay) add += L[lp];
-                    Y[p] += add;
-                }
-                __syncthreads();
-            }
-        }
+#define FTS_FACE(TT, SIDE) \
+    face_terms<D, N1, TT, SIDE>(g, cell, cc, x, U, Un, X, Xn, sV, sD, sxq, swq, sde, work, Y);
+    FTS_FACE(0, 0)
+    FTS_FACE(0, 1)
+    FTS_FACE(1, 0)
+    FTS_FACE(1, 1)
+    if constexpr (D == 3) {
+        FTS_FACE(2, 0)
+        FTS_FACE(2, 1)
+    }
+#undef FTS_FACE
     for (int e2 = t; e2 < NC; e2 += blockDim.x) {
         const int64_t gi = cell * NC + e2;
         y[gi] = RES ? bvec[gi] - Y[e2] : Y[e2];
