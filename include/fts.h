@@ -441,6 +441,32 @@ size_t fts_mapped_smooth_ws_bytes(const fts_mapped_level *level);
 fts_status fts_mapped_schwarz_smooth(const fts_mapped_level *level, double omega, const double *b, double *x,
                                      int32_t nsweeps, void *ws, size_t ws_bytes, void *stream);
 
+/* Multigrid on mapped meshes (Sec. 4 with Alg. gmg).  levels[0..nlevels-1],
+ * coarsest first, same dim, degree and penalty factor; level l+1 has twice
+ * the cells of level l per axis and its cells are the images of the children
+ * of level l's cells under their maps (uniform refinement on the multilinear
+ * cell maps, so the spaces are nested and the grid transfers are the
+ * reference-cell embeddings of the Cartesian hierarchy).  Smoother on levels
+ * l >= 1: omega_per_level[l], m_pre / m_post steps of the additive cell
+ * smoother with Cartesian surrogate local solvers; level 0: the mapped
+ * operator's own matrix (probed column by column) factored by the slab LU of
+ * the Cartesian coarse solver.  Allocates through the registered allocator. */
+typedef struct fts_mapped_hierarchy fts_mapped_hierarchy;
+fts_status fts_mapped_hierarchy_create(const fts_mapped_desc *levels, int32_t nlevels,
+                                       const double *omega_per_level, int32_t m_pre, int32_t m_post,
+                                       fts_mapped_hierarchy **out);
+fts_status fts_mapped_hierarchy_destroy(fts_mapped_hierarchy *hier);
+int64_t fts_mapped_hierarchy_ndofs(const fts_mapped_hierarchy *hier);
+/* x <- MG_L(x, b) on the finest level. */
+fts_status fts_mapped_vcycle(fts_mapped_hierarchy *hier, const double *b, double *x, void *stream);
+/* FP64 CG preconditioned by one V-cycle (x = 0 initial guess of the V-cycle),
+ * as fts_pcg: stops at ||r|| <= rtol ||b||; history (maxit + 1 doubles, may
+ * be NULL) gets ||r_i|| / ||b||; ws: fts_mapped_pcg_ws_bytes bytes. */
+size_t fts_mapped_pcg_ws_bytes(const fts_mapped_hierarchy *hier);
+fts_status fts_mapped_pcg(fts_mapped_hierarchy *hier, const double *b, double *x, double rtol, int32_t maxit,
+                          void *ws, size_t ws_bytes, int32_t *iters, double *relres, double *history,
+                          void *stream);
+
 #ifdef __cplusplus
 }
 #endif

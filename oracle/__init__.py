@@ -29,6 +29,13 @@ Galerkin methods"):
 * ``sampled``   the same definitions restricted to a few cells of a large mesh
                 (residual and one smoothing step need only a bounded
                 neighbourhood), for parity checks at full problem size.
+* ``tangent``   forward-mode derivatives of the V-cycle iteration with respect
+                to the right-hand side, the damping and the penalty factor of
+                every level, propagated step by step.
+* ``mapped``    SIPG on multilinearly mapped cells (Sec. 4): the assembled
+                matrix, load and boundary terms by quadrature, the Cartesian
+                surrogate cell solvers (eq. avglength), the surrogate
+                additive smoother and the mapped-mesh V-cycle.
 
 Functions with no independent pin say "parity unpinned" in their docstring.
 """

@@ -36,8 +36,11 @@ Pins (tests/test_oracle_mapped.py): on rectilinear vertex grids the mapped
 matrix equals ``sipg.assemble`` and the surrogate solver equals the exact local
 solver; on distorted meshes A is symmetric positive definite (gamma_hat = 4)
 and reproduces linear functions with their boundary data exactly (A u_I = b,
-which fixes volume, face normal, area element and consistency terms); the
-surrogate widths of affine cells are their edge lengths.
+which fixes volume, face normal, area element and consistency terms) and,
+with the volume load, quadratics with their Laplacian (k >= 2, where every
+integrand is a polynomial the rule integrates exactly); the right-hand side
+equals ``sipg.rhs`` on rectilinear grids; the surrogate widths of affine cells
+are their edge lengths.
 """
 import itertools
 
@@ -276,6 +279,22 @@ def rhs_boundary(mesh, g):
     return b
 
 
+def rhs(mesh, f, g=None):
+    """Right-hand side of eq. (sipg) on the mapped cells: int_Omega f v plus,
+    for Dirichlet data g, the boundary terms of ``rhs_boundary``; the volume
+    integral uses the operator's rule (k+1 Gauss points per axis, weights
+    times det J).  f, g: callables on an (npts, d) array of physical points."""
+    d, tab = mesh.dim, _Tab(mesh.k)
+    pts, W, Phi, _ = _ref_basis(tab, d)
+    b = np.zeros(mesh.ndofs)
+    for c in mesh.cells():
+        x, J = multilinear_map(mesh.corners(c), pts)
+        b[mesh.cell_dofs(c)] += Phi.T @ (W * np.linalg.det(J) * f(x))
+    if g is not None:
+        b += rhs_boundary(mesh, g)
+    return b
+
+
 def interpolate(mesh, u):
     """Nodal interpolant: u at the images of the reference Gauss-Lobatto nodes."""
     d, nodes = mesh.dim, gll_nodes(mesh.k)
@@ -347,3 +366,40 @@ class SurrogateCellSolvers:
 def surrogate_smooth(A, solvers, x, b, omega):
     """One additive step with the surrogate cell solvers (eq. schwarzproj)."""
     return x + omega * solvers.apply(b - A @ x)
+
+
+class MappedHierarchy:
+    """Alg. (gmg) on mapped meshes (Sec. 4): ``meshes`` coarsest first, each the
+    uniform refinement of the previous one on its cell maps (the fine cells are
+    the images of the children of the coarse reference cell), so the spaces
+    are nested.  The prolongation evaluates a coarse function at the fine
+    Gauss-Lobatto nodes; in reference coordinates that is the embedding of the
+    children, the same matrix as on a uniform Cartesian mesh of the same cell
+    counts (``multigrid.prolongation`` of two such meshes).  Smoother on
+    levels l >= 1: the additive cell smoother with the surrogate solvers
+    (``surrogate_smooth``, omegas[l]); on level 0 dense LU of A_0.  Restriction
+    is the transpose of the prolongation; the V-cycle is the one of
+    ``multigrid.Hierarchy``."""
+
+    def __init__(self, meshes, omegas, m_pre=1, m_post=1):
+        from .multigrid import prolongation
+        self.meshes, self.L = meshes, len(meshes) - 1
+        self.omegas, self.m_pre, self.m_post = list(omegas), m_pre, m_post
+        self.A = [assemble(m) for m in meshes]
+        shapes = [Mesh(m.dim, m.k, tuple(np.full(n, 1.0 / n) for n in m.ncells), 1.0) for m in meshes]
+        self.P = [None] + [prolongation(shapes[l - 1], shapes[l]) for l in range(1, self.L + 1)]
+        self.solvers = [None] + [SurrogateCellSolvers(m) for m in meshes[1:]]
+        self.coarse_lu = sla.lu_factor(self.A[0].toarray())
+
+    def vcycle(self, x, b, l=None):
+        l = self.L if l is None else l
+        if l == 0:
+            return sla.lu_solve(self.coarse_lu, b)
+        for _ in range(self.m_pre):
+            x = surrogate_smooth(self.A[l], self.solvers[l], x, b, self.omegas[l])
+        bc = self.P[l].T @ (b - self.A[l] @ x)
+        e = self.vcycle(np.zeros(self.meshes[l - 1].ndofs), bc, l - 1)
+        x = x + self.P[l] @ e
+        for _ in range(self.m_post):
+            x = surrogate_smooth(self.A[l], self.solvers[l], x, b, self.omegas[l])
+        return x

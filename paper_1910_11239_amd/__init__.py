@@ -88,6 +88,12 @@ _SIGS = {
     "fts_mapped_schwarz_apply": (_I32, [_VP, _D, _VP, _VP, _VP]),
     "fts_mapped_smooth_ws_bytes": (_SZ, [_VP]),
     "fts_mapped_schwarz_smooth": (_I32, [_VP, _D, _VP, _VP, _I32, _VP, _SZ, _VP]),
+    "fts_mapped_hierarchy_create": (_I32, [_VP, _I32, _VP, _I32, _I32, _VP]),
+    "fts_mapped_hierarchy_destroy": (_I32, [_VP]),
+    "fts_mapped_hierarchy_ndofs": (_I64, [_VP]),
+    "fts_mapped_vcycle": (_I32, [_VP, _VP, _VP, _VP]),
+    "fts_mapped_pcg_ws_bytes": (_SZ, [_VP]),
+    "fts_mapped_pcg": (_I32, [_VP, _VP, _VP, _D, _I32, _VP, _SZ, _VP, _VP, _VP, _VP]),
 }
 
 
@@ -445,6 +451,57 @@ class MappedLevel:
                                                _ptr(x, self.ndofs, "x"), int(nsweeps), _ptr(ws, None, "ws"),
                                                ws.numel() * 8, _stream()), "fts_mapped_schwarz_smooth")
         return x
+
+
+class MappedHierarchy:
+    """Multigrid on mapped meshes (fts_mapped_hierarchy_*): vertex arrays of
+    every level, coarsest first (each level the uniform refinement of the
+    previous one on its cell maps); additive cell smoother with Cartesian
+    surrogate solvers, omega per level (omegas[0] unused)."""
+
+    def __init__(self, dim, k, coarse_ncells, level_verts, gamma_hat, omegas, m_pre=1, m_post=1):
+        n = len(level_verts)
+        self._verts = [np.ascontiguousarray(np.asarray(v, dtype=np.float64)) for v in level_verts]
+        descs = (MappedDesc * n)()
+        for l in range(n):
+            d = descs[l]
+            d.dim, d.degree, d.penalty_factor = dim, k, float(gamma_hat)
+            for a in range(3):
+                d.ncells[a] = int(coarse_ncells[a]) * 2 ** l if a < dim else 1
+            d.vertices = self._verts[l].ctypes.data
+        om = np.ascontiguousarray(np.asarray(omegas, dtype=np.float64))
+        if om.size != n:
+            raise ValueError("one omega per level")
+        h = ctypes.c_void_p()
+        _check(lib().fts_mapped_hierarchy_create(descs, n, om.ctypes.data, int(m_pre), int(m_post),
+                                                 ctypes.byref(h)), "fts_mapped_hierarchy_create")
+        self._h = h
+        self.ndofs = int(lib().fts_mapped_hierarchy_ndofs(self._h))
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.fts_mapped_hierarchy_destroy(self._h)
+            self._h = None
+
+    def vcycle(self, b, x):
+        _check(lib().fts_mapped_vcycle(self._h, _ptr(b, self.ndofs, "b"), _ptr(x, self.ndofs, "x"), _stream()),
+               "fts_mapped_vcycle")
+        return x
+
+    def pcg(self, b, x, rtol=1e-8, maxit=200, ws=None):
+        """CG with one V-cycle as preconditioner; x: initial guess, updated.
+        Returns (iterations, final relative residual, history)."""
+        import torch
+        nbytes = int(lib().fts_mapped_pcg_ws_bytes(self._h))
+        if ws is None:
+            ws = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=x.device)
+        hist = np.zeros(maxit + 1)
+        it = ctypes.c_int32()
+        rel = ctypes.c_double()
+        _check(lib().fts_mapped_pcg(self._h, _ptr(b, self.ndofs, "b"), _ptr(x, self.ndofs, "x"), float(rtol),
+                                    int(maxit), _ptr(ws, None, "ws"), ws.numel() * 8, ctypes.byref(it),
+                                    ctypes.byref(rel), hist.ctypes.data, _stream()), "fts_mapped_pcg")
+        return it.value, rel.value, hist[:it.value + 1]
 
 
 class Batch:

@@ -390,6 +390,12 @@ void coarse_destroy(CoarseLU *c) {
 }
 
 fts_status coarse_create(const fts_level *l0, hipStream_t stream, CoarseLU **out) {
+    return coarse_create_with(l0, [&](const SlabBlocks &blk) { return launch_assemble_slabs(l0, blk, stream); },
+                              stream, out);
+}
+
+fts_status coarse_create_with(const fts_level *l0, const std::function<fts_status(const SlabBlocks &)> &fill,
+                              hipStream_t stream, CoarseLU **out) {
     *out = nullptr;
     const int d = l0->dim;
     int64_t nc = 1;
@@ -416,7 +422,7 @@ fts_status coarse_create(const fts_level *l0, hipStream_t stream, CoarseLU **out
     if (st == FTS_OK) st = launch_fill(c->D, nb * nblk, 0.0, stream);
     if (st == FTS_OK && nb > 1) st = launch_fill(c->Lo, (nb - 1) * nblk, 0.0, stream);
     if (st == FTS_OK && nb > 1) st = launch_fill(c->Up, (nb - 1) * nblk, 0.0, stream);
-    if (st == FTS_OK) st = launch_assemble_slabs(l0, SlabBlocks{c->D, c->Lo, c->Up, B}, stream);
+    if (st == FTS_OK) st = fill(SlabBlocks{c->D, c->Lo, c->Up, B});
     rocblas_handle h = nullptr;
     void *bws = nullptr;
     if (st == FTS_OK && rocblas_create_handle(&h) != rocblas_status_success)

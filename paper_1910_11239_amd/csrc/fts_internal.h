@@ -2,6 +2,8 @@
 // host setup helpers and the launchers of the HIP kernels.
 #pragma once
 
+#include <functional>
+
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -276,6 +278,11 @@ int operator_cells_per_block(int dim, int n1);
 // Direct solver of the coarsest level (coarse.hip).
 struct CoarseLU;
 fts_status coarse_create(const fts_level *l0, hipStream_t stream, CoarseLU **out);
+// The same factorisation of a matrix with the slab structure of l0 (cell
+// counts, degree, DoF numbering), whose blocks `fill` writes into the zeroed
+// slab storage (launch_assemble_slabs for the Cartesian A_0).
+fts_status coarse_create_with(const fts_level *l0, const std::function<fts_status(const SlabBlocks &)> &fill,
+                              hipStream_t stream, CoarseLU **out);
 void coarse_destroy(CoarseLU *c);
 // x = A_0^-1 b; x must not alias b.  Uses the solver's own workspaces, so
 // solves with one CoarseLU must not overlap.

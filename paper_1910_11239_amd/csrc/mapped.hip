@@ -823,3 +823,287 @@ fts_status fts_mapped_schwarz_smooth(const fts_mapped_level *lv, double omega, c
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Multigrid on mapped meshes (Sec. 4 with Alg. gmg): levels from uniform
+// refinement on the cell maps, so the spaces are nested and the grid transfers
+// are those of the Cartesian hierarchy in reference coordinates (embedding of
+// the children, k_transfer); the additive cell smoother with the Cartesian
+// surrogate local solvers on every level l >= 1; on level 0 the mapped
+// operator's own matrix, probed column by column, factored by the slab LU of
+// the Cartesian coarse solver.
+
+namespace fts {
+
+// e[(c, i)] = 1 for every cell c whose indices are congruent to col[] modulo
+// 3 along every axis (two such cells are at least three apart along some axis,
+// so no cell is a face neighbour, or itself, of two of them).
+__global__ void k_probe_set(int dim, int m0, int m1, int64_t ncells, int nc, int col0, int col1, int col2, int i,
+                            double *__restrict__ e) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncells; c += (int64_t)gridDim.x * blockDim.x) {
+        const int cx = (int)(c % m0), r0 = (int)(c / m0);
+        const int cy = dim == 3 ? r0 % m1 : r0, cz = dim == 3 ? r0 / m1 : 0;
+        if (cx % 3 == col0 && cy % 3 == col1 && (dim == 2 || cz % 3 == col2)) e[c * nc + i] = 1.0;
+    }
+}
+
+// Column (c, i) of the matrix for every probed cell c, from y = A e: row
+// (c', i') of y belongs to the probed cell among c' and its face neighbours
+// (at most one), and goes to the slab block of (slab of c', slab of c).
+__global__ void k_probe_scatter(int dim, int m0, int m1, int m2, int nc, int64_t ndofs, int col0, int col1, int col2,
+                                int i, const double *__restrict__ y, SlabBlocks blk) {
+    const int mm[3] = {m0, m1, dim == 3 ? m2 : 1};
+    const int col[3] = {col0, col1, col2};
+    for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < ndofs;
+         row += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t cr = row / nc;
+        const int ir = (int)(row - cr * nc);
+        int c[3];
+        c[0] = (int)(cr % m0);
+        const int64_t r0 = cr / m0;
+        c[1] = dim == 3 ? (int)(r0 % m1) : (int)r0;
+        c[2] = dim == 3 ? (int)(r0 / m1) : 0;
+        for (int o = 0; o <= 2 * dim; ++o) {  // o = 0: the cell itself, then -e_a, +e_a
+            int p[3] = {c[0], c[1], c[2]};
+            if (o > 0) p[(o - 1) / 2] += (o % 2) ? -1 : 1;
+            bool ok = true;
+            for (int a = 0; a < dim; ++a) ok = ok && p[a] >= 0 && p[a] < mm[a] && p[a] % 3 == col[a];
+            if (!ok) continue;
+            const int s_row = c[dim - 1], s_col = p[dim - 1];
+            const int64_t in_row = dim == 3 ? c[0] + (int64_t)m0 * c[1] : c[0];
+            const int64_t in_col = dim == 3 ? p[0] + (int64_t)m0 * p[1] : p[0];
+            const int64_t B = blk.B;
+            double *base = s_col == s_row ? blk.D + s_row * B * B
+                                          : (s_col == s_row - 1 ? blk.Lo + (s_row - 1) * B * B : blk.Up + s_row * B * B);
+            base[(in_row * nc + ir) + (in_col * nc + i) * B] = y[row];
+            break;
+        }
+    }
+}
+
+}  // namespace fts
+
+struct fts_mapped_hierarchy {
+    int nlevels = 0, m_pre = 1, m_post = 1;
+    std::vector<double> omega;
+    std::vector<fts_mapped_level *> levels;  // 0 = coarsest
+    std::vector<fts_level *> shapes;  // Cartesian levels of the same cell counts and degree (transfers, slab shape)
+    std::vector<double *> vb, vx, vr;
+    fts::CoarseLU *coarse = nullptr;
+    double *host_scalars = nullptr;
+};
+
+namespace fts {
+
+static fts_status mapped_vcycle_level(fts_mapped_hierarchy *h, int l, const double *b, double *x, hipStream_t s,
+                                      bool x_zero) {
+    if (l == 0) return coarse_solve(h->coarse, b, x, s);
+    const fts_mapped_level *lv = h->levels[l];
+    double *r = h->vr[l];
+    fts_status st = FTS_OK;
+    auto smooth = [&](bool first_zero) {
+        // r = b - A x (b itself when x = 0), x += omega sum_K Atilde_K^-1 r_K
+        fts_status e = first_zero ? FTS_OK : run_mapped(lv, 1, 0.0, x, b, r, s);
+        if (e == FTS_OK) e = run_mapped(lv, 2, h->omega[l], first_zero ? b : r, nullptr, x, s);
+        return e;
+    };
+    for (int i = 0; i < h->m_pre && st == FTS_OK; ++i) st = smooth(x_zero && i == 0);
+    if (st == FTS_OK) st = run_mapped(lv, 1, 0.0, x, b, r, s);
+    if (st == FTS_OK) st = launch_restrict(h->shapes[l - 1], h->shapes[l], r, h->vb[l - 1], s);
+    if (st == FTS_OK && l - 1 > 0) st = launch_fill(h->vx[l - 1], h->levels[l - 1]->ndofs, 0.0, s);
+    if (st == FTS_OK) st = mapped_vcycle_level(h, l - 1, h->vb[l - 1], h->vx[l - 1], s, true);
+    if (st == FTS_OK) st = launch_prolongate(h->shapes[l - 1], h->shapes[l], h->vx[l - 1], x, s);
+    for (int i = 0; i < h->m_post && st == FTS_OK; ++i) st = smooth(false);
+    return st;
+}
+
+static fts_status mapped_readback(fts_mapped_hierarchy *h, const double *dev, hipStream_t s, double *out2) {
+    FTS_HIP_CHECK(hipMemcpyAsync(h->host_scalars, dev, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    FTS_HIP_CHECK(hipStreamSynchronize(s));
+    out2[0] = h->host_scalars[0];
+    out2[1] = h->host_scalars[1];
+    return FTS_OK;
+}
+
+}  // namespace fts
+
+extern "C" {
+
+fts_status fts_mapped_hierarchy_destroy(fts_mapped_hierarchy *h) {
+    if (!h) return FTS_OK;
+    if (h->coarse) coarse_destroy(h->coarse);
+    for (auto *p : h->vb) dev_free(p);
+    for (auto *p : h->vx) dev_free(p);
+    for (auto *p : h->vr) dev_free(p);
+    for (auto *l : h->levels) fts_mapped_level_destroy(l);
+    for (auto *l : h->shapes) fts_level_destroy(l);
+    if (h->host_scalars) (void)hipHostFree(h->host_scalars);
+    delete h;
+    return FTS_OK;
+}
+
+fts_status fts_mapped_hierarchy_create(const fts_mapped_desc *levels, int32_t nlevels, const double *omega_per_level,
+                                       int32_t m_pre, int32_t m_post, fts_mapped_hierarchy **out) {
+    if (!levels || !omega_per_level || !out) return fail(FTS_E_INVAL, "fts_mapped_hierarchy_create: NULL argument");
+    *out = nullptr;
+    if (nlevels < 1 || nlevels > 16) return fail(FTS_E_INVAL, "nlevels must be in 1..16");
+    if (m_pre < 0 || m_post < 0) return fail(FTS_E_INVAL, "negative smoothing step count");
+    const int d = levels[0].dim;
+    for (int l = 0; l < nlevels; ++l) {
+        if (levels[l].dim != d || levels[l].degree != levels[0].degree)
+            return fail(FTS_E_INVAL, "all levels need the same dimension and degree");
+        for (int a = 0; a < d; ++a)
+            if (l > 0 && levels[l].ncells[a] != 2 * levels[l - 1].ncells[a])
+                return fail(FTS_E_INVAL, "each level must have twice the cells of the previous one per axis");
+    }
+    fts_mapped_hierarchy *h = new fts_mapped_hierarchy();
+    h->nlevels = nlevels;
+    h->m_pre = m_pre;
+    h->m_post = m_post;
+    h->omega.assign(omega_per_level, omega_per_level + nlevels);
+    fts_status st = FTS_OK;
+    for (int l = 0; l < nlevels && st == FTS_OK; ++l) {
+        fts_mapped_level *lv = nullptr;
+        st = fts_mapped_level_create(&levels[l], &lv);
+        if (st != FTS_OK) break;
+        h->levels.push_back(lv);
+        std::vector<double> w[3];
+        fts_mesh_desc cd{};
+        cd.dim = d;
+        cd.degree = levels[l].degree;
+        cd.penalty_factor = 1.0;
+        for (int a = 0; a < 3; ++a) {
+            cd.ncells[a] = a < d ? levels[l].ncells[a] : 1;
+            w[a].assign(cd.ncells[a], 1.0 / cd.ncells[a]);
+            cd.h[a] = w[a].data();
+        }
+        fts_level *shape = nullptr;
+        st = fts_level_create(&cd, &shape);
+        if (st != FTS_OK) break;
+        h->shapes.push_back(shape);
+        double *pb = nullptr, *px = nullptr, *pr = nullptr;
+        const size_t bytes = (size_t)lv->ndofs * sizeof(double);
+        if (l < nlevels - 1 && (dev_malloc(&pb, bytes) != hipSuccess || dev_malloc(&px, bytes) != hipSuccess))
+            st = fail(FTS_E_HIP, "device allocation of level vectors failed");
+        if (st == FTS_OK && dev_malloc(&pr, bytes) != hipSuccess)
+            st = fail(FTS_E_HIP, "device allocation of level vectors failed");
+        h->vb.push_back(pb);
+        h->vx.push_back(px);
+        h->vr.push_back(pr);
+    }
+    if (st == FTS_OK) {
+        // A_0 by probing: for each class of cells (indices modulo 3) and local
+        // DoF i, y = A e with e = 1 at DoF i of every cell of the class
+        const fts_mapped_level *l0 = h->levels[0];
+        const int64_t N = l0->ndofs, nc = N / l0->ncells;
+        double *e = nullptr, *y = nullptr;
+        if (dev_malloc(&e, N * sizeof(double)) != hipSuccess || dev_malloc(&y, N * sizeof(double)) != hipSuccess)
+            st = fail(FTS_E_HIP, "device allocation of the probing vectors failed");
+        auto fill = [&](const SlabBlocks &blk) -> fts_status {
+            const int ncls = d == 3 ? 27 : 9;
+            const unsigned gc = (unsigned)std::min<int64_t>((l0->ncells + 255) / 256, 4096);
+            const unsigned gr = (unsigned)std::min<int64_t>((N + 255) / 256, 4096);
+            for (int cls = 0; cls < ncls; ++cls) {
+                const int c0 = cls % 3, c1 = (cls / 3) % 3, c2 = cls / 9;
+                for (int i = 0; i < nc; ++i) {
+                    fts_status f = launch_fill(e, N, 0.0, nullptr);
+                    if (f != FTS_OK) return f;
+                    k_probe_set<<<gc, 256>>>(d, l0->m[0], l0->m[1], l0->ncells, (int)nc, c0, c1, c2, i, e);
+                    f = run_mapped(l0, 0, 0.0, e, nullptr, y, nullptr);
+                    if (f != FTS_OK) return f;
+                    k_probe_scatter<<<gr, 256>>>(d, l0->m[0], l0->m[1], l0->m[2], (int)nc, N, c0, c1, c2, i, y, blk);
+                    const hipError_t he = hipGetLastError();
+                    if (he != hipSuccess) return hip_fail(he, "coarse probing");
+                }
+            }
+            return FTS_OK;
+        };
+        if (st == FTS_OK) st = coarse_create_with(h->shapes[0], fill, nullptr, &h->coarse);
+        dev_free(e);
+        dev_free(y);
+        if (st == FTS_OK && hipHostMalloc(&h->host_scalars, 4 * sizeof(double)) != hipSuccess)
+            st = fail(FTS_E_HIP, "hipHostMalloc of the readback buffer failed");
+    }
+    if (st != FTS_OK) {
+        fts_mapped_hierarchy_destroy(h);
+        return st;
+    }
+    *out = h;
+    return FTS_OK;
+}
+
+int64_t fts_mapped_hierarchy_ndofs(const fts_mapped_hierarchy *h) { return h ? h->levels.back()->ndofs : -1; }
+
+fts_status fts_mapped_vcycle(fts_mapped_hierarchy *h, const double *b, double *x, void *stream) {
+    if (!h || !b || !x) return fail(FTS_E_INVAL, "fts_mapped_vcycle: NULL argument");
+    return mapped_vcycle_level(h, h->nlevels - 1, b, x, reinterpret_cast<hipStream_t>(stream), false);
+}
+
+size_t fts_mapped_pcg_ws_bytes(const fts_mapped_hierarchy *h) {
+    if (!h) return 0;
+    return (size_t)(5 * h->levels.back()->ndofs + 2 * red_partials() + 2) * sizeof(double);
+}
+
+fts_status fts_mapped_pcg(fts_mapped_hierarchy *h, const double *b, double *x, double rtol, int32_t maxit, void *ws,
+                          size_t ws_bytes, int32_t *iters, double *relres, double *history, void *stream) {
+    if (!h || !b || !x || !ws) return fail(FTS_E_INVAL, "fts_mapped_pcg: NULL argument");
+    if (ws_bytes < fts_mapped_pcg_ws_bytes(h)) return fail(FTS_E_SIZE, "fts_mapped_pcg: workspace too small");
+    if (!(rtol >= 0.0) || maxit < 0) return fail(FTS_E_INVAL, "fts_mapped_pcg: invalid rtol or maxit");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const fts_mapped_level *lv = h->levels.back();
+    const int64_t N = lv->ndofs;
+    double *r = static_cast<double *>(ws), *z = r + N, *zo = z + N, *p = zo + N, *q = p + N;
+    double *part = q + N, *dout = part + 2 * red_partials();
+    double v[2];
+    fts_status st;
+#define FTS_TRY(expr)                    \
+    do {                                 \
+        st = (expr);                     \
+        if (st != FTS_OK) return st;     \
+    } while (0)
+    FTS_TRY(run_mapped(lv, 1, 0.0, x, b, r, s));
+    FTS_TRY(launch_dot2(b, b, nullptr, N, part, dout, s));
+    FTS_TRY(mapped_readback(h, dout, s, v));
+    const double bb = v[0];
+    FTS_TRY(launch_dot2(r, r, nullptr, N, part, dout, s));
+    FTS_TRY(mapped_readback(h, dout, s, v));
+    double rel = bb > 0.0 ? std::sqrt(v[0] / bb) : 0.0;
+    if (history) history[0] = rel;
+    int it = 0;
+    if (rel > rtol && maxit > 0) {
+        FTS_TRY(launch_fill(z, N, 0.0, s));
+        FTS_TRY(mapped_vcycle_level(h, h->nlevels - 1, r, z, s, true));
+        FTS_HIP_CHECK(hipMemcpyAsync(p, z, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+        FTS_TRY(launch_dot2(r, z, nullptr, N, part, dout, s));
+        FTS_TRY(mapped_readback(h, dout, s, v));
+        double rz = v[0];
+        while (it < maxit) {
+            FTS_TRY(run_mapped(lv, 0, 0.0, p, nullptr, q, s));
+            FTS_TRY(launch_dot2(p, q, nullptr, N, part, dout, s));
+            FTS_TRY(mapped_readback(h, dout, s, v));
+            const double alpha = rz / v[0];
+            FTS_TRY(launch_cg_update(x, r, p, q, alpha, N, s));
+            FTS_TRY(launch_dot2(r, r, nullptr, N, part, dout, s));
+            FTS_TRY(mapped_readback(h, dout, s, v));
+            rel = std::sqrt(v[0] / bb);
+            ++it;
+            if (history) history[it] = rel;
+            if (!(rel > rtol)) break;
+            std::swap(z, zo);
+            FTS_TRY(launch_fill(z, N, 0.0, s));
+            FTS_TRY(mapped_vcycle_level(h, h->nlevels - 1, r, z, s, true));
+            FTS_TRY(launch_dot2(r, z, zo, N, part, dout, s));
+            FTS_TRY(mapped_readback(h, dout, s, v));
+            // flexible (Polak-Ribiere) update: beta = r.(z - z_old) / rz_old
+            const double beta = (v[0] - v[1]) / rz;
+            rz = v[0];
+            FTS_TRY(launch_xpby(p, z, beta, N, s));
+        }
+    }
+#undef FTS_TRY
+    if (iters) *iters = it;
+    if (relres) *relres = rel;
+    return FTS_OK;
+}
+
+}  // extern "C"

@@ -53,6 +53,46 @@ def test_linear_functions_are_reproduced_on_distorted_meshes(d, k, m, levels):
     assert np.linalg.norm(A @ uI - b) <= 1e-11 * np.linalg.norm(b)
 
 
+@pytest.mark.parametrize("d,k,m,levels", [(2, 2, 3, 1), (2, 3, 2, 1), (3, 2, 2, 1), (3, 3, 2, 0)])
+def test_quadratics_are_reproduced_with_their_load(d, k, m, levels):
+    """A quadratic u* composed with a multilinear map has degree <= 2 in every
+    reference coordinate, so it lies in the mapped Q_k space for k >= 2, and
+    every integrand of a(u*, v) and of the load (f v det J, grad u* . cof(J)
+    grad_xi v, the Nanson face terms) is a polynomial of degree <= 2k + 1
+    per axis, which k+1 Gauss points integrate exactly.  Consistency of SIPG
+    then gives A u*_I = rhs(-Laplace u*, u*) to rounding.  A dropped det J in
+    the load, a wrong sign of f or of a boundary term breaks it."""
+    mm = _distorted(d, k, m, levels, 11)
+    A = mapped.assemble(mm)
+    if d == 2:
+        u = lambda X: X[:, 0] ** 2 - 0.5 * X[:, 1] ** 2 + 0.3 * X[:, 0] * X[:, 1] + 0.7 * X[:, 0] - 0.2
+        lap = 1.0
+    else:
+        u = lambda X: X[:, 0] ** 2 + 0.5 * X[:, 1] ** 2 - 2.5 * X[:, 2] ** 2 + 0.3 * X[:, 1] * X[:, 2] + 0.1
+        lap = -2.0
+    f = lambda X: np.full(len(X), -lap)
+    b = mapped.rhs(mm, f, u)
+    uI = mapped.interpolate(mm, u)
+    res = np.linalg.norm(A @ uI - b)
+    assert res <= 1e-11 * np.linalg.norm(b)
+    # the load is small next to the boundary penalty terms, but not zero:
+    # dropping it leaves a residual far above rounding
+    assert np.linalg.norm(A @ uI - mapped.rhs_boundary(mm, u)) > 1e6 * max(res, 1e-300)
+
+
+@pytest.mark.parametrize("d,k,ms", [(2, 2, (3, 4)), (3, 1, (2, 3, 2))])
+def test_rectilinear_rhs_is_the_cartesian_rhs(d, k, ms):
+    """On a rectilinear grid the mapped load and boundary terms equal the
+    Cartesian ones of ``sipg.rhs`` (polynomial data, so both quadrature rules
+    are exact and agree)."""
+    cart, mm = _rect(d, k, ms, 13)
+    f = lambda X: 1.0 + X[:, 0] - 0.5 * X[:, -1] ** 2
+    g = lambda X: 0.3 - X[:, 0] * X[:, -1]
+    b0 = sipg.rhs(cart, f, g)
+    b1 = mapped.rhs(mm, f, g)
+    assert np.linalg.norm(b1 - b0) <= 1e-12 * np.linalg.norm(b0)
+
+
 def test_undistorted_surrogate_is_the_exact_local_solver():
     """On a rectilinear mesh the surrogate box is the cell itself: the
     surrogate local matrix equals R_K A R_K^T for every cell."""
@@ -103,3 +143,36 @@ def test_surrogate_smoother_step_and_local_stability():
         eta = max(eta, np.max(np.real(np.linalg.eigvals(np.linalg.solve(At, Ad[np.ix_(dofs, dofs)])))))
     assert np.abs(out - ref).max() <= 1e-12 * np.abs(ref).max()
     assert 1.0 < eta < 3.0
+
+
+def test_mapped_prolongation_is_nested():
+    """The refined distorted mesh is the uniform refinement of the coarse one on
+    its cell maps, and the prolongation is the embedding: the interpolant of a
+    linear function (which lies in both mapped spaces) on the coarse mesh is
+    carried to its interpolant on the fine mesh."""
+    for d, k, m in ((2, 2, 3), (2, 3, 2), (3, 2, 2)):
+        meshes = [_distorted(d, k, m, lev, 13) for lev in (0, 1)]
+        hier = mapped.MappedHierarchy(meshes, [0.0, 0.5])
+        coef = np.array([0.3, -1.1, 0.8][:d])
+        u = lambda X: X @ coef - 0.4
+        uc, uf = mapped.interpolate(meshes[0], u), mapped.interpolate(meshes[1], u)
+        assert np.abs(hier.P[1] @ uc - uf).max() <= 1e-13 * np.abs(uf).max()
+
+
+def test_mapped_hierarchy_on_rectilinear_grids_is_the_cartesian_vcycle():
+    """On rectilinear vertex grids the surrogate solvers are the exact cell
+    solvers and the mapped matrices the Cartesian ones, so the mapped V-cycle
+    is the Cartesian V-cycle with the additive cell smoother (the oracle's
+    multigrid.Hierarchy, pinned in test_oracle_mg.py)."""
+    from oracle import multigrid
+    from synthetic import random_vector
+    for d, k, m in ((2, 2, 2), (3, 1, 2)):
+        fine = Mesh(d, k, tuple(np.full(2 * m, 0.5 / m) for _ in range(d)), 4.0)
+        cart = multigrid.Hierarchy(fine, 2, "cell", [0.0, 0.45], m_pre=2, m_post=1)
+        meshes = [mapped.MappedMesh(d, k, (n,) * d, grid_vertices([np.full(n, 1.0 / n)] * d), 4.0)
+                  for n in (m, 2 * m)]
+        hier = mapped.MappedHierarchy(meshes, [0.0, 0.45], m_pre=2, m_post=1)
+        b, x = random_vector(fine.ndofs, 0), random_vector(fine.ndofs, 1)
+        ref = cart.vcycle(x.copy(), b)
+        got = hier.vcycle(x.copy(), b)
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
