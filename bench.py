@@ -258,7 +258,8 @@ def distorted_workload():
     by 25 % of the local edge length in random directions, refined twice to
     32^3 cells), Q3, gamma_hat = 4: one sweep of the additive cell smoother
     with Cartesian surrogate local solvers = matrix-free mapped SIPG residual
-    + per-cell fast-diagonalisation solves."""
+    + per-cell fast-diagonalisation solves; then the V-cycle and CG of the
+    multigrid on the three nested distorted levels (Sec. 4 with Alg. gmg)."""
     import torch
     import paper_1910_11239_amd as fts
     from synthetic import distorted_vertices
@@ -273,12 +274,35 @@ def distorted_workload():
     t_apply = _events_time(lambda: lv.schwarz_apply(0.5, r, x), 5)
     t_sweep = _events_time(lambda: lv.schwarz_smooth(0.5, b, x, 1, ws), 5)
     del lv
+    # multigrid on the three nested distorted levels 8^3, 16^3, 32^3 (the
+    # paper's 3-D damping for Q3, omega 0.55), CG to 1e-8 from x = 0
+    levels = [distorted_vertices(3, 8, lev, 0.25, 0)[1] for lev in range(2)] + [V]
+    mg = {}
+    for steps in (1, 2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = fts.MappedHierarchy(3, 3, (8, 8, 8), levels, 4.0, [0.0, 0.55, 0.55], steps, steps)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        t_vc = _events_time(lambda: h.vcycle(b, x), 5)
+        xs = torch.zeros_like(b)
+        h.pcg(b, xs, rtol=1e-8, maxit=300)  # warm-up solve
+        xs.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it, rel, _ = h.pcg(b, xs, rtol=1e-8, maxit=300)
+        torch.cuda.synchronize()
+        mg[f"ACS_{steps}"] = {"setup_s": setup_s, "vcycle_ms": t_vc, "cg_iterations": it, "cg_relres": rel,
+                              "cg_seconds": time.perf_counter() - t0}
+        del h
     torch.cuda.empty_cache()
     return {"workload": "distorted cube: 8^3 cells, interior vertices moved by 0.25 h_v, refined twice to 32^3 "
                         "mapped cells, Q3 (2,097,152 DoFs), gamma_hat 4, omega 0.5",
             "dofs": N, "residual_ms": t_res, "surrogate_apply_ms": t_apply, "sweep_ms": t_sweep,
             "sweep_dofs_per_s": N / (t_sweep * 1e-3),
-            "residual_gbs": wm.residual_bytes(3, 3, ms) / (t_res * 1e-3) / 1e9}
+            "residual_gbs": wm.residual_bytes(3, 3, ms) / (t_res * 1e-3) / 1e9,
+            "multigrid": {"levels": "8^3, 16^3, 32^3 mapped cells, omega 0.55, ACS_m = m pre- and post-smoothing "
+                                    "steps, CG to 1e-8, uniform random right-hand side", **mg}}
 
 
 def multiplicative_workload():
