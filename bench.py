@@ -7,7 +7,8 @@ finer levels 2 pre- and 2 post-smoothing sweeps of the additive vertex-patch
 Schwarz smoother (omega = 0.5, fast-diagonalisation local solves, matrix-free
 residual), restriction and prolongation, and the LU solve of the 64,000-DoF
 coarse problem (8^3 cells; factors stored by slabs of cells, the exact zeros
-of the dense factors left out).  Setup (1-D eigenproblems, coarse LU) is
+of the dense factors left out and the blocks between slabs kept in the
+low-rank form their face coupling gives them).  Setup (1-D eigenproblems, coarse LU) is
 outside the timed region; b is resident in HBM.
 
 value = fine-level DoFs processed per second = N / (time per V-cycle).
@@ -467,12 +468,12 @@ def main():
     patch_flops = wm.smoother_flops(dim, k, ncells, "vertex")
     res_bytes = wm.residual_bytes(dim, k, ncells)
     # coarse factors: nb slabs of B unknowns; the diagonal blocks are read in
-    # full (lower half forward, upper half backward), the nb - 1 blocks below
-    # and above the diagonal in their nonzero halves
+    # full (lower half forward, upper half backward), the low-rank factors of
+    # the blocks between slabs in their nonzero parts
     m0 = m // 2 ** (nl - 1)
     B0 = (k + 1) ** dim * m0 ** (dim - 1)
     nb0 = m0
-    coarse_bytes = 8.0 * B0 * B0 * (2 * nb0 - 1)
+    coarse_bytes = float(wm.coarse_solve_bytes(dim, k, (m0,) * dim))
     sweeps_fine = cfg["m_pre"] + cfg["m_post"]
     kernels = {
         "vertex_patch_apply_fp64": {
@@ -487,11 +488,13 @@ def main():
             "ms_per_call": t_res, "calls_per_step": sweeps_fine + 1,
             "algorithmic": f"{res_bytes:.4g} bytes per call (read x, b, write r)"},
         "coarse_lu_solve": {
-            "kernel": f"k_slab_mv ({2 * (2 * nb0 - 1)} launches)", "bound": "hbm",
+            "kernel": f"k_slab_mv ({2 * (2 * nb0 - 1)} launches) + k_lr_expand / k_lr_reduce "
+                      f"({2 * (nb0 - 1)} launches)", "bound": "hbm",
             "achieved": coarse_bytes / (t_coarse * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "ms_per_call": t_coarse, "calls_per_step": 1,
             "algorithmic": f"{coarse_bytes:.4g} bytes per call (slab-blocked LU factors of the {n0}-DoF "
-                           f"coarse matrix, {nb0} slabs of {B0}: 8 B^2 (2 nb - 1))"},
+                           f"coarse matrix, {nb0} slabs of {B0}: diagonal blocks 8 nb B^2, blocks between slabs "
+                           "in low-rank form)"},
     }
     for v in kernels.values():
         v["frac"] = v["achieved"] / v["peak"]

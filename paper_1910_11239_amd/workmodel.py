@@ -47,3 +47,23 @@ def patch_apply_bytes(dim, k, ncells, word=8):
 
 def smoother_sweep_bytes(dim, k, ncells, word=8):
     return 5 * word * ndofs(dim, k, ncells)
+
+
+def coarse_solve_bytes(dim, k, ncells, word=8):
+    """Factor bytes read by one slab-blocked coarse solve on a mesh of
+    ``ncells`` cells (slabs along the last axis): every diagonal block in
+    full (B^2 for its lower and upper halves), and for each pair of
+    neighbouring slabs the nonzero parts of W_i (row of cell c from column
+    c nc on) and V_i (row of cell c up to column (c + 1) rc) plus the per-cell
+    factors P_i and R_i, with nc = (k+1)^d unknowns and rc = 2 (k+1)^(d-1)
+    face numbers per cell."""
+    n1 = k + 1
+    nc, rc = n1 ** dim, 2 * n1 ** (dim - 1)
+    nb = ncells[-1]
+    ncs = 1
+    for m in ncells[:-1]:
+        ncs *= int(m)
+    B = ncs * nc
+    w = rc * (ncs * B - nc * ncs * (ncs - 1) // 2)
+    v = nc * rc * ncs * (ncs + 1) // 2
+    return word * (nb * B * B + (nb - 1) * (w + v + 2 * ncs * rc * nc))

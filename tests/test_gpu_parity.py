@@ -273,9 +273,14 @@ def test_vcycle(kind, d, k, ms, nl):
     assert rel(host(x0), ref0) < TOL
 
 
-@pytest.mark.parametrize("d,k,ms", [(3, 2, (2, 2, 2)), (3, 4, (4, 3, 2)), (2, 3, (9, 10))])
+@pytest.mark.parametrize("d,k,ms", [(3, 2, (2, 2, 2)), (3, 4, (4, 3, 2)), (2, 3, (9, 10)), (3, 2, (3, 3, 3)),
+                                    (3, 1, (3, 2, 4)), (2, 2, (5, 4))])
 def test_coarse_lu_solve(d, k, ms):
-    """Dense LU of the coarse matrix (several 256-blocks and a ragged last block)."""
+    """Dense LU of the coarse matrix (several 256-blocks and a ragged last
+    block), against scipy's pivoted LU of the assembled matrix.  The cases
+    cover even and odd slab sizes (paired and single-column loads of the
+    substitution mat-vecs), k = 1 (as many face numbers as unknowns per cell)
+    and several slabs in 2-D and 3-D."""
     announce("coarse", d, k, ms)
     m = omesh(d, k, ms, 17)
     gh = fts.Hierarchy(d, k, m.widths, 1, "vertex", [0.0], m.gamma_hat)

@@ -31,3 +31,21 @@ def test_counts():
     assert wm.n_subdomains((16, 16, 16), "vertex") == 3375
     assert wm.ndofs(3, 4, (32, 32, 32)) == 4096000
     assert wm.ndofs(3, 7, (48, 48, 48)) == 56623104
+
+
+def test_coarse_solve_bytes_count_the_rows_the_kernels_read():
+    """Brute force over rows: the diagonal blocks' strict lower and upper
+    halves, W_i rows (cell c, face number a) over [c nc, B), V_i rows of cell
+    c over [0, (c + 1) rc), and P_i, R_i in full."""
+    for dim, k, ncells in ((3, 4, (8, 8, 8)), (2, 3, (5, 3)), (3, 1, (2, 3, 4))):
+        n1 = k + 1
+        nc, rc = n1 ** dim, 2 * n1 ** (dim - 1)
+        nb, ncs = ncells[-1], int(np.prod(ncells[:-1]))
+        B = ncs * nc
+        diag = sum(r for r in range(B)) + sum(B - r for r in range(B))
+        w = sum(B - (row // rc) * nc for row in range(ncs * rc))
+        v = sum((r // nc + 1) * rc for r in range(B))
+        count = nb * diag + (nb - 1) * (w + v + 2 * ncs * rc * nc)
+        assert wm.coarse_solve_bytes(dim, k, ncells) == 8 * count
+    # the 8^3 Q4 coarse level: 5.60 GB against 7.68 GB for the full triangular off-diagonal blocks
+    assert abs(wm.coarse_solve_bytes(3, 4, (8, 8, 8)) / 1e9 - 5.597) < 0.001
