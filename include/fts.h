@@ -457,6 +457,14 @@ fts_status fts_mapped_hierarchy_create(const fts_mapped_desc *levels, int32_t nl
                                        fts_mapped_hierarchy **out);
 fts_status fts_mapped_hierarchy_destroy(fts_mapped_hierarchy *hier);
 int64_t fts_mapped_hierarchy_ndofs(const fts_mapped_hierarchy *hier);
+/* Smoother on levels >= 1: FTS_SMOOTHER_ADDITIVE (default) or
+ * FTS_SMOOTHER_MULTIPLICATIVE, Alg. multsmoother with the surrogate cell
+ * solvers and red-black cells (parity of the cell index sum), the residual
+ * recomputed before each color; pre-smoothing runs red then black,
+ * post-smoothing black then red, so the V-cycle stays symmetric and can
+ * precondition fts_mapped_pcg (Sec. 4, Tab. cubedist25mcp).  FTS_E_INVAL for
+ * any other value. */
+fts_status fts_mapped_hierarchy_set_smoother(fts_mapped_hierarchy *hier, int32_t smoother);
 /* x <- MG_L(x, b) on the finest level. */
 fts_status fts_mapped_vcycle(fts_mapped_hierarchy *hier, const double *b, double *x, void *stream);
 /* FP64 CG preconditioned by one V-cycle (x = 0 initial guess of the V-cycle),

@@ -30,7 +30,9 @@ Cartesian cell block of a rectilinear patch of 3 (or 2 at the boundary) boxes
 per axis, taken from ``sipg.assemble``.
 
 Smoother (Sec. 4, eq. schwarzproj with the additive cell smoother):
-x <- x + omega sum_K R_K^T Atilde_K^-1 R_K (b - A x) with the mapped A.
+x <- x + omega sum_K R_K^T Atilde_K^-1 R_K (b - A x) with the mapped A; the
+multiplicative variant (Alg. multsmoother) takes the red-black colors of the
+cells one after the other with the residual recomputed before each.
 
 Pins (tests/test_oracle_mapped.py): on rectilinear vertex grids the mapped
 matrix equals ``sipg.assemble`` and the surrogate solver equals the exact local
@@ -40,7 +42,9 @@ which fixes volume, face normal, area element and consistency terms) and,
 with the volume load, quadratics with their Laplacian (k >= 2, where every
 integrand is a polynomial the rule integrates exactly); the right-hand side
 equals ``sipg.rhs`` on rectilinear grids; the surrogate widths of affine cells
-are their edge lengths.
+are their edge lengths; the multiplicative surrogate step equals the
+sequential formula with explicit inverses, and the multiplicative V-cycle is
+symmetric with reversed post-smoothing (and not without it).
 """
 import itertools
 
@@ -355,9 +359,13 @@ class SurrogateCellSolvers:
         self.mesh = mesh
         self.lu = {c: sla.lu_factor(surrogate_local_matrix(mesh, c, hbar)) for c in mesh.cells()}
 
-    def apply(self, r):
+    def apply(self, r, color=None):
+        """sum_K R_K^T Atilde_K^-1 R_K r over all cells, or over the cells of
+        one red-black color (sum of the cell indices modulo 2)."""
         out = np.zeros_like(r)
         for c, f in self.lu.items():
+            if color is not None and sum(c) % 2 != color:
+                continue
             dofs = self.mesh.cell_dofs(c)
             out[dofs] = sla.lu_solve(f, r[dofs])
         return out
@@ -366,6 +374,17 @@ class SurrogateCellSolvers:
 def surrogate_smooth(A, solvers, x, b, omega):
     """One additive step with the surrogate cell solvers (eq. schwarzproj)."""
     return x + omega * solvers.apply(b - A @ x)
+
+
+def surrogate_mult_smooth(A, solvers, x, b, omega, reverse=False):
+    """One multiplicative step (Alg. multsmoother, eq. coloredschwarz) with the
+    surrogate cell solvers and the red-black coloring of the cells: the
+    residual is recomputed before each color.  reverse runs black before red,
+    which is how Sec. 4 symmetrises the V-cycle (post-smoothing in the reverse
+    order of pre-smoothing)."""
+    for color in ((1, 0) if reverse else (0, 1)):
+        x = x + omega * solvers.apply(b - A @ x, color)
+    return x
 
 
 class MappedHierarchy:
@@ -379,12 +398,16 @@ class MappedHierarchy:
     levels l >= 1: the additive cell smoother with the surrogate solvers
     (``surrogate_smooth``, omegas[l]); on level 0 dense LU of A_0.  Restriction
     is the transpose of the prolongation; the V-cycle is the one of
-    ``multigrid.Hierarchy``."""
+    ``multigrid.Hierarchy``.  smoother="multiplicative" replaces the additive
+    step by ``surrogate_mult_smooth``, red before black in pre-smoothing and
+    black before red in post-smoothing (Sec. 4: the reversed order makes the
+    V-cycle symmetric, so that it can precondition CG)."""
 
-    def __init__(self, meshes, omegas, m_pre=1, m_post=1):
+    def __init__(self, meshes, omegas, m_pre=1, m_post=1, smoother="additive"):
         from .multigrid import prolongation
         self.meshes, self.L = meshes, len(meshes) - 1
         self.omegas, self.m_pre, self.m_post = list(omegas), m_pre, m_post
+        self.smoother = smoother
         self.A = [assemble(m) for m in meshes]
         shapes = [Mesh(m.dim, m.k, tuple(np.full(n, 1.0 / n) for n in m.ncells), 1.0) for m in meshes]
         self.P = [None] + [prolongation(shapes[l - 1], shapes[l]) for l in range(1, self.L + 1)]
@@ -396,10 +419,15 @@ class MappedHierarchy:
         if l == 0:
             return sla.lu_solve(self.coarse_lu, b)
         for _ in range(self.m_pre):
-            x = surrogate_smooth(self.A[l], self.solvers[l], x, b, self.omegas[l])
+            x = self.smooth(l, x, b, False)
         bc = self.P[l].T @ (b - self.A[l] @ x)
         e = self.vcycle(np.zeros(self.meshes[l - 1].ndofs), bc, l - 1)
         x = x + self.P[l] @ e
         for _ in range(self.m_post):
-            x = surrogate_smooth(self.A[l], self.solvers[l], x, b, self.omegas[l])
+            x = self.smooth(l, x, b, True)
         return x
+
+    def smooth(self, l, x, b, post):
+        if self.smoother == "multiplicative":
+            return surrogate_mult_smooth(self.A[l], self.solvers[l], x, b, self.omegas[l], reverse=post)
+        return surrogate_smooth(self.A[l], self.solvers[l], x, b, self.omegas[l])

@@ -91,6 +91,7 @@ _SIGS = {
     "fts_mapped_hierarchy_create": (_I32, [_VP, _I32, _VP, _I32, _I32, _VP]),
     "fts_mapped_hierarchy_destroy": (_I32, [_VP]),
     "fts_mapped_hierarchy_ndofs": (_I64, [_VP]),
+    "fts_mapped_hierarchy_set_smoother": (_I32, [_VP, _I32]),
     "fts_mapped_vcycle": (_I32, [_VP, _VP, _VP, _VP]),
     "fts_mapped_pcg_ws_bytes": (_SZ, [_VP]),
     "fts_mapped_pcg": (_I32, [_VP, _VP, _VP, _D, _I32, _VP, _SZ, _VP, _VP, _VP, _VP]),
@@ -482,6 +483,11 @@ class MappedHierarchy:
         if getattr(self, "_h", None) is not None and _lib is not None:
             _lib.fts_mapped_hierarchy_destroy(self._h)
             self._h = None
+
+    def set_smoother(self, smoother):
+        """'additive' or 'multiplicative' (red-black cells, reversed in post-smoothing)."""
+        code = {"additive": 0, "multiplicative": 1}[smoother]
+        _check(lib().fts_mapped_hierarchy_set_smoother(self._h, code), "fts_mapped_hierarchy_set_smoother")
 
     def vcycle(self, b, x):
         _check(lib().fts_mapped_vcycle(self._h, _ptr(b, self.ndofs, "b"), _ptr(x, self.ndofs, "x"), _stream()),

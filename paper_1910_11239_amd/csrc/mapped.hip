@@ -441,13 +441,20 @@ k_mapped_operator(MappedView g, const double *__restrict__ x, const double *__re
 
 // x += omega sum_K R_K^T Atilde_K^-1 R_K r with the surrogate tables of each
 // cell: (S_d x .. x S_1) diag(1 / sum_t lambda_t) (S_d x .. x S_1)^T.
+// color >= 0: only the cells whose index sum has that parity (the red-black
+// coloring of the multiplicative smoother); the others leave at once.
 template <int D, int N1>
 __global__ void __launch_bounds__(kMapThreads)
-k_mapped_surrogate(MappedView g, double omega, const double *__restrict__ r, double *__restrict__ x) {
+k_mapped_surrogate(MappedView g, double omega, int color, const double *__restrict__ r, double *__restrict__ x) {
     constexpr int NC = D == 2 ? N1 * N1 : N1 * N1 * N1;
     __shared__ double A[NC], B[NC];
     __shared__ double S[D][N1 * N1], L[D][N1];
     const int64_t cell = blockIdx.x;
+    if (color >= 0) {  // uniform over the workgroup: it leaves before any barrier
+        const int64_t c1 = cell / g.m[0];
+        const int64_t par = cell % g.m[0] + (D == 3 ? c1 % g.m[1] + c1 / g.m[1] : c1);
+        if ((int)(par & 1) != color) return;
+    }
     const int t = threadIdx.x;
     for (int e2 = t; e2 < D * N1 * N1; e2 += blockDim.x) S[e2 / (N1 * N1)][e2 % (N1 * N1)] = g.S[cell * D * N1 * N1 + e2];
     for (int e2 = t; e2 < D * N1; e2 += blockDim.x) L[e2 / N1][e2 % N1] = g.lam[cell * D * N1 + e2];
@@ -494,9 +501,10 @@ static fts_status launch_mapped_op(const fts_mapped_level *lv, const double *x, 
 }
 
 template <int D, int N1>
-static fts_status launch_mapped_sur(const fts_mapped_level *lv, double omega, const double *r, double *x,
+static fts_status launch_mapped_sur(const fts_mapped_level *lv, double omega, int color, const double *r, double *x,
                                     hipStream_t st) {
-    k_mapped_surrogate<D, N1><<<dim3((unsigned)lv->ncells), dim3(kMapThreads), 0, st>>>(lv->view, omega, r, x);
+    k_mapped_surrogate<D, N1><<<dim3((unsigned)lv->ncells), dim3(kMapThreads), 0, st>>>(lv->view, omega, color, r,
+                                                                                          x);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? FTS_OK : hip_fail(e, "k_mapped_surrogate launch");
 }
@@ -504,22 +512,24 @@ static fts_status launch_mapped_sur(const fts_mapped_level *lv, double omega, co
 constexpr int kMapMaxN1 = 8;  // k <= 7
 
 template <int D, int N1 = 2>
-static fts_status dispatch_mapped(const fts_mapped_level *lv, int what, double omega, const double *x,
+static fts_status dispatch_mapped(const fts_mapped_level *lv, int what, double omega, int color, const double *x,
                                   const double *b, double *y, hipStream_t st) {
     if constexpr (N1 > kMapMaxN1) {
         return fail(FTS_E_UNSUPPORTED, "mapped meshes: degree above 7");
     } else {
-        if (lv->n1 != N1) return dispatch_mapped<D, N1 + 1>(lv, what, omega, x, b, y, st);
-        if (what == 2) return launch_mapped_sur<D, N1>(lv, omega, x, y, st);
+        if (lv->n1 != N1) return dispatch_mapped<D, N1 + 1>(lv, what, omega, color, x, b, y, st);
+        if (what == 2) return launch_mapped_sur<D, N1>(lv, omega, color, x, y, st);
         return launch_mapped_op<D, N1>(lv, x, b, y, what == 1, st);
     }
 }
 
+// what: 0 y = A x, 1 y = b - A x, 2 y += omega (surrogate solves) x over all
+// cells (color < 0) or over one red-black color.
 static fts_status run_mapped(const fts_mapped_level *lv, int what, double omega, const double *x, const double *b,
-                             double *y, hipStream_t st) {
+                             double *y, hipStream_t st, int color = -1) {
     if (lv->ncells == 0) return FTS_OK;
-    return lv->dim == 2 ? dispatch_mapped<2>(lv, what, omega, x, b, y, st)
-                        : dispatch_mapped<3>(lv, what, omega, x, b, y, st);
+    return lv->dim == 2 ? dispatch_mapped<2>(lv, what, omega, color, x, b, y, st)
+                        : dispatch_mapped<3>(lv, what, omega, color, x, b, y, st);
 }
 
 // ---- host geometry (FP64): multilinear map, cell volumes, face areas
@@ -885,6 +895,7 @@ __global__ void k_probe_scatter(int dim, int m0, int m1, int m2, int nc, int64_t
 
 struct fts_mapped_hierarchy {
     int nlevels = 0, m_pre = 1, m_post = 1;
+    int smoother = FTS_SMOOTHER_ADDITIVE;
     std::vector<double> omega;
     std::vector<fts_mapped_level *> levels;  // 0 = coarsest
     std::vector<fts_level *> shapes;  // Cartesian levels of the same cell counts and degree (transfers, slab shape)
@@ -901,19 +912,31 @@ static fts_status mapped_vcycle_level(fts_mapped_hierarchy *h, int l, const doub
     const fts_mapped_level *lv = h->levels[l];
     double *r = h->vr[l];
     fts_status st = FTS_OK;
-    auto smooth = [&](bool first_zero) {
-        // r = b - A x (b itself when x = 0), x += omega sum_K Atilde_K^-1 r_K
-        fts_status e = first_zero ? FTS_OK : run_mapped(lv, 1, 0.0, x, b, r, s);
-        if (e == FTS_OK) e = run_mapped(lv, 2, h->omega[l], first_zero ? b : r, nullptr, x, s);
+    auto smooth = [&](bool first_zero, bool post) {
+        // additive: r = b - A x (b itself when x = 0), x += omega sum_K
+        // Atilde_K^-1 r_K; multiplicative: the same per red-black color with
+        // the residual recomputed before each, black first after the coarse
+        // correction (the reversed order keeps the V-cycle symmetric)
+        if (h->smoother != FTS_SMOOTHER_MULTIPLICATIVE) {
+            fts_status e = first_zero ? FTS_OK : run_mapped(lv, 1, 0.0, x, b, r, s);
+            if (e == FTS_OK) e = run_mapped(lv, 2, h->omega[l], first_zero ? b : r, nullptr, x, s);
+            return e;
+        }
+        fts_status e = FTS_OK;
+        for (int ci = 0; ci < 2 && e == FTS_OK; ++ci) {
+            const bool zero = first_zero && ci == 0;
+            if (!zero) e = run_mapped(lv, 1, 0.0, x, b, r, s);
+            if (e == FTS_OK) e = run_mapped(lv, 2, h->omega[l], zero ? b : r, nullptr, x, s, post ? 1 - ci : ci);
+        }
         return e;
     };
-    for (int i = 0; i < h->m_pre && st == FTS_OK; ++i) st = smooth(x_zero && i == 0);
+    for (int i = 0; i < h->m_pre && st == FTS_OK; ++i) st = smooth(x_zero && i == 0, false);
     if (st == FTS_OK) st = run_mapped(lv, 1, 0.0, x, b, r, s);
     if (st == FTS_OK) st = launch_restrict(h->shapes[l - 1], h->shapes[l], r, h->vb[l - 1], s);
     if (st == FTS_OK && l - 1 > 0) st = launch_fill(h->vx[l - 1], h->levels[l - 1]->ndofs, 0.0, s);
     if (st == FTS_OK) st = mapped_vcycle_level(h, l - 1, h->vb[l - 1], h->vx[l - 1], s, true);
     if (st == FTS_OK) st = launch_prolongate(h->shapes[l - 1], h->shapes[l], h->vx[l - 1], x, s);
-    for (int i = 0; i < h->m_post && st == FTS_OK; ++i) st = smooth(false);
+    for (int i = 0; i < h->m_post && st == FTS_OK; ++i) st = smooth(false, true);
     return st;
 }
 
@@ -1033,6 +1056,14 @@ fts_status fts_mapped_hierarchy_create(const fts_mapped_desc *levels, int32_t nl
 }
 
 int64_t fts_mapped_hierarchy_ndofs(const fts_mapped_hierarchy *h) { return h ? h->levels.back()->ndofs : -1; }
+
+fts_status fts_mapped_hierarchy_set_smoother(fts_mapped_hierarchy *h, int32_t smoother) {
+    if (!h) return fail(FTS_E_INVAL, "fts_mapped_hierarchy_set_smoother: NULL hierarchy");
+    if (smoother != FTS_SMOOTHER_ADDITIVE && smoother != FTS_SMOOTHER_MULTIPLICATIVE)
+        return fail(FTS_E_INVAL, "fts_mapped_hierarchy_set_smoother: unknown smoother");
+    h->smoother = smoother;
+    return FTS_OK;
+}
 
 fts_status fts_mapped_vcycle(fts_mapped_hierarchy *h, const double *b, double *x, void *stream) {
     if (!h || !b || !x) return fail(FTS_E_INVAL, "fts_mapped_vcycle: NULL argument");

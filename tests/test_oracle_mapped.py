@@ -176,3 +176,46 @@ def test_mapped_hierarchy_on_rectilinear_grids_is_the_cartesian_vcycle():
         ref = cart.vcycle(x.copy(), b)
         got = hier.vcycle(x.copy(), b)
         assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_multiplicative_surrogate_step_against_explicit_inverses():
+    """Alg. multsmoother with red-black cells: x1 = x + omega sum_red
+    Atilde_K^-1 R_K (b - A x), x2 = x1 + omega sum_black Atilde_K^-1 R_K
+    (b - A x1), built from explicit inverses of the surrogate local matrices;
+    reversed, black goes first."""
+    mm = _distorted(2, 2, 3, 1, 17)
+    A = mapped.assemble(mm)
+    sol = mapped.SurrogateCellSolvers(mm)
+    hbar = mapped.surrogate_widths(mm)
+    b, x = random_vector(mm.ndofs, 2), random_vector(mm.ndofs, 3)
+    inv = {c: np.linalg.inv(mapped.surrogate_local_matrix(mm, c, hbar)) for c in mm.cells()}
+    for reverse in (False, True):
+        ref = x.copy()
+        for color in ((1, 0) if reverse else (0, 1)):
+            r = b - A @ ref
+            dx = np.zeros_like(ref)
+            for c in mm.cells():
+                if sum(c) % 2 == color:
+                    dofs = mm.cell_dofs(c)
+                    dx[dofs] = inv[c] @ r[dofs]
+            ref = ref + 0.7 * dx
+        out = mapped.surrogate_mult_smooth(A, sol, x, b, 0.7, reverse=reverse)
+        assert np.abs(out - ref).max() <= 1e-12 * np.abs(ref).max()
+    # one color holding every cell reduces the multiplicative step to the additive one
+    assert np.allclose(sol.apply(b), sol.apply(b, 0) + sol.apply(b, 1), rtol=0, atol=1e-14 * np.abs(sol.apply(b)).max())
+
+
+def test_reversed_post_smoothing_makes_the_mapped_vcycle_symmetric():
+    """Sec. 4: with the colors of post-smoothing in the reverse order of
+    pre-smoothing the multiplicative V-cycle, as a linear map b -> MG(0, b),
+    is symmetric (it can precondition CG); with the same order it is not."""
+    meshes = [_distorted(2, 2, 2, lev, 19) for lev in (0, 1)]
+    N = meshes[-1].ndofs
+    for smoother in ("multiplicative", "additive"):
+        h = mapped.MappedHierarchy(meshes, [0.0, 0.6], m_pre=2, m_post=2, smoother=smoother)
+        B = np.column_stack([h.vcycle(np.zeros(N), e) for e in np.eye(N)])
+        assert np.abs(B - B.T).max() <= 1e-10 * np.abs(B).max(), smoother
+    h = mapped.MappedHierarchy(meshes, [0.0, 0.6], m_pre=1, m_post=1, smoother="multiplicative")
+    h.smooth = lambda l, x, b, post: mapped.surrogate_mult_smooth(h.A[l], h.solvers[l], x, b, 0.6, reverse=False)
+    B = np.column_stack([h.vcycle(np.zeros(N), e) for e in np.eye(N)])
+    assert np.abs(B - B.T).max() > 1e-4 * np.abs(B).max()
