@@ -465,6 +465,17 @@ int64_t fts_mapped_hierarchy_ndofs(const fts_mapped_hierarchy *hier);
  * precondition fts_mapped_pcg (Sec. 4, Tab. cubedist25mcp).  FTS_E_INVAL for
  * any other value. */
 fts_status fts_mapped_hierarchy_set_smoother(fts_mapped_hierarchy *hier, int32_t smoother);
+/* Local solvers of the smoother on levels >= 1: FTS_LOCAL_SURROGATE (default,
+ * the Cartesian surrogate of eq. avglength by fast diagonalisation) or
+ * FTS_LOCAL_EXACT (the inverse of the cell block R_K A R_K^T of the mapped
+ * operator, the sACS reference of Tab. cubedist25acp; the blocks are probed
+ * from the operator and inverted once, on the first request, and kept:
+ * ncells (k+1)^(2d) doubles per level, allocated through the registered
+ * allocator).  FTS_E_UNSUPPORTED above 64 unknowns per cell; FTS_E_INVAL for
+ * any other value.  Synchronous. */
+#define FTS_LOCAL_SURROGATE 0
+#define FTS_LOCAL_EXACT 1
+fts_status fts_mapped_hierarchy_set_local_solver(fts_mapped_hierarchy *hier, int32_t local);
 /* x <- MG_L(x, b) on the finest level. */
 fts_status fts_mapped_vcycle(fts_mapped_hierarchy *hier, const double *b, double *x, void *stream);
 /* FP64 CG preconditioned by one V-cycle (x = 0 initial guess of the V-cycle),

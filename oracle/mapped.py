@@ -371,6 +371,22 @@ class SurrogateCellSolvers:
         return out
 
 
+class ExactCellSolvers:
+    """LU factors of the exact cell blocks R_K A R_K^T of the mapped matrix
+    (the sACS smoother of Tab. cubedist25acp), with the interface of
+    ``SurrogateCellSolvers``."""
+
+    def __init__(self, mesh, A):
+        A = A.tocsr()
+        self.mesh = mesh
+        self.lu = {}
+        for c in mesh.cells():
+            dofs = mesh.cell_dofs(c)
+            self.lu[c] = sla.lu_factor(A[dofs][:, dofs].toarray())
+
+    apply = SurrogateCellSolvers.apply
+
+
 def surrogate_smooth(A, solvers, x, b, omega):
     """One additive step with the surrogate cell solvers (eq. schwarzproj)."""
     return x + omega * solvers.apply(b - A @ x)
@@ -401,9 +417,10 @@ class MappedHierarchy:
     ``multigrid.Hierarchy``.  smoother="multiplicative" replaces the additive
     step by ``surrogate_mult_smooth``, red before black in pre-smoothing and
     black before red in post-smoothing (Sec. 4: the reversed order makes the
-    V-cycle symmetric, so that it can precondition CG)."""
+    V-cycle symmetric, so that it can precondition CG).  local="exact" uses
+    ``ExactCellSolvers`` instead of the surrogates."""
 
-    def __init__(self, meshes, omegas, m_pre=1, m_post=1, smoother="additive"):
+    def __init__(self, meshes, omegas, m_pre=1, m_post=1, smoother="additive", local="surrogate"):
         from .multigrid import prolongation
         self.meshes, self.L = meshes, len(meshes) - 1
         self.omegas, self.m_pre, self.m_post = list(omegas), m_pre, m_post
@@ -411,7 +428,10 @@ class MappedHierarchy:
         self.A = [assemble(m) for m in meshes]
         shapes = [Mesh(m.dim, m.k, tuple(np.full(n, 1.0 / n) for n in m.ncells), 1.0) for m in meshes]
         self.P = [None] + [prolongation(shapes[l - 1], shapes[l]) for l in range(1, self.L + 1)]
-        self.solvers = [None] + [SurrogateCellSolvers(m) for m in meshes[1:]]
+        if local == "exact":
+            self.solvers = [None] + [ExactCellSolvers(m, self.A[l]) for l, m in enumerate(meshes) if l > 0]
+        else:
+            self.solvers = [None] + [SurrogateCellSolvers(m) for m in meshes[1:]]
         self.coarse_lu = sla.lu_factor(self.A[0].toarray())
 
     def vcycle(self, x, b, l=None):

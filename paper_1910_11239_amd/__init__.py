@@ -92,6 +92,7 @@ _SIGS = {
     "fts_mapped_hierarchy_destroy": (_I32, [_VP]),
     "fts_mapped_hierarchy_ndofs": (_I64, [_VP]),
     "fts_mapped_hierarchy_set_smoother": (_I32, [_VP, _I32]),
+    "fts_mapped_hierarchy_set_local_solver": (_I32, [_VP, _I32]),
     "fts_mapped_vcycle": (_I32, [_VP, _VP, _VP, _VP]),
     "fts_mapped_pcg_ws_bytes": (_SZ, [_VP]),
     "fts_mapped_pcg": (_I32, [_VP, _VP, _VP, _D, _I32, _VP, _SZ, _VP, _VP, _VP, _VP]),
@@ -488,6 +489,12 @@ class MappedHierarchy:
         """'additive' or 'multiplicative' (red-black cells, reversed in post-smoothing)."""
         code = {"additive": 0, "multiplicative": 1}[smoother]
         _check(lib().fts_mapped_hierarchy_set_smoother(self._h, code), "fts_mapped_hierarchy_set_smoother")
+
+    def set_local_solver(self, local):
+        """'surrogate' (fast diagonalisation of the Cartesian surrogate) or
+        'exact' (inverses of the mapped cell blocks)."""
+        code = {"surrogate": 0, "exact": 1}[local]
+        _check(lib().fts_mapped_hierarchy_set_local_solver(self._h, code), "fts_mapped_hierarchy_set_local_solver")
 
     def vcycle(self, b, x):
         _check(lib().fts_mapped_vcycle(self._h, _ptr(b, self.ndofs, "b"), _ptr(x, self.ndofs, "x"), _stream()),

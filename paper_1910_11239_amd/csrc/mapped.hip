@@ -896,15 +896,146 @@ __global__ void k_probe_scatter(int dim, int m0, int m1, int m2, int nc, int64_t
 struct fts_mapped_hierarchy {
     int nlevels = 0, m_pre = 1, m_post = 1;
     int smoother = FTS_SMOOTHER_ADDITIVE;
+    int local = FTS_LOCAL_SURROGATE;
     std::vector<double> omega;
     std::vector<fts_mapped_level *> levels;  // 0 = coarsest
     std::vector<fts_level *> shapes;  // Cartesian levels of the same cell counts and degree (transfers, slab shape)
     std::vector<double *> vb, vx, vr;
+    std::vector<double *> inv;  // per level >= 1 (built on request): inverses of the cell blocks R_K A R_K^T
     fts::CoarseLU *coarse = nullptr;
     double *host_scalars = nullptr;
 };
 
 namespace fts {
+
+// Exact cell solvers on mapped meshes: the diagonal blocks A_KK = R_K A R_K^T
+// of the mapped operator, probed with the red-black coloring (a cell's face
+// neighbours all have the other color, so (A e)|_K = A_KK e_K when e is zero
+// on every cell of the other color) and inverted in LDS.
+__device__ __forceinline__ int cell_parity(int dim, int m0, int m1, int64_t c) {
+    const int64_t c1 = c / m0;
+    const int64_t sum = c % m0 + (dim == 3 ? c1 % m1 + c1 / m1 : c1);
+    return (int)(sum & 1);
+}
+
+// e[(c, i)] = 1 on the cells c of `color`, 0 elsewhere.
+__global__ void k_cell_probe_set(int dim, int m0, int m1, int64_t ncells, int nc, int color, int i,
+                                 double *__restrict__ e) {
+    const int64_t n = ncells * nc;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = q / nc;
+        e[q] = (q - c * nc == i && cell_parity(dim, m0, m1, c) == color) ? 1.0 : 0.0;
+    }
+}
+
+// blk[c][row][i] = y[c nc + row] on the cells c of `color`.
+__global__ void k_cell_probe_take(int dim, int m0, int m1, int64_t ncells, int nc, int color, int i,
+                                  const double *__restrict__ y, double *__restrict__ blk) {
+    const int64_t n = ncells * nc;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = q / nc;
+        if (cell_parity(dim, m0, m1, c) != color) continue;
+        const int row = (int)(q - c * nc);
+        blk[(c * nc + row) * nc + i] = y[q];
+    }
+}
+
+// In-place Gauss-Jordan inversion of one nc x nc block per workgroup, in LDS
+// (no pivoting: the blocks are symmetric positive definite).
+__global__ void __launch_bounds__(256) k_invert_cells(int nc, double *__restrict__ blk) {
+    extern __shared__ double lds[];
+    double *a = lds, *col = lds + nc * nc;
+    double *g = blk + (int64_t)blockIdx.x * nc * nc;
+    const int t = threadIdx.x, nn = nc * nc;
+    for (int q = t; q < nn; q += blockDim.x) a[q] = g[q];
+    for (int p = 0; p < nc; ++p) {
+        __syncthreads();
+        for (int i = t; i < nc; i += blockDim.x) col[i] = a[i * nc + p];
+        __syncthreads();
+        const double piv = col[p];
+        for (int j = t; j < nc; j += blockDim.x) a[p * nc + j] = (j == p ? 1.0 : a[p * nc + j]) / piv;
+        __syncthreads();
+        for (int q = t; q < nn; q += blockDim.x) {
+            const int i = q / nc, j = q - i * nc;
+            if (i != p) a[q] = (j == p ? 0.0 : a[q]) - col[i] * a[p * nc + j];
+        }
+    }
+    __syncthreads();
+    for (int q = t; q < nn; q += blockDim.x) g[q] = a[q];
+}
+
+// x += omega A_KK^-1 r_K on the cells of `color` (every cell if color < 0);
+// one workgroup per cell, one thread per row (A_KK^-1 is symmetric, so row
+// `row` is read as column `row`: coalesced across the threads).
+__global__ void __launch_bounds__(64) k_mapped_exact(int dim, int m0, int m1, int nc, double omega, int color,
+                                                     const double *__restrict__ inv, const double *__restrict__ r,
+                                                     double *__restrict__ x) {
+    extern __shared__ double rs[];
+    const int64_t c = blockIdx.x;
+    if (color >= 0 && cell_parity(dim, m0, m1, c) != color) return;  // uniform over the workgroup
+    const double *ic = inv + c * nc * nc;
+    for (int q = threadIdx.x; q < nc; q += blockDim.x) rs[q] = r[c * nc + q];
+    __syncthreads();
+    for (int row = threadIdx.x; row < nc; row += blockDim.x) {
+        double acc = 0.0;
+        for (int j = 0; j < nc; ++j) acc = fma(ic[(int64_t)j * nc + row], rs[j], acc);
+        x[c * nc + row] += omega * acc;
+    }
+}
+
+constexpr int kExactMaxNc = 64;  // the inversion keeps a block and a column in LDS
+
+static fts_status build_exact_inverses(const fts_mapped_level *lv, double **out) {
+    *out = nullptr;
+    const int nc = (int)(lv->ndofs / lv->ncells);
+    if (nc > kExactMaxNc)
+        return fail(FTS_E_UNSUPPORTED, "exact cell solvers on mapped meshes: at most 64 unknowns per cell");
+    double *blk = nullptr, *e = nullptr, *y = nullptr;
+    const int64_t N = lv->ndofs;
+    fts_status st = FTS_OK;
+    if (dev_malloc(&blk, (size_t)lv->ncells * nc * nc * sizeof(double)) != hipSuccess ||
+        dev_malloc(&e, N * sizeof(double)) != hipSuccess || dev_malloc(&y, N * sizeof(double)) != hipSuccess)
+        st = fail(FTS_E_HIP, "device allocation of the exact cell solvers failed");
+    const unsigned grid = (unsigned)std::min<int64_t>((N + 255) / 256, 8192);
+    for (int color = 0; color < 2 && st == FTS_OK; ++color)
+        for (int i = 0; i < nc && st == FTS_OK; ++i) {
+            k_cell_probe_set<<<grid, 256>>>(lv->dim, lv->m[0], lv->m[1], lv->ncells, nc, color, i, e);
+            st = run_mapped(lv, 0, 0.0, e, nullptr, y, nullptr);
+            if (st == FTS_OK) {
+                k_cell_probe_take<<<grid, 256>>>(lv->dim, lv->m[0], lv->m[1], lv->ncells, nc, color, i, y, blk);
+                const hipError_t he = hipGetLastError();
+                if (he != hipSuccess) st = hip_fail(he, "cell probing");
+            }
+        }
+    if (st == FTS_OK) {
+        k_invert_cells<<<dim3((unsigned)lv->ncells), 256, (size_t)(nc * nc + nc) * sizeof(double)>>>(nc, blk);
+        const hipError_t he = hipGetLastError();
+        if (he != hipSuccess) st = hip_fail(he, "k_invert_cells launch");
+    }
+    if (st == FTS_OK && hipDeviceSynchronize() != hipSuccess) st = fail(FTS_E_HIP, "exact cell solver setup failed");
+    dev_free(e);
+    dev_free(y);
+    if (st != FTS_OK) {
+        dev_free(blk);
+        return st;
+    }
+    *out = blk;
+    return FTS_OK;
+}
+
+// x += omega sum_K (local solve of K) r_K over the cells of `color` (all if
+// color < 0), with the hierarchy's local solvers on level l.
+static fts_status local_apply(const fts_mapped_hierarchy *h, int l, const double *r, double *x, int color,
+                              hipStream_t s) {
+    const fts_mapped_level *lv = h->levels[l];
+    if (h->local != FTS_LOCAL_EXACT) return run_mapped(lv, 2, h->omega[l], r, nullptr, x, s, color);
+    if (lv->ncells == 0) return FTS_OK;
+    const int nc = (int)(lv->ndofs / lv->ncells);
+    k_mapped_exact<<<dim3((unsigned)lv->ncells), 64, nc * sizeof(double), s>>>(lv->dim, lv->m[0], lv->m[1], nc,
+                                                                               h->omega[l], color, h->inv[l], r, x);
+    const hipError_t he = hipGetLastError();
+    return he == hipSuccess ? FTS_OK : hip_fail(he, "k_mapped_exact launch");
+}
 
 static fts_status mapped_vcycle_level(fts_mapped_hierarchy *h, int l, const double *b, double *x, hipStream_t s,
                                       bool x_zero) {
@@ -919,14 +1050,14 @@ static fts_status mapped_vcycle_level(fts_mapped_hierarchy *h, int l, const doub
         // correction (the reversed order keeps the V-cycle symmetric)
         if (h->smoother != FTS_SMOOTHER_MULTIPLICATIVE) {
             fts_status e = first_zero ? FTS_OK : run_mapped(lv, 1, 0.0, x, b, r, s);
-            if (e == FTS_OK) e = run_mapped(lv, 2, h->omega[l], first_zero ? b : r, nullptr, x, s);
+            if (e == FTS_OK) e = local_apply(h, l, first_zero ? b : r, x, -1, s);
             return e;
         }
         fts_status e = FTS_OK;
         for (int ci = 0; ci < 2 && e == FTS_OK; ++ci) {
             const bool zero = first_zero && ci == 0;
             if (!zero) e = run_mapped(lv, 1, 0.0, x, b, r, s);
-            if (e == FTS_OK) e = run_mapped(lv, 2, h->omega[l], zero ? b : r, nullptr, x, s, post ? 1 - ci : ci);
+            if (e == FTS_OK) e = local_apply(h, l, zero ? b : r, x, post ? 1 - ci : ci, s);
         }
         return e;
     };
@@ -958,6 +1089,7 @@ fts_status fts_mapped_hierarchy_destroy(fts_mapped_hierarchy *h) {
     for (auto *p : h->vb) dev_free(p);
     for (auto *p : h->vx) dev_free(p);
     for (auto *p : h->vr) dev_free(p);
+    for (auto *p : h->inv) dev_free(p);
     for (auto *l : h->levels) fts_mapped_level_destroy(l);
     for (auto *l : h->shapes) fts_level_destroy(l);
     if (h->host_scalars) (void)hipHostFree(h->host_scalars);
@@ -1056,6 +1188,22 @@ fts_status fts_mapped_hierarchy_create(const fts_mapped_desc *levels, int32_t nl
 }
 
 int64_t fts_mapped_hierarchy_ndofs(const fts_mapped_hierarchy *h) { return h ? h->levels.back()->ndofs : -1; }
+
+fts_status fts_mapped_hierarchy_set_local_solver(fts_mapped_hierarchy *h, int32_t local) {
+    if (!h) return fail(FTS_E_INVAL, "fts_mapped_hierarchy_set_local_solver: NULL hierarchy");
+    if (local != FTS_LOCAL_SURROGATE && local != FTS_LOCAL_EXACT)
+        return fail(FTS_E_INVAL, "fts_mapped_hierarchy_set_local_solver: unknown local solver");
+    if (local == FTS_LOCAL_EXACT) {
+        h->inv.resize(h->nlevels, nullptr);
+        for (int l = 1; l < h->nlevels; ++l) {
+            if (h->inv[l]) continue;
+            fts_status st = build_exact_inverses(h->levels[l], &h->inv[l]);
+            if (st != FTS_OK) return st;
+        }
+    }
+    h->local = local;
+    return FTS_OK;
+}
 
 fts_status fts_mapped_hierarchy_set_smoother(fts_mapped_hierarchy *h, int32_t smoother) {
     if (!h) return fail(FTS_E_INVAL, "fts_mapped_hierarchy_set_smoother: NULL hierarchy");

@@ -55,6 +55,38 @@ def test_mapped_vcycle_matches_oracle(d, k, m, nlev, mpre, mpost, smoother):
     assert err < 1e-12
 
 
+@pytest.mark.parametrize("smoother", ["additive", "multiplicative"])
+@pytest.mark.parametrize("d,k,m,nlev", [(2, 3, 3, 2), (2, 2, 2, 3), (3, 2, 2, 2), (3, 3, 2, 2)])
+def test_mapped_vcycle_with_exact_cell_solvers_matches_oracle(d, k, m, nlev, smoother):
+    """The sACS / sMCS reference: the cell blocks R_K A R_K^T of the mapped
+    operator, probed and inverted on the GPU, against the oracle's LU of the
+    same blocks of the assembled matrix (k = 3 in 3-D: 64 unknowns per cell,
+    the largest block the inversion holds)."""
+    announce("mapped vcycle exact", smoother, d, k, m, nlev)
+    lv = _levels(d, k, m, nlev, 5)
+    omegas = [0.0] + [0.6] * (nlev - 1)
+    meshes = [mapped.MappedMesh(d, k, ms, V, 4.0) for ms, V in lv]
+    ohier = mapped.MappedHierarchy(meshes, omegas, m_pre=1, m_post=1, smoother=smoother, local="exact")
+    N = meshes[-1].ndofs
+    b, x = random_vector(N, 0), random_vector(N, 1)
+    ref = ohier.vcycle(x.copy(), b)
+    g = fts.MappedHierarchy(d, k, (m,) * d, [V for _, V in lv], 4.0, omegas, 1, 1)
+    g.set_smoother(smoother)
+    g.set_local_solver("exact")
+    xg = dev(x)
+    g.vcycle(dev(b), xg)
+    err = rel(host(xg), ref)
+    print("mapped V-cycle, exact cell solvers, vs oracle", err)
+    assert err < 1e-11
+
+
+def test_exact_cell_solvers_refuse_large_blocks():
+    lv = _levels(3, 4, 2, 2, 5)
+    g = fts.MappedHierarchy(3, 4, (2, 2, 2), [V for _, V in lv], 4.0, [0.0, 0.6], 1, 1)
+    with pytest.raises(fts.FtsError):
+        g.set_local_solver("exact")
+
+
 def _nu_frac(history, red=1e-8):
     """Fractional iteration count (Sec. 2.4) from the residual history: the
     number of steps that reduce the residual by `red` at the average rate of
@@ -97,7 +129,8 @@ def test_cg_iterations_on_distorted_meshes():
     Gaussian bells, assembled by the oracle on the mapped cells), CG to 1e-8
     with one V-cycle of the additive (ACS_m) or the red-black multiplicative
     (MCS_m, colors reversed in post-smoothing) cell smoother with surrogate
-    solvers, m = 1, 2 pre- and post-smoothing steps, as preconditioner.  The
+    solvers, or the additive one with exact cell solvers (sACS_m), m = 1, 2
+    pre- and post-smoothing steps, as preconditioner.  The
     paper's meshes come from another random draw of the vertex shifts, so its
     printed counts are matched within BAND, not reproduced.  (A white-noise
     right-hand side needs about half as many iterations again: the counts
@@ -106,7 +139,7 @@ def test_cg_iterations_on_distorted_meshes():
     results, problems = {}, {}
     for case in gold["cases"]:
         d, k, m, L, mm, omega = case["dim"], case["k"], case["m"], case["L"], case["smoothing_steps"], case["omega"]
-        announce("cubedist", case.get("smoother", "ACS"), d, k, L, mm)
+        announce("cubedist", case.get("smoother", "ACS"), case.get("local", "surrogate"), d, k, L, mm)
         if (d, k, m, L) not in problems:
             lv = _levels(d, k, m, L + 1, 0)
             fine = mapped.MappedMesh(d, k, lv[-1][0], lv[-1][1], 4.0)
@@ -115,11 +148,15 @@ def test_cg_iterations_on_distorted_meshes():
         g = fts.MappedHierarchy(d, k, (m,) * d, [V for _, V in lv], 4.0, [0.0] + [omega] * L, mm, mm)
         if case.get("smoother") == "MCS":
             g.set_smoother("multiplicative")
+        if case.get("local") == "exact":
+            g.set_local_solver("exact")
         x = torch.zeros_like(b)
         it, relres, hist = g.pcg(b, x, rtol=1e-8, maxit=300)
         nu = _nu_frac(hist)
-        results[f"{case.get('smoother', 'ACS')}_{d}d_L{L}_m{mm}"] = (it, round(nu, 2), case["printed"])
-        print(d, "D L", L, "m", mm, "iterations", it, "nu_frac", round(nu, 2), "printed", case["printed"], flush=True)
+        name = ("s" if case.get("local") == "exact" else "") + case.get("smoother", "ACS")
+        results[f"{name}_{d}d_L{L}_m{mm}"] = (it, round(nu, 2), case["printed"])
+        print(name, d, "D L", L, "m", mm, "iterations", it, "nu_frac", round(nu, 2), "printed", case["printed"],
+              flush=True)
         assert relres <= 1e-8
         assert abs(nu - case["printed"]) <= BAND * case["printed"], (nu, case)
     print(results)

@@ -219,3 +219,20 @@ def test_reversed_post_smoothing_makes_the_mapped_vcycle_symmetric():
     h.smooth = lambda l, x, b, post: mapped.surrogate_mult_smooth(h.A[l], h.solvers[l], x, b, 0.6, reverse=False)
     B = np.column_stack([h.vcycle(np.zeros(N), e) for e in np.eye(N)])
     assert np.abs(B - B.T).max() > 1e-4 * np.abs(B).max()
+
+
+def test_exact_cell_solvers_equal_the_surrogates_on_rectilinear_grids():
+    """The exact cell blocks of the mapped matrix and the surrogate boxes are
+    built by separate routes (the mapped quadrature against a Cartesian
+    mini-mesh); on a rectilinear grid both are the Cartesian cell block, and
+    on a distorted mesh they differ."""
+    _, mm = _rect(2, 3, (3, 4), 23)
+    r = random_vector(mm.ndofs, 4)
+    ex = mapped.ExactCellSolvers(mm, mapped.assemble(mm)).apply(r)
+    su = mapped.SurrogateCellSolvers(mm).apply(r)
+    assert np.abs(ex - su).max() <= 1e-11 * np.abs(su).max()
+    md = _distorted(2, 3, 3, 1, 23)
+    r = random_vector(md.ndofs, 4)
+    ex = mapped.ExactCellSolvers(md, mapped.assemble(md)).apply(r)
+    su = mapped.SurrogateCellSolvers(md).apply(r)
+    assert np.abs(ex - su).max() > 1e-3 * np.abs(su).max()
