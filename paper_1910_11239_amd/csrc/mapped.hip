@@ -74,11 +74,19 @@ __device__ void contract(const double *in, const int *e, int a, const double *M,
 
 // Jacobian J[b][a] = d x_b / d xi_a of the multilinear map through the corners
 // X[corner * D + b] (corner = sum_a o_a 2^a) at xi; returns det J and J^-1.
-template <int D>
+// The loop over the corners is unrolled UNR times.  Fully unrolled, the 3-D
+// operator kernel loads all 24 corner coordinates at once and the two
+// Jacobians of a face point hold about 200 VGPRs (two waves per SIMD); four
+// corners at a time keep it near 96 (five waves), which is faster for
+// k <= 4 (32^3 Q3 distorted residual 0.44 -> 0.31 ms).  For k >= 5 LDS caps
+// the occupancy at three waves anyway and the full unroll is faster (16^3 Q5:
+// 0.134 against 0.147 ms).
+template <int D, int UNR = (1 << D)>
 __device__ double jacobian_inverse(const double *X, const double *xi, double Ji[D][D]) {
     double J[D][D];
     for (int b = 0; b < D; ++b)
         for (int a = 0; a < D; ++a) J[b][a] = 0.0;
+#pragma unroll UNR
     for (int cidx = 0; cidx < (1 << D); ++cidx)
         for (int a = 0; a < D; ++a) {
             double dN = ((cidx >> a) & 1) ? 1.0 : -1.0;
@@ -112,6 +120,10 @@ __device__ double jacobian_inverse(const double *X, const double *xi, double Ji[
     }
     return det;
 }
+
+// Corners per step of the Jacobian's corner loop for degree N1 - 1.
+template <int D, int N1>
+constexpr int jac_unroll() { return (D == 3 && N1 <= 5) ? 4 : (1 << D); }
 
 template <int D>
 __device__ void load_corners(const MappedView &g, int64_t cell, double *X) {
@@ -237,7 +249,7 @@ __device__ __forceinline__ void face_terms(const MappedView &g, int64_t cell, co
             wf *= swq[gb];
         }
         double Ji[D][D];
-        const double det = jacobian_inverse<D>(X, xi, Ji);
+        const double det = jacobian_inverse<D, jac_unroll<D, N1>()>(X, xi, Ji);
         double nrm = 0.0;
         for (int b = 0; b < D; ++b) nrm += Ji[TT][b] * Ji[TT][b];
         nrm = sqrt(nrm);
@@ -254,7 +266,7 @@ __device__ __forceinline__ void face_terms(const MappedView &g, int64_t cell, co
         double cv, jmp;
         if (interior) {
             double Jn[D][D];
-            (void)jacobian_inverse<D>(Xn, xin, Jn);
+            (void)jacobian_inverse<D, jac_unroll<D, N1>()>(Xn, xin, Jn);
             double dnp = 0.0;
             for (int b = 0; b < D; ++b) {
                 double ph = 0.0;
@@ -391,7 +403,7 @@ k_mapped_operator(MappedView g, const double *__restrict__ x, const double *__re
             w *= swq[q[a]];
         }
         double Ji[D][D];
-        const double det = jacobian_inverse<D>(X, xi, Ji);
+        const double det = jacobian_inverse<D, jac_unroll<D, N1>()>(X, xi, Ji);
         double gr[D], fl[D];
         for (int a = 0; a < D; ++a) gr[a] = G(a)[p];
         // physical gradient J^-T gr, then back: flux_a = w det sum_b Ji[a][b] (J^-T gr)_b
