@@ -16,7 +16,8 @@ Per-kernel rooflines are measured live with events on the launch stream.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
                     [--no-mixed] [--no-batched] [--no-mult]
-    python bench.py --profile-only | --profile-mixed PREC | --calibrate-copy   (for rocprofv3)
+    python bench.py --profile-only | --profile-mixed PREC | --profile-batched | --profile-distorted
+                    | --calibrate-copy   (for rocprofv3)
 
 The JSON line also carries the smoother rooflines, the 48^3 Q7
 mixed-precision CG comparison, the 64-mesh batched sweep, the multiplicative
@@ -370,6 +371,8 @@ def main():
     ap.add_argument("--profile-mixed", choices=["f64", "f32", "f16", "bf16"],
                     help="run warmup + steps V-cycles of the 48^3 Q7 CG preconditioner at this contraction "
                          "precision only (for rocprofv3)")
+    ap.add_argument("--profile-distorted", action="store_true",
+                    help="only the distorted-mesh multigrid V-cycle (ACS_1), warmup + steps times (for rocprofv3)")
     ap.add_argument("--profile-batched", action="store_true",
                     help="run the 64-mesh batched smoother only: 3 x (FP32 patch apply + gathers, FP64 residual) "
                          "at 256 threads x 1,024 workgroups x chunks of 4 (for rocprofv3)")
@@ -393,6 +396,19 @@ def main():
         print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "copies": args.steps}))
         return
     import paper_1910_11239_amd as fts
+    if args.profile_distorted:
+        from synthetic import distorted_vertices
+        levels = [distorted_vertices(3, 8, lev, 0.25, 0)[1] for lev in range(3)]
+        hd = fts.MappedHierarchy(3, 3, (8, 8, 8), levels, 4.0, [0.0, 0.55, 0.55], 1, 1)
+        bd = torch.as_tensor(random_vector(hd.ndofs, 0)).cuda()
+        xd = torch.zeros_like(bd)
+        for _ in range(args.warmup + args.steps):
+            xd.zero_()
+            hd.vcycle(bd, xd)
+        torch.cuda.synchronize()
+        print(json.dumps({"distorted_dofs": hd.ndofs, "vcycles": args.warmup + args.steps}))
+        return
+
     if args.profile_batched:
         from synthetic import batched_meshes
         batch = fts.Batch([(k, w, 1.0) for k, w in batched_meshes()])
