@@ -282,11 +282,16 @@ fts_status fts_pcg(fts_hierarchy *hier, fts_prec prec, const double *b, double *
                    double *history, void *stream);
 
 /* Smoother of the V-cycle on every level > 0: FTS_SMOOTHER_ADDITIVE (default,
- * Alg. addsmoother) or FTS_SMOOTHER_MULTIPLICATIVE (Alg. multsmoother with the
+ * Alg. addsmoother), FTS_SMOOTHER_MULTIPLICATIVE (Alg. multsmoother with the
  * colors of fts_schwarz_smooth_mult; pre- and post-smoothing run the colors
- * in the same order, so the V-cycle is not symmetric: use fts_gmres). */
+ * in the same order, as in Sec. 2.4, so the V-cycle is not symmetric: use
+ * fts_gmres) or FTS_SMOOTHER_MULTIPLICATIVE_SYMMETRIC (post-smoothing runs
+ * the colors in reverse order, the symmetrisation of Sec. 4, so the V-cycle
+ * is symmetric and can precondition fts_pcg).  FTS_E_INVAL for other values;
+ * fts_vcycle_adjoint needs the additive smoother. */
 #define FTS_SMOOTHER_ADDITIVE 0
 #define FTS_SMOOTHER_MULTIPLICATIVE 1
+#define FTS_SMOOTHER_MULTIPLICATIVE_SYMMETRIC 2
 fts_status fts_hierarchy_set_smoother(fts_hierarchy *hier, int32_t smoother);
 
 /* Workspace bytes of fts_gmres: 2 restart + 2 finest-level vectors plus

@@ -56,7 +56,9 @@ class Hierarchy:
     omegas[l] and gamma_hats[l] (l = 0..L) are per-level relaxation and
     penalty factors (omegas[0] unused).  smoother: "additive" (Alg. addsmoother)
     or "multiplicative" (Alg. multsmoother with red-black cells or the 2^(d+1)
-    vertex-patch colors, pre- and post-smoothing in the same color order)."""
+    vertex-patch colors, pre- and post-smoothing in the same color order), or
+    "multiplicative_symmetric" (post-smoothing in the reverse color order, the
+    symmetrisation Sec. 4 applies so that the V-cycle preconditions CG)."""
 
     def __init__(self, fine, nlevels, kind="vertex", omegas=0.5, m_pre=1, m_post=1,
                  gamma_hats=None, cache=True, smoother="additive"):
@@ -81,9 +83,13 @@ class Hierarchy:
         col = cell_red_black if kind == "cell" else vertex_patch_mult_colors
         self.colors = [None] + [col(meshes[l]) for l in range(1, L + 1)]
 
-    def smooth(self, l, x, b):
-        if self.smoother == "multiplicative":
-            return multiplicative_smooth(self.A[l], self.solvers[l], x, b, self.omegas[l], self.colors[l])
+    def smooth(self, l, x, b, post=False):
+        if self.smoother in ("multiplicative", "multiplicative_symmetric"):
+            colors = self.colors[l]
+            if post and self.smoother == "multiplicative_symmetric":
+                top = max(colors)
+                colors = [top - c for c in colors]  # the same colors, visited in reverse order
+            return multiplicative_smooth(self.A[l], self.solvers[l], x, b, self.omegas[l], colors)
         return additive_smooth(self.A[l], self.solvers[l], x, b, self.omegas[l])
 
     def vcycle(self, x, b, l=None):
@@ -96,5 +102,5 @@ class Hierarchy:
         e = self.vcycle(np.zeros(self.meshes[l - 1].ndofs), bc, l - 1)
         x = x + self.P[l] @ e
         for _ in range(self.m_post):
-            x = self.smooth(l, x, b)
+            x = self.smooth(l, x, b, post=True)
         return x

@@ -354,9 +354,11 @@ class Hierarchy:
         return it.value, rel.value, hist[:it.value + 1]
 
     def set_smoother(self, smoother):
-        """'additive' (default) or 'multiplicative' on every smoothed level."""
-        _check(lib().fts_hierarchy_set_smoother(self._h, {"additive": 0, "multiplicative": 1}[smoother]),
-               "fts_hierarchy_set_smoother")
+        """'additive' (default), 'multiplicative' (colors in the same order
+        before and after the coarse correction) or 'multiplicative_symmetric'
+        (reversed after it) on every smoothed level."""
+        code = {"additive": 0, "multiplicative": 1, "multiplicative_symmetric": 2}[smoother]
+        _check(lib().fts_hierarchy_set_smoother(self._h, code), "fts_hierarchy_set_smoother")
 
     def gmres(self, b, x, rtol=1e-10, restart=30, maxit=200, prec="f64", ws=None):
         """Flexible restarted GMRES with one V-cycle as right preconditioner; x:

@@ -227,20 +227,24 @@ fts_status fts_coarse_solve(fts_hierarchy *h, const double *b0, double *x0, void
     return coarse_solve(h->coarse, b0, x0, S(stream));
 }
 
-// One smoothing step on level l: Alg. addsmoother (one residual, all local
-// solves) or Alg. multsmoother (a residual before each color).
-// One smoothing step x <- S(x, b).  x_zero: x is known to be zero on entry,
-// so the first residual is b itself (A 0 = 0) and is not computed.
+// One smoothing step x <- S(x, b) on level l: Alg. addsmoother (one
+// residual, all local solves) or Alg. multsmoother (a residual before each
+// color; with FTS_SMOOTHER_MULTIPLICATIVE_SYMMETRIC the colors of a
+// post-smoothing step (post = true) run in reverse order).  x_zero: x is
+// known to be zero on entry, so the first residual is b itself (A 0 = 0) and
+// is not computed.
 static fts_status smooth_step(fts_hierarchy *h, int l, fts_prec prec, const double *b, double *x, hipStream_t s,
-                              bool x_zero = false) {
+                              bool x_zero = false, bool post = false) {
     const fts_level *lv = h->levels[l];
     const fts_eigs *eg = h->eigs[l];
     double *r = h->vr[l];
     fts_status st = FTS_OK;
-    if (h->smoother == FTS_SMOOTHER_MULTIPLICATIVE) {
+    if (h->smoother != FTS_SMOOTHER_ADDITIVE) {
         const int nc = schwarz_mult_colors(eg);
-        for (int c = 0; c < nc && st == FTS_OK; ++c) {
-            const bool first = x_zero && c == 0;
+        const bool reverse = post && h->smoother == FTS_SMOOTHER_MULTIPLICATIVE_SYMMETRIC;
+        for (int i = 0; i < nc && st == FTS_OK; ++i) {
+            const int c = reverse ? nc - 1 - i : i;
+            const bool first = x_zero && i == 0;
             if (!first) st = launch_operator(lv, x, b, r, true, s);
             if (st == FTS_OK) st = launch_schwarz_color(lv, eg, h->omega[l], prec, first ? b : r, x, c, s);
         }
@@ -263,7 +267,7 @@ static fts_status vcycle_level(fts_hierarchy *h, int l, fts_prec prec, const dou
     if (st == FTS_OK && l - 1 > 0) st = launch_fill(h->vx[l - 1], h->levels[l - 1]->ndofs, 0.0, s);
     if (st == FTS_OK) st = vcycle_level(h, l - 1, prec, h->vb[l - 1], h->vx[l - 1], s, true);
     if (st == FTS_OK) st = launch_prolongate(h->levels[l - 1], lv, h->vx[l - 1], x, s);
-    for (int i = 0; i < h->m_post && st == FTS_OK; ++i) st = smooth_step(h, l, prec, b, x, s);
+    for (int i = 0; i < h->m_post && st == FTS_OK; ++i) st = smooth_step(h, l, prec, b, x, s, false, true);
     return st;
 }
 
@@ -449,7 +453,8 @@ fts_status fts_gmres(fts_hierarchy *h, fts_prec prec, const double *b, double *x
 
 fts_status fts_hierarchy_set_smoother(fts_hierarchy *h, int32_t smoother) {
     if (!h) return fail(FTS_E_INVAL, "fts_hierarchy_set_smoother: NULL handle");
-    if (smoother != FTS_SMOOTHER_ADDITIVE && smoother != FTS_SMOOTHER_MULTIPLICATIVE)
+    if (smoother != FTS_SMOOTHER_ADDITIVE && smoother != FTS_SMOOTHER_MULTIPLICATIVE &&
+        smoother != FTS_SMOOTHER_MULTIPLICATIVE_SYMMETRIC)
         return fail(FTS_E_INVAL, "fts_hierarchy_set_smoother: unknown smoother");
     h->smoother = smoother;
     return FTS_OK;

@@ -78,22 +78,23 @@ def test_mult_smoother_reduced_precision(prec, bound):
     assert err < bound
 
 
-def hierarchies(kind, d, k, ms, nl, omega, seed):
+def hierarchies(kind, d, k, ms, nl, omega, seed, smoother="multiplicative"):
     fine = omesh(d, k, tuple(mm >> (nl - 1) for mm in ms), seed)
     for _ in range(nl - 1):
         fine = refine(fine)
     omegas = [0.0] + [omega] * (nl - 1)
-    oh = multigrid.Hierarchy(fine, nl, kind, omegas, m_pre=1, m_post=1, cache=False, smoother="multiplicative")
+    oh = multigrid.Hierarchy(fine, nl, kind, omegas, m_pre=1, m_post=1, cache=False, smoother=smoother)
     gh = fts.Hierarchy(d, k, fine.widths, nl, kind, omegas, fine.gamma_hat, m_pre=1, m_post=1)
-    gh.set_smoother("multiplicative")
+    gh.set_smoother(smoother)
     return fine, oh, gh
 
 
+@pytest.mark.parametrize("smoother", ["multiplicative", "multiplicative_symmetric"])
 @pytest.mark.parametrize("kind,d,k,ms,nl", [("vertex", 3, 2, (8, 4, 4), 3), ("cell", 2, 3, (8, 12), 3),
                                             ("vertex", 2, 4, (8, 8), 3)])
-def test_vcycle_mult_parity(kind, d, k, ms, nl):
-    announce("mult vcycle", kind, d, k, ms, nl)
-    fine, oh, gh = hierarchies(kind, d, k, ms, nl, 1.0, 33)
+def test_vcycle_mult_parity(kind, d, k, ms, nl, smoother):
+    announce("mult vcycle", smoother, kind, d, k, ms, nl)
+    fine, oh, gh = hierarchies(kind, d, k, ms, nl, 1.0, 33, smoother)
     b, x = random_vector(fine.ndofs, 0), random_vector(fine.ndofs, 1)
     ref = oh.vcycle(x.copy(), b)
     xg = dev(x)
@@ -141,3 +142,31 @@ def test_gmres_additive_vcycle_agrees_with_pcg():
     itc, relc, _ = gh.pcg(b, xc, rtol=1e-10, maxit=200)
     assert relg <= 1e-10 and relc <= 1e-10
     assert rel(host(xg), host(xc)) < 1e-8
+
+
+@pytest.mark.parametrize("kind,d,k,ms,nl", [("cell", 3, 3, (8, 8, 8), 3), ("vertex", 3, 2, (8, 8, 8), 3),
+                                            ("cell", 2, 4, (16, 16), 3)])
+def test_pcg_with_symmetrised_multiplicative_vcycle(kind, d, k, ms, nl):
+    """The symmetrised multiplicative V-cycle (colors reversed in
+    post-smoothing) preconditions CG: the library's PCG reaches 1e-10 with
+    the oracle's iteration count and residual history (oracle PCG with the
+    oracle's symmetrised V-cycle), and the solution is the discrete one."""
+    announce("pcg symmetric mult", kind, d, k, ms, nl)
+    fine = uniform_mesh(d, k, tuple(mm >> (nl - 1) for mm in ms))
+    for _ in range(nl - 1):
+        fine = refine(fine)
+    omegas = [0.0] + [1.0] * (nl - 1)
+    oh = multigrid.Hierarchy(fine, nl, kind, omegas, m_pre=1, m_post=1, smoother="multiplicative_symmetric")
+    b = random_vector(fine.ndofs, 0)
+    xo, ito, histo = krylov.pcg(oh.A[-1], b, lambda v: oh.vcycle(np.zeros_like(v), v), rtol=1e-10, maxit=200,
+                                flexible=True)
+    gh = fts.Hierarchy(d, k, fine.widths, nl, kind, omegas, fine.gamma_hat, m_pre=1, m_post=1)
+    gh.set_smoother("multiplicative_symmetric")
+    xg = dev(np.zeros(fine.ndofs))
+    it, relres, hist = gh.pcg(dev(b), xg, rtol=1e-10, maxit=200)
+    print("pcg iterations gpu", it, "oracle", ito, "final", relres)
+    assert relres <= 1e-10 and abs(it - ito) <= 1
+    nh = min(6, len(hist), len(histo))
+    assert np.allclose(hist[:nh], histo[:nh], rtol=1e-8, atol=1e-14)
+    xs = onedim.global_fastdiag_solve(fine, b)
+    assert rel(host(xg), xs) < 1e-8

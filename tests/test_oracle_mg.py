@@ -95,3 +95,21 @@ def test_gmres_with_multiplicative_vcycle_converges(kind, d, k, ms):
     assert hist[-1] <= 1e-10 and it < 40
     xs = onedim.global_fastdiag_solve(fine, b)
     assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
+
+
+@pytest.mark.parametrize("kind,d,k,ms", [("cell", 2, 2, (4, 4)), ("vertex", 2, 1, (4, 4)), ("cell", 3, 1, (2, 2, 4))])
+def test_reversed_post_smoothing_symmetrises_the_multiplicative_vcycle(kind, d, k, ms):
+    """With the colors of post-smoothing in the reverse order of
+    pre-smoothing, the multiplicative V-cycle as a linear map b -> MG(0, b) is
+    symmetric (and positive: CG can use it); with the same order it is not."""
+    mesh = Mesh(d, k, [np.full(m, 1.0 / m) for m in ms], 1.0)
+    N = mesh.ndofs
+    for smoother, sym in (("multiplicative_symmetric", True), ("multiplicative", False)):
+        h = multigrid.Hierarchy(mesh, 2, kind, [0.0, 0.8], m_pre=1, m_post=1, smoother=smoother)
+        B = np.column_stack([h.vcycle(np.zeros(N), e) for e in np.eye(N)])
+        asym = np.abs(B - B.T).max() / np.abs(B).max()
+        if sym:
+            assert asym <= 1e-10, (smoother, asym)
+            assert np.linalg.eigvalsh(0.5 * (B + B.T)).min() > 0
+        else:
+            assert asym > 1e-4, (smoother, asym)
