@@ -107,3 +107,32 @@ def test_library_sources_never_call_hipmalloc():
 def test_allocator_must_be_given_in_pairs():
     lib = fts.lib()
     assert lib.fts_set_allocator(fts._ALLOC_CB, ctypes.cast(None, fts._FREE_T), None) == -1
+
+
+def test_mapped_hierarchy_validates_before_allocating():
+    """fts_mapped_hierarchy_create checks the level list (count, dimension,
+    degree, twice the cells per axis from one level to the next) before any
+    device work; the setters check their handle and value."""
+    lib = fts.lib()
+    verts = [np.zeros(((2 * 2 ** l + 1) ** 2, 2)) for l in range(2)]
+    descs = (fts.MappedDesc * 2)()
+    for l in range(2):
+        descs[l].dim, descs[l].degree, descs[l].penalty_factor = 2, 2, 4.0
+        for a in range(3):
+            descs[l].ncells[a] = 2 * 2 ** l if a < 2 else 1
+        descs[l].vertices = verts[l].ctypes.data
+    descs[1].ncells[0] = 3  # not twice the coarse count
+    om = np.array([0.0, 0.5])
+    h = ctypes.c_void_p()
+    assert lib.fts_mapped_hierarchy_create(descs, 2, om.ctypes.data, 1, 1, ctypes.byref(h)) == -1
+    assert "twice" in fts.last_error()
+    descs[1].ncells[0] = 4
+    descs[1].degree = 3  # another degree
+    assert lib.fts_mapped_hierarchy_create(descs, 2, om.ctypes.data, 1, 1, ctypes.byref(h)) == -1
+    assert lib.fts_mapped_hierarchy_create(descs, 0, om.ctypes.data, 1, 1, ctypes.byref(h)) == -1
+    assert lib.fts_mapped_hierarchy_create(descs, 2, om.ctypes.data, -1, 1, ctypes.byref(h)) == -1
+    assert lib.fts_mapped_hierarchy_set_smoother(None, 0) == -1
+    assert lib.fts_mapped_hierarchy_set_local_solver(None, 0) == -1
+    assert lib.fts_mapped_hierarchy_destroy(None) == 0
+    assert lib.fts_mapped_hierarchy_ndofs(None) == -1
+    assert lib.fts_hierarchy_set_smoother(None, 2) == -1
