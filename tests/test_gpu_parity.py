@@ -230,6 +230,47 @@ def test_one_patch_mesh_is_exact_solve(d, k):
     assert np.linalg.norm(A @ xs - b) < 1e-10 * np.linalg.norm(b)
 
 
+@pytest.mark.parametrize("d,k,ms", [(2, 5, (1, 1)), (3, 3, (1, 1, 1))])
+def test_one_cell_mesh_is_exact_solve(d, k, ms):
+    """Degenerate mesh of one cell (every face on the boundary): the cell
+    smoother with omega = 1 is the exact solve A^-1 b, and the residual is
+    the assembled one."""
+    announce("one cell", d, k)
+    m = omesh(d, k, ms, 15)
+    A = sipg.assemble(m)
+    b, x0 = random_vector(m.ndofs, 0), random_vector(m.ndofs, 1)
+    lv = glevel(m)
+    r = dev(np.zeros(m.ndofs))
+    lv.residual(dev(b), dev(x0), r)
+    assert rel(host(r), b - A @ x0) < 1e-12
+    eg = fts.Eigs(lv, "cell")
+    xg = dev(x0)
+    fts.schwarz_smooth(lv, eg, 1.0, dev(b), xg, nsweeps=1)
+    assert np.linalg.norm(A @ host(xg) - b) < 1e-10 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("d,k,ms", [(3, 2, (1, 3, 3)), (2, 3, (5, 1))])
+def test_vertex_patches_need_two_cells_per_axis(d, k, ms):
+    """A mesh with a single cell along some axis has no interior vertex (the
+    oracle finds no vertex patch): the library refuses vertex-patch tables
+    for it with an error instead of returning an empty smoother, and the
+    cell smoother on the same mesh works."""
+    announce("no patches", d, k, ms)
+    m = omesh(d, k, ms, 16)
+    assert len(schwarz.vertex_patch_subdomains(m)) == 0
+    lv = glevel(m)
+    with pytest.raises(fts.FtsError, match="at least 2 cells"):
+        fts.Eigs(lv, "vertex")
+    eg = fts.Eigs(lv, "cell")
+    A = sipg.assemble(m)
+    sol = schwarz.ExactLocalSolvers(A, schwarz.cell_subdomains(m), cache=False)
+    b, x0 = random_vector(m.ndofs, 0), random_vector(m.ndofs, 1)
+    ref = schwarz.additive_smooth(A, sol, x0, b, 0.7)
+    xg = dev(x0)
+    fts.schwarz_smooth(lv, eg, 0.7, dev(b), xg, nsweeps=1)
+    assert rel(host(xg), ref) < 1e-12
+
+
 @pytest.mark.parametrize("d,k,ms", [(2, 3, (3, 2)), (3, 2, (2, 3, 2)), (3, 4, (1, 2, 2)), (3, 9, (1, 1, 2))])
 def test_transfers(d, k, ms):
     announce("transfer", d, k, ms)
