@@ -184,3 +184,21 @@ def test_damping_must_drop_on_distorted_meshes():
     assert nu[0.5] < nu[0.45] < nu[0.4] < 100
     for omega, printed in ((0.5, 38.7), (0.45, 42.9), (0.4, 48.6)):
         assert abs(nu[omega] - printed) <= BAND * printed, (omega, nu[omega], printed)
+
+
+@pytest.mark.parametrize("d,k,m", [(2, 3, 3), (3, 2, 2), (2, 2, 1)])
+def test_single_level_mapped_hierarchy_is_the_exact_solve(d, k, m):
+    """One level: the V-cycle is the coarse solve, the probed mapped matrix
+    factored by the slab LU, i.e. x = A^-1 b of the oracle's assembled mapped
+    matrix (m = 1: a single cell, whose vertices are all on the boundary and
+    stay in place, in one slab)."""
+    announce("mapped single level", d, k, m)
+    ms, V = distorted_vertices(d, m, 0, 0.25, 9)
+    mm = mapped.MappedMesh(d, k, ms, V, 4.0)
+    A = mapped.assemble(mm).toarray()
+    b = random_vector(mm.ndofs, 0)
+    xs = np.linalg.solve(A, b)
+    g = fts.MappedHierarchy(d, k, (m,) * d, [V], 4.0, [0.0], 1, 1)
+    xg = dev(np.zeros(mm.ndofs))
+    g.vcycle(dev(b), xg)
+    assert rel(host(xg), xs) < 1e-11 * max(1.0, np.linalg.cond(A) / 1e3)
