@@ -365,7 +365,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the 48^3 Q7 mixed-precision CG comparison")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-mesh batched sweep")
     ap.add_argument("--no-mult", action="store_true", help="skip the multiplicative-smoother measurements")
-    ap.add_argument("--no-distorted", action="store_true", help="skip the distorted-mesh surrogate smoother")
+    ap.add_argument("--no-distorted", action="store_true", help="skip the distorted-mesh surrogate smoother and multigrid")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup + steps of the V-cycle only (for rocprofv3)")
     ap.add_argument("--profile-mixed", choices=["f64", "f32", "f16", "bf16"],
