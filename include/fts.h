@@ -72,7 +72,7 @@ typedef enum { FTS_PREC_F64 = 0, FTS_PREC_F32 = 1, FTS_PREC_BF16 = 2, FTS_PREC_F
  * Homogeneous Dirichlet conditions are imposed weakly on the whole boundary. */
 typedef struct fts_mesh_desc {
     int32_t dim;            /* 2 or 3 */
-    int32_t degree;         /* k, 1..9 */
+    int32_t degree;         /* k: 1..9 in 3-D, 1..15 in 2-D */
     int32_t ncells[3];      /* cells per axis (ncells[2] ignored for dim 2) */
     const double *h[3];     /* host arrays of widths */
     double penalty_factor;  /* gamma_hat > 0 */
@@ -104,7 +104,7 @@ fts_status fts_last_error(char *buf, size_t len);
 
 /* Builds the FP64 1-D operator tables of the SIPG form on this mesh (Sec. 3.2,
  * eq. 1Dstiffnessmass, 1Dnitsche, 1Dsipg, 1DsipgVP) and uploads them to the
- * current device.  Validates: dim in {2,3}, 1 <= degree <= 9, ncells >= 1,
+ * current device.  Validates: dim in {2,3}, 1 <= degree <= 9 (3-D) or 15 (2-D), ncells >= 1,
  * h > 0 and finite, penalty_factor > 0.  *out receives the handle. */
 fts_status fts_level_create(const fts_mesh_desc *mesh, fts_level **out);
 fts_status fts_level_destroy(fts_level *level);

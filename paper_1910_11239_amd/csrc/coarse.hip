@@ -74,7 +74,7 @@ struct CoarseLU {
 // number a = kind * nxy + q takes sum_z f[kind][z] u[q + z nxy] over the node
 // line q (f[0] = phi(1), f[1] = phi'(1)); ginv = G^-1 of their Gram matrix.
 struct FaceMap {
-    double f[2][kMaxN1];
+    double f[2][kMaxN1Any];
     double ginv[2][2];
     int n1, nxy, nc, rc;
 };

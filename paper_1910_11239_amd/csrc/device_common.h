@@ -245,7 +245,8 @@ fts_status dispatch(int dim, int n1, Args &&...args) {
 #define FTS_CASE(DD, NN) \
     if (dim == DD && n1 == NN) return F<DD, NN>::run(args...);
     FTS_CASE(2, 2) FTS_CASE(2, 3) FTS_CASE(2, 4) FTS_CASE(2, 5) FTS_CASE(2, 6) FTS_CASE(2, 7)
-    FTS_CASE(2, 8) FTS_CASE(2, 9) FTS_CASE(2, 10)
+    FTS_CASE(2, 8) FTS_CASE(2, 9) FTS_CASE(2, 10) FTS_CASE(2, 11) FTS_CASE(2, 12) FTS_CASE(2, 13)
+    FTS_CASE(2, 14) FTS_CASE(2, 15) FTS_CASE(2, 16)
     FTS_CASE(3, 2) FTS_CASE(3, 3) FTS_CASE(3, 4) FTS_CASE(3, 5) FTS_CASE(3, 6) FTS_CASE(3, 7)
     FTS_CASE(3, 8) FTS_CASE(3, 9) FTS_CASE(3, 10)
 #undef FTS_CASE

@@ -14,8 +14,10 @@
 
 namespace fts {
 
-constexpr int kMaxDegree = 9;
+constexpr int kMaxDegree = 9;     // 3-D
+constexpr int kMaxDegree2D = 15;  // 2-D (a patch of n = 32 lines still fits a workgroup)
 constexpr int kMaxN1 = kMaxDegree + 1;
+constexpr int kMaxN1Any = kMaxDegree2D + 1;
 
 void set_error(const std::string &msg);
 

@@ -394,7 +394,8 @@ fts_status fts_level_create(const fts_mesh_desc *mesh, fts_level **out) {
     if (!mesh || !out) return fail(FTS_E_INVAL, "fts_level_create: NULL argument");
     *out = nullptr;
     if (mesh->dim != 2 && mesh->dim != 3) return fail(FTS_E_UNSUPPORTED, "dim must be 2 or 3");
-    if (mesh->degree < 1 || mesh->degree > kMaxDegree) return fail(FTS_E_UNSUPPORTED, "degree must be in 1..9");
+    if (mesh->degree < 1 || mesh->degree > (mesh->dim == 2 ? kMaxDegree2D : kMaxDegree))
+        return fail(FTS_E_UNSUPPORTED, mesh->dim == 2 ? "degree must be in 1..15 in 2-D" : "degree must be in 1..9 in 3-D");
     if (!(mesh->penalty_factor > 0.0) || !std::isfinite(mesh->penalty_factor))
         return fail(FTS_E_INVAL, "penalty_factor must be positive");
     fts_level *lv = new fts_level();

@@ -34,7 +34,8 @@ def glevel(m):
     return fts.Level(m.dim, m.k, m.widths, m.gamma_hat)
 
 
-OP_CASES = [(2, 1, (5, 3)), (2, 3, (5, 4)), (2, 5, (4, 3)), (2, 8, (3, 4)), (2, 9, (3, 2)), (3, 1, (4, 3, 5)),
+OP_CASES = [(2, 1, (5, 3)), (2, 3, (5, 4)), (2, 5, (4, 3)), (2, 8, (3, 4)), (2, 9, (3, 2)), (2, 12, (3, 2)),
+            (2, 15, (2, 3)), (3, 1, (4, 3, 5)),
             (3, 2, (3, 4, 3)), (3, 4, (4, 3, 5)), (3, 5, (3, 4, 2)), (3, 6, (2, 3, 3)), (3, 7, (3, 2, 3)),
             (3, 8, (2, 3, 2)), (3, 9, (2, 2, 3))]
 
@@ -78,7 +79,8 @@ def test_setup_1d_eigs(kind, d, k, ms):
 SMOOTH_CASES = [("cell", 2, 3, (5, 4)), ("cell", 3, 4, (3, 4, 3)), ("cell", 3, 5, (3, 2, 3)),
                 ("cell", 3, 8, (2, 3, 2)), ("cell", 3, 9, (2, 2, 1)),
                 ("vertex", 2, 3, (5, 4)), ("vertex", 2, 5, (4, 3)), ("vertex", 2, 8, (3, 4)),
-                ("vertex", 2, 9, (3, 3)), ("vertex", 3, 1, (5, 4, 3)),
+                ("vertex", 2, 9, (3, 3)), ("cell", 2, 11, (3, 2)), ("cell", 2, 15, (2, 3)),
+                ("vertex", 2, 13, (3, 3)), ("vertex", 2, 15, (3, 2)), ("vertex", 3, 1, (5, 4, 3)),
                 ("vertex", 3, 2, (4, 3, 5)), ("vertex", 3, 4, (3, 4, 3)), ("vertex", 3, 5, (3, 4, 3)),
                 ("vertex", 3, 6, (3, 3, 2)), ("vertex", 3, 7, (3, 4, 3)),  # k = 7: FP64 MFMA local solves
                 ("vertex", 3, 8, (3, 2, 3))]
@@ -271,7 +273,8 @@ def test_vertex_patches_need_two_cells_per_axis(d, k, ms):
     assert rel(host(xg), ref) < 1e-12
 
 
-@pytest.mark.parametrize("d,k,ms", [(2, 3, (3, 2)), (3, 2, (2, 3, 2)), (3, 4, (1, 2, 2)), (3, 9, (1, 1, 2))])
+@pytest.mark.parametrize("d,k,ms", [(2, 3, (3, 2)), (3, 2, (2, 3, 2)), (3, 4, (1, 2, 2)), (3, 9, (1, 1, 2)),
+                                    (2, 11, (2, 3)), (2, 15, (2, 2))])
 def test_transfers(d, k, ms):
     announce("transfer", d, k, ms)
     mc = omesh(d, k, ms, 15)
@@ -292,7 +295,8 @@ def test_transfers(d, k, ms):
 @pytest.mark.parametrize("kind,d,k,ms,nl", [("vertex", 3, 2, (8, 4, 4), 3), ("cell", 2, 3, (8, 8), 3),
                                             ("vertex", 2, 4, (8, 4), 3), ("vertex", 3, 4, (4, 4, 4), 2),
                                             ("vertex", 3, 5, (4, 4, 4), 2), ("cell", 3, 5, (4, 4, 2), 2),
-                                            ("vertex", 2, 8, (8, 4), 3), ("vertex", 3, 8, (4, 2, 2), 2)])
+                                            ("vertex", 2, 8, (8, 4), 3), ("vertex", 3, 8, (4, 2, 2), 2),
+                                            ("vertex", 2, 15, (4, 4), 2), ("cell", 2, 13, (4, 4), 3)])
 def test_vcycle(kind, d, k, ms, nl):
     announce("vcycle", kind, d, k, ms, nl)
     from oracle.mesh import refine
