@@ -405,7 +405,7 @@ fts_status fts_batch_autotune(fts_batch *batch, fts_prec prec, const double *r, 
  * during the call only.  Cells and DoFs are numbered as on Cartesian meshes. */
 typedef struct fts_mapped_desc {
     int32_t dim;            /* 2 or 3 */
-    int32_t degree;         /* k, 1..7 */
+    int32_t degree;         /* k: 1..7 in 3-D, 1..15 in 2-D */
     int32_t ncells[3];      /* cells per axis */
     const double *vertices; /* host, prod(ncells + 1) x dim */
     double penalty_factor;  /* gamma_hat > 0 */

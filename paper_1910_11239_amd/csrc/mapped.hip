@@ -521,13 +521,16 @@ static fts_status launch_mapped_sur(const fts_mapped_level *lv, double omega, in
     return e == hipSuccess ? FTS_OK : hip_fail(e, "k_mapped_surrogate launch");
 }
 
-constexpr int kMapMaxN1 = 8;  // k <= 7
+// Largest N1 = k + 1 on mapped cells: k <= 7 in 3-D (the cell's work arrays
+// stay in LDS at several workgroups per CU), k <= 15 in 2-D.
+template <int D>
+constexpr int map_max_n1() { return D == 2 ? 16 : 8; }
 
 template <int D, int N1 = 2>
 static fts_status dispatch_mapped(const fts_mapped_level *lv, int what, double omega, int color, const double *x,
                                   const double *b, double *y, hipStream_t st) {
-    if constexpr (N1 > kMapMaxN1) {
-        return fail(FTS_E_UNSUPPORTED, "mapped meshes: degree above 7");
+    if constexpr (N1 > map_max_n1<D>()) {
+        return fail(FTS_E_UNSUPPORTED, "mapped meshes: degree above 7 in 3-D or 15 in 2-D");
     } else {
         if (lv->n1 != N1) return dispatch_mapped<D, N1 + 1>(lv, what, omega, color, x, b, y, st);
         if (what == 2) return launch_mapped_sur<D, N1>(lv, omega, color, x, y, st);
@@ -590,8 +593,8 @@ fts_status fts_mapped_level_create(const fts_mapped_desc *desc, fts_mapped_level
     *out = nullptr;
     const int d = desc->dim;
     if (d != 2 && d != 3) return fail(FTS_E_UNSUPPORTED, "mapped meshes: dim must be 2 or 3");
-    if (desc->degree < 1 || desc->degree > kMapMaxN1 - 1)
-        return fail(FTS_E_UNSUPPORTED, "mapped meshes: degree must be in 1..7");
+    if (desc->degree < 1 || desc->degree > (d == 2 ? map_max_n1<2>() : map_max_n1<3>()) - 1)
+        return fail(FTS_E_UNSUPPORTED, "mapped meshes: degree must be in 1..7 (3-D) or 1..15 (2-D)");
     if (!(desc->penalty_factor > 0.0) || !std::isfinite(desc->penalty_factor))
         return fail(FTS_E_INVAL, "penalty_factor must be positive");
     auto *lv = new fts_mapped_level();

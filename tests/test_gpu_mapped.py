@@ -20,6 +20,7 @@ import paper_1910_11239_amd as fts  # noqa: E402
 TOL = 1e-12
 
 CASES = [("distorted", 2, 1, 3, 1), ("distorted", 2, 3, 3, 1), ("distorted", 2, 5, 2, 1), ("distorted", 2, 7, 2, 1),
+         ("distorted", 2, 11, 2, 1), ("distorted", 2, 15, 2, 1),
          ("distorted", 3, 1, 2, 1), ("distorted", 3, 2, 2, 1), ("distorted", 3, 3, 2, 1), ("distorted", 3, 5, 1, 1),
          ("distorted", 2, 3, 8, 2), ("distorted", 3, 3, 4, 1),
          ("rect", 2, 4, (5, 3), 0), ("rect", 3, 3, (3, 4, 2), 0)]
