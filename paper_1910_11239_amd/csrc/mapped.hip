@@ -451,6 +451,14 @@ k_mapped_operator(MappedView g, const double *__restrict__ x, const double *__re
     }
 }
 
+// Red-black color of cell c (x fastest, m0 x m1 cells per layer): the parity
+// of its index sum.  Face neighbours have opposite colors.
+__device__ __forceinline__ int cell_parity(int dim, int m0, int m1, int64_t c) {
+    const int64_t c1 = c / m0;
+    const int64_t sum = c % m0 + (dim == 3 ? c1 % m1 + c1 / m1 : c1);
+    return (int)(sum & 1);
+}
+
 // x += omega sum_K R_K^T Atilde_K^-1 R_K r with the surrogate tables of each
 // cell: (S_d x .. x S_1) diag(1 / sum_t lambda_t) (S_d x .. x S_1)^T.
 // color >= 0: only the cells whose index sum has that parity (the red-black
@@ -462,11 +470,8 @@ k_mapped_surrogate(MappedView g, double omega, int color, const double *__restri
     __shared__ double A[NC], B[NC];
     __shared__ double S[D][N1 * N1], L[D][N1];
     const int64_t cell = blockIdx.x;
-    if (color >= 0) {  // uniform over the workgroup: it leaves before any barrier
-        const int64_t c1 = cell / g.m[0];
-        const int64_t par = cell % g.m[0] + (D == 3 ? c1 % g.m[1] + c1 / g.m[1] : c1);
-        if ((int)(par & 1) != color) return;
-    }
+    // uniform over the workgroup: it leaves before any barrier
+    if (color >= 0 && cell_parity(D, g.m[0], g.m[1], cell) != color) return;
     const int t = threadIdx.x;
     for (int e2 = t; e2 < D * N1 * N1; e2 += blockDim.x) S[e2 / (N1 * N1)][e2 % (N1 * N1)] = g.S[cell * D * N1 * N1 + e2];
     for (int e2 = t; e2 < D * N1; e2 += blockDim.x) L[e2 / N1][e2 % N1] = g.lam[cell * D * N1 + e2];
@@ -927,11 +932,6 @@ namespace fts {
 // of the mapped operator, probed with the red-black coloring (a cell's face
 // neighbours all have the other color, so (A e)|_K = A_KK e_K when e is zero
 // on every cell of the other color) and inverted in LDS.
-__device__ __forceinline__ int cell_parity(int dim, int m0, int m1, int64_t c) {
-    const int64_t c1 = c / m0;
-    const int64_t sum = c % m0 + (dim == 3 ? c1 % m1 + c1 / m1 : c1);
-    return (int)(sum & 1);
-}
 
 // e[(c, i)] = 1 on the cells c of `color`, 0 elsewhere.
 __global__ void k_cell_probe_set(int dim, int m0, int m1, int64_t ncells, int nc, int color, int i,
